@@ -1,0 +1,206 @@
+/*
+ * deflan.h -- C ABI of libdeflan.so: deflated Hermitian Lanczos solvers for the
+ * Wilson-Dirac matrix on one MI355X (gfx950) GPU.
+ *
+ * Method: A. M. Abdel-Rehim, R. B. Morgan, D. Nicely, W. Wilcox, "Deflated
+ * Hermitian Lanczos Methods for Multiple Right-Hand Sides" (arXiv:0901.3163).
+ * The abstract states the problem the two solve calls implement: solve a
+ * Hermitian system for the first right-hand side while computing eigenvectors
+ * of small eigenvalues (Lan-DR for the positive definite form, MinRes-DR for the
+ * indefinite form), then project over those eigenvectors for every additional
+ * right-hand side (D-CG, D-MinRes).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice:   dims = {Lx, Ly, Lz, Lt}, each >= 2, periodic in all directions;
+ *            site = x + Lx*(y + Ly*(z + Lz*t)), V = Lx*Ly*Lz*Lt sites.
+ * Spinor:    interleaved complex128, [V][4 spin][3 colour] (12 complex per site),
+ *            i.e. 24 doubles per site.  "N" below is 12*V complex numbers.
+ * Links:     interleaved complex128, [V][4 mu][3 row][3 col]; mu = 0..3 is x,y,z,t.
+ * Operator:  (M psi)(x) = psi(x) - kappa * sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                          + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *            with the chiral gamma basis, gamma5 = diag(1, 1, -1, -1) on spin.
+ *            (The paper names "the Wilson matrix" M without conventions, Section 2.)
+ * Memory:    DL_HOST    -- pointers are host memory; the library copies.
+ *            DL_DEVICE  -- pointers are device memory on the context's device, in
+ *                          the same interleaved host layout (e.g. a torch complex128
+ *                          tensor's data_ptr()); the library reads/writes them on
+ *                          the context's stream.
+ * Ownership: the caller owns every array it passes; handles returned through
+ *            an out-pointer belong to the caller and are freed by the matching
+ *            *_destroy call.  One context per host thread.
+ * Errors:    every int-returning call returns a DL_* status; on a negative
+ *            status nothing has been written through out-pointers and
+ *            dl_last_error() describes the failure (thread-local).  No C++
+ *            exception crosses this boundary.
+ */
+#ifndef DEFLAN_H
+#define DEFLAN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DL_OK             0
+#define DL_NOT_CONVERGED  1   /* outputs are filled with the best iterate */
+#define DL_E_INVALID     -1   /* bad argument (null pointer, size, option) */
+#define DL_E_HIP         -2   /* HIP runtime error */
+#define DL_E_NOMEM       -3   /* device allocation failed */
+#define DL_E_BREAKDOWN   -4   /* Krylov breakdown that could not be resolved */
+#define DL_E_NONFINITE   -5   /* NaN / Inf in input or in a reduction */
+#define DL_E_MISMATCH    -6   /* eigenvector handle does not belong to this operator */
+
+/* ---- enumerations -------------------------------------------------------- */
+/* The Hermitian form the solvers iterate on (Section 2):
+ *   DL_MDAGM: M^dag M x = M^dag b -- Lan-DR (first rhs) and D-CG (later rhs);
+ *   DL_G5M:   gamma5 M x = gamma5 b -- MinRes-DR (first rhs) and D-MinRes.
+ * In both cases the user solves M x = b and the reported residual is
+ * ||b - M x|| / ||b||, the paper's "residual norm for convergence of M^-1". */
+#define DL_MDAGM 0
+#define DL_G5M   1
+
+#define DL_FP64 0
+#define DL_FP32 1
+#define DL_BF16 2
+
+#define DL_HOST   0
+#define DL_DEVICE 1
+
+/* which operator dl_apply applies */
+#define DL_APPLY_M     0
+#define DL_APPLY_MDAG  1
+#define DL_APPLY_G5M   2
+#define DL_APPLY_MDAGM 3
+
+/* stop rules reported in dl_stats.stop_rule for dl_solve_first */
+#define DL_STOP_LINEAR     0  /* k = 0: stopped at linear convergence */
+#define DL_STOP_EIGEN      1  /* every kept eigen-residual <= eig_tol * ||A||_est */
+#define DL_STOP_MVP_FACTOR 2  /* MVPs reached past_conv_factor x MVPs at linear convergence */
+#define DL_STOP_MAX_MVP    3  /* MVP cap reached (status DL_NOT_CONVERGED if not converged) */
+#define DL_STOP_BREAKDOWN  4  /* invariant subspace found: exact solve */
+
+typedef struct dl_ctx dl_ctx;
+typedef struct dl_op  dl_op;
+typedef struct dl_eig dl_eig;
+
+/* Options for the first right-hand side.  Pass NULL for the defaults. */
+typedef struct {
+  double eig_tol;           /* eigen-residual target relative to ||A||_est; default 1e-12 */
+  double past_conv_factor;  /* run past linear convergence up to this MVP factor; default 2.0
+                               (the paper: "at most a factor of two in MVPs", Section 2) */
+  long   max_mvp;           /* hard cap on MVPs; default 1000000 */
+} dl_first_opts;
+
+/* Options for later right-hand sides.  Pass NULL for the defaults. */
+typedef struct {
+  int    storage;           /* DL_FP64 (default): plain FP64 D-CG / D-MinRes.
+                               DL_FP32 / DL_BF16: low-precision Krylov storage and Dslash,
+                               FP32 arithmetic, FP64 reliable updates and FP64 true residual. */
+  int    reliable_every;    /* iterations between FP64 reliable updates (default 50) */
+  int    batched;           /* 0: one rhs after another; 1: all rhs advance together through
+                               the multi-rhs kernels (links read once per site for all rhs) */
+  int    x0_given;          /* 1: X holds initial guesses on entry (default 0: x0 = 0) */
+  long   max_mvp;           /* per-rhs MVP cap; default 1000000 */
+} dl_next_opts;
+
+/* Per-solve statistics. */
+typedef struct {
+  int    status;            /* DL_OK or DL_NOT_CONVERGED */
+  int    stop_rule;         /* DL_STOP_* (solve_first) */
+  int    cycles;            /* restart cycles (solve_first) */
+  int    reserved;
+  long   mvp;               /* applications of M or M^dag (M^dag M counts 2; gamma5 is free) */
+  long   mvp_lin;           /* MVPs when the linear system first met tol (solve_first) */
+  long   iters;             /* Krylov iterations */
+  double relres;            /* true ||b - M x|| / ||b||, recomputed in FP64 at return */
+  double time_s;            /* wall time of the call */
+} dl_stats;
+
+/* ---- library ----------------------------------------------------------- */
+/* Message describing the last non-OK status on this thread ("" if none). */
+const char* dl_last_error(void);
+/* ABI version (major*100 + minor). */
+int dl_version(void);
+
+/* ---- context ------------------------------------------------------------ */
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (NULL: the library creates its own stream). */
+int  dl_ctx_create(int device, void* hip_stream, dl_ctx** out);
+void dl_ctx_destroy(dl_ctx* ctx);
+/* Block until all work queued by the library on the context's stream is done. */
+int  dl_ctx_sync(dl_ctx* ctx);
+/* Kernel timing: when enabled, every launch of the kernel families below is
+ * bracketed by HIP events on the context's stream and its duration summed.
+ * name: "wilson" (every M / M^dag / gamma5 M launch in the precision used),
+ * "tsk_dots" (V^H w), "tsk_update" (V c / V Y), "small" (one-workgroup FP64
+ * problems).  dl_kernel_time returns launches and total milliseconds since the
+ * last reset (enable != 0 resets). */
+int  dl_timing(dl_ctx* ctx, int enable);
+int  dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_ms);
+
+/* ---- operator ----------------------------------------------------------- */
+/* Create the operator A of the paper for links U, hopping parameter kappa and
+ * Hermitian form `kind` (DL_MDAGM or DL_G5M).  The links are converted once to
+ * the device's site-major tiled layout (FP64, plus FP32/BF16 copies on first
+ * use).  Errors: DL_E_INVALID for dims < 2, kappa not finite, unknown kind. */
+int  dl_op_create(dl_ctx* ctx, const int dims[4], const double* links, int mem,
+                  double kappa, int kind, dl_op** out);
+void dl_op_destroy(dl_op* op);
+/* Number of complex entries N = 12 V of one spinor. */
+long dl_op_size(const dl_op* op);
+
+/* out = op(in) with op one of DL_APPLY_* (FP64).  in/out are N complex each
+ * and may not alias. */
+int  dl_apply(dl_op* op, int which, const double* in, double* out, int mem);
+
+/* ---- first right-hand side: Lan-DR(m,k) / MinRes-DR(m,k) --------------- */
+/* Solves M x = b through the op's Hermitian form with Lan-DR(m,k) (DL_MDAGM)
+ * or MinRes-DR(m,k) (DL_G5M) from x0 = 0, keeping k eigenvectors of smallest
+ * eigenvalue (regular Ritz for Lan-DR, harmonic Ritz for MinRes-DR,
+ * Section 2), and runs past linear convergence to refine them (Section 2,
+ * last paragraph).  On return x holds the solution, *eig_out (if eig_out is
+ * not NULL and k > 0) the k eigenpairs, and *stats the counters.
+ * Requires 0 <= k < m <= N and tol > 0.  b = 0 gives x = 0 and DL_OK. */
+int  dl_solve_first(dl_op* op, const double* b, double* x, int mem, int m, int k,
+                    double tol, const dl_first_opts* opts, dl_eig** eig_out,
+                    dl_stats* stats);
+
+/* ---- later right-hand sides: D-CG / D-MinRes ----------------------------- */
+/* Solves M X[i] = B[i] for i < nrhs (B, X: [nrhs][V][4][3] complex128) by a
+ * Galerkin projection over the eigenvectors of `eig` at the beginning
+ * (Section 2), then CG on the normal equations (DL_MDAGM) or MinRes on
+ * gamma5 M (DL_G5M) until ||b - M x||/||b|| <= tol.  eig may be NULL (no
+ * deflation: plain CG / MinRes).  stats, if not NULL, has nrhs entries.
+ * nrhs = 0 is a no-op.  DL_E_MISMATCH if eig was built for another operator. */
+int  dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B,
+                   double* X, int mem, double tol, const dl_next_opts* opts,
+                   dl_stats* stats);
+
+/* ---- eigenvector handle ---------------------------------------------------- */
+/* Build a handle from k caller-supplied orthonormal vectors V ([k][V][4][3]);
+ * H = V^H A V is formed with k MVPs in FP64. */
+int  dl_eig_create(dl_op* op, int k, const double* V, int mem, dl_eig** out);
+/* k, the eigenvalues (Rayleigh quotients of A) and eigen-residual norms. */
+int  dl_eig_info(const dl_eig* eig, int* k, double* evals, double* resid);
+/* Copy the k eigenvectors out ([k][V][4][3] complex128). */
+int  dl_eig_vectors(const dl_eig* eig, double* V, int mem);
+void dl_eig_destroy(dl_eig* eig);
+
+/* ---- kernel-level entry points (used by the parity tests) --------------- */
+/* c = V^H w for nv vectors V ([nv][N]) and one vector w ([N]); c: nv complex.
+ * Then, if `subtract`, w <- w - V c in place.  All pointers DL_HOST or DL_DEVICE. */
+int  dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w,
+                    double* c, int subtract, int mem);
+/* Y = V G for V ([nv][n] complex) and real G ([nv][ny], row-major); Y: [ny][n]. */
+int  dl_tsk_combine(dl_ctx* ctx, long n, int nv, const double* V, const double* G,
+                    int ny, double* Y, int mem);
+/* Eigen-decomposition of a real symmetric n x n matrix A (row-major, host) by
+ * the device's one-workgroup Jacobi solver: evals ascending, Z[i][j] = j-th
+ * eigenvector's i-th entry. n <= 512. */
+int  dl_small_eigh(dl_ctx* ctx, int n, const double* A, double* evals, double* Z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEFLAN_H */

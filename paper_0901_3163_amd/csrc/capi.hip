@@ -1,0 +1,461 @@
+// extern "C" boundary of libdeflan (declared in include/deflan.h).
+//
+// Every entry point validates its arguments, converts between the caller's
+// interleaved complex128 layout and the device's tiled site-major layout, runs
+// the solver on the context's stream and maps C++ errors to DL_* status codes.
+#include "engine.hpp"
+#include "small.hpp"
+#include "tsk.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+namespace dl {
+const std::string& last_error();
+}
+
+using namespace dl;
+
+namespace {
+
+template <class F>
+int guard(F&& f) {
+  try {
+    set_error("");
+    return f();
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DL_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return DL_E_INVALID;
+  }
+}
+
+void need(bool ok, const char* msg) {
+  if (!ok) fail(DL_E_INVALID, msg);
+}
+
+void use_device(dl_ctx* ctx) { DL_HIP(hipSetDevice(ctx->device)); }
+
+// nfield fields in the caller's layout -> tiled device buffer (pads zeroed).
+DBuf<double2> fields_in(dl_op* op, const double* p, int nfield, int mem) {
+  const Lattice& lat = op->lat;
+  hipStream_t s = op->ctx->stream;
+  DBuf<double2> t((size_t)nfield * lat.nc);
+  zero(s, (long)nfield * lat.nc, t.get());
+  const size_t bytes = (size_t)nfield * lat.V * kSpin * sizeof(double2);
+  if (mem == DL_DEVICE) {
+    pack_spinor(s, lat, reinterpret_cast<const double2*>(p), t.get(), nfield);
+  } else {
+    DBuf<double2> stage((size_t)nfield * lat.V * kSpin);
+    DL_HIP(hipMemcpyAsync(stage.get(), p, bytes, hipMemcpyHostToDevice, s));
+    pack_spinor(s, lat, stage.get(), t.get(), nfield);
+    DL_HIP(hipStreamSynchronize(s));
+  }
+  return t;
+}
+
+void fields_out(dl_op* op, const double2* t, double* p, int nfield, int mem) {
+  const Lattice& lat = op->lat;
+  hipStream_t s = op->ctx->stream;
+  const size_t bytes = (size_t)nfield * lat.V * kSpin * sizeof(double2);
+  if (mem == DL_DEVICE) {
+    unpack_spinor(s, lat, t, reinterpret_cast<double2*>(p), nfield);
+  } else {
+    DBuf<double2> stage((size_t)nfield * lat.V * kSpin);
+    unpack_spinor(s, lat, t, stage.get(), nfield);
+    DL_HIP(hipMemcpyAsync(p, stage.get(), bytes, hipMemcpyDeviceToHost, s));
+  }
+  DL_HIP(hipStreamSynchronize(s));
+}
+
+uint64_t fnv(uint64_t h, const void* data, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+dl_first_opts first_defaults(const dl_first_opts* o) {
+  dl_first_opts d{};
+  d.eig_tol = 1e-12;
+  d.past_conv_factor = 2.0;
+  d.max_mvp = 1000000;
+  if (o) {
+    if (o->eig_tol > 0) d.eig_tol = o->eig_tol;
+    if (o->past_conv_factor > 0) d.past_conv_factor = o->past_conv_factor;
+    if (o->max_mvp > 0) d.max_mvp = o->max_mvp;
+  }
+  return d;
+}
+
+dl_next_opts next_defaults(const dl_next_opts* o) {
+  dl_next_opts d{};
+  d.storage = DL_FP64;
+  d.reliable_every = 50;
+  d.batched = 0;
+  d.x0_given = 0;
+  d.max_mvp = 1000000;
+  if (o) {
+    d.storage = o->storage;
+    if (o->reliable_every > 0) d.reliable_every = o->reliable_every;
+    d.batched = o->batched;
+    d.x0_given = o->x0_given;
+    if (o->max_mvp > 0) d.max_mvp = o->max_mvp;
+  }
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dl_last_error(void) { return dl::last_error().c_str(); }
+
+int dl_version(void) { return 100; }
+
+int dl_ctx_create(int device, void* hip_stream, dl_ctx** out) {
+  return guard([&] {
+    need(out != nullptr, "out is NULL");
+    int ndev = 0;
+    DL_HIP(hipGetDeviceCount(&ndev));
+    need(device >= 0 && device < ndev, "device index out of range");
+    auto* c = new dl_ctx();
+    try {
+      c->device = device;
+      DL_HIP(hipSetDevice(device));
+      if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+      } else {
+        DL_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+      }
+      void* pin = nullptr;
+      DL_HIP(hipHostMalloc(&pin, 4096 * sizeof(double), hipHostMallocDefault));
+      c->pinned = static_cast<double*>(pin);
+    } catch (...) {
+      if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+      delete c;
+      throw;
+    }
+    *out = c;
+    return DL_OK;
+  });
+}
+
+void dl_ctx_destroy(dl_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->timers.collect();
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+int dl_ctx_sync(dl_ctx* ctx) {
+  return guard([&] {
+    need(ctx != nullptr, "ctx is NULL");
+    use_device(ctx);
+    DL_HIP(hipStreamSynchronize(ctx->stream));
+    return DL_OK;
+  });
+}
+
+int dl_timing(dl_ctx* ctx, int enable) {
+  return guard([&] {
+    need(ctx != nullptr, "ctx is NULL");
+    use_device(ctx);
+    ctx->timers.reset();
+    ctx->timers.enabled = enable != 0;
+    return DL_OK;
+  });
+}
+
+int dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_ms) {
+  return guard([&] {
+    need(ctx && name && launches && total_ms, "NULL argument");
+    use_device(ctx);
+    int id = -1;
+    if (!std::strcmp(name, "wilson")) id = T_WILSON;
+    else if (!std::strcmp(name, "tsk_dots")) id = T_TSK_DOTS;
+    else if (!std::strcmp(name, "tsk_update")) id = T_TSK_UPDATE;
+    else if (!std::strcmp(name, "small")) id = T_SMALL;
+    need(id >= 0, "unknown kernel family");
+    ctx->timers.collect();
+    *launches = ctx->timers.launches[id];
+    *total_ms = ctx->timers.ms[id];
+    return DL_OK;
+  });
+}
+
+int dl_op_create(dl_ctx* ctx, const int dims[4], const double* links, int mem, double kappa, int kind, dl_op** out) {
+  return guard([&] {
+    need(ctx && dims && links && out, "NULL argument");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    need(kind == DL_MDAGM || kind == DL_G5M, "kind must be DL_MDAGM or DL_G5M");
+    need(std::isfinite(kappa), "kappa must be finite");
+    use_device(ctx);
+    auto* op = new dl_op();
+    try {
+      op->ctx = ctx;
+      op->lat = make_lattice(dims);
+      op->kappa = kappa;
+      op->kind = kind;
+      const Lattice& lat = op->lat;
+      hipStream_t s = ctx->stream;
+      op->U.alloc(lat.nl);
+      zero(s, lat.nl, op->U.get());
+      const size_t bytes = (size_t)lat.V * kLinkC * sizeof(double2);
+      std::vector<double> sample;
+      if (mem == DL_DEVICE) {
+        pack_links(s, lat, reinterpret_cast<const double2*>(links), op->U.get());
+        sample.resize(std::min<size_t>(4096, (size_t)lat.V * kLinkC * 2));
+        DL_HIP(hipMemcpyAsync(sample.data(), links, sample.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      } else {
+        DBuf<double2> stage((size_t)lat.V * kLinkC);
+        DL_HIP(hipMemcpyAsync(stage.get(), links, bytes, hipMemcpyHostToDevice, s));
+        pack_links(s, lat, stage.get(), op->U.get());
+        DL_HIP(hipStreamSynchronize(s));
+        const size_t nd = (size_t)lat.V * kLinkC * 2;
+        for (size_t i = 0; i < nd; i += std::max<size_t>(1, nd / 4096)) sample.push_back(links[i]);
+      }
+      DL_HIP(hipStreamSynchronize(s));
+      uint64_t h = 1469598103934665603ull;
+      h = fnv(h, dims, 4 * sizeof(int));
+      h = fnv(h, &kappa, sizeof(double));
+      h = fnv(h, &kind, sizeof(int));
+      h = fnv(h, sample.data(), sample.size() * sizeof(double));
+      op->fingerprint = h;
+    } catch (...) {
+      delete op;
+      throw;
+    }
+    *out = op;
+    return DL_OK;
+  });
+}
+
+void dl_op_destroy(dl_op* op) {
+  if (!op) return;
+  (void)hipSetDevice(op->ctx->device);
+  (void)hipStreamSynchronize(op->ctx->stream);
+  delete op;
+}
+
+long dl_op_size(const dl_op* op) { return op ? 12 * op->lat.V : 0; }
+
+int dl_apply(dl_op* op, int which, const double* in, double* out, int mem) {
+  return guard([&] {
+    need(op && in && out, "NULL argument");
+    need(which >= 0 && which <= 3, "which must be one of DL_APPLY_*");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    need(in != out, "in and out may not alias");
+    use_device(op->ctx);
+    DBuf<double2> t = fields_in(op, in, 1, mem);
+    DBuf<double2> r(op->lat.nc), tmp(op->lat.nc);
+    zero(op->ctx->stream, op->lat.nc, r.get());
+    zero(op->ctx->stream, op->lat.nc, tmp.get());
+    if (which == DL_APPLY_MDAGM) {
+      apply_wilson(op, 0, t.get(), tmp.get());
+      apply_wilson(op, 1, tmp.get(), r.get());
+    } else {
+      apply_wilson(op, which, t.get(), r.get());
+    }
+    fields_out(op, r.get(), out, 1, mem);
+    return DL_OK;
+  });
+}
+
+int dl_solve_first(dl_op* op, const double* b, double* x, int mem, int m, int k, double tol,
+                   const dl_first_opts* opts, dl_eig** eig_out, dl_stats* stats) {
+  return guard([&] {
+    need(op && b && x, "NULL argument");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    need(k >= 0 && m > k, "need 0 <= k < m");
+    need((long)m <= 12 * op->lat.V, "m exceeds the vector length");
+    need(m <= 510, "m must be <= 510");
+    need(tol > 0 && std::isfinite(tol), "tol must be positive");
+    use_device(op->ctx);
+    const dl_first_opts o = first_defaults(opts);
+    DBuf<double2> bt = fields_in(op, b, 1, mem);
+    DBuf<double2> xt(op->lat.nc);
+    zero(op->ctx->stream, op->lat.nc, xt.get());
+    dl_eig* e = nullptr;
+    const int rc = solve_first(op, bt.get(), xt.get(), m, k, tol, o, eig_out ? &e : nullptr, stats);
+    fields_out(op, xt.get(), x, 1, mem);
+    if (eig_out) *eig_out = e;
+    return rc;
+  });
+}
+
+int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, double* X, int mem, double tol,
+                  const dl_next_opts* opts, dl_stats* stats) {
+  return guard([&] {
+    need(op != nullptr, "op is NULL");
+    need(nrhs >= 0, "nrhs must be >= 0");
+    if (nrhs == 0) return DL_OK;
+    need(B && X, "NULL argument");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    need(tol > 0 && std::isfinite(tol), "tol must be positive");
+    const dl_next_opts o = next_defaults(opts);
+    need(o.storage == DL_FP64, "only DL_FP64 storage is available in this build");
+    need(o.batched == 0, "batched execution is not available in this build");
+    use_device(op->ctx);
+    if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
+      fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
+    DBuf<double2> bt = fields_in(op, B, nrhs, mem);
+    DBuf<double2> xt = o.x0_given ? fields_in(op, X, nrhs, mem) : DBuf<double2>((size_t)nrhs * op->lat.nc);
+    if (!o.x0_given) zero(op->ctx->stream, (long)nrhs * op->lat.nc, xt.get());
+    const int rc = solve_next(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats);
+    fields_out(op, xt.get(), X, nrhs, mem);
+    return rc;
+  });
+}
+
+int dl_eig_create(dl_op* op, int k, const double* V, int mem, dl_eig** out) {
+  return guard([&] {
+    need(op && out, "NULL argument");
+    need(k >= 0 && k <= 512, "k must be in [0, 512]");
+    need(k == 0 || V != nullptr, "V is NULL");
+    use_device(op->ctx);
+    DBuf<double2> Y = k ? fields_in(op, V, k, mem) : DBuf<double2>();
+    *out = eig_build(op, k, std::move(Y), nullptr);
+    return DL_OK;
+  });
+}
+
+int dl_eig_info(const dl_eig* eig, int* k, double* evals, double* resid) {
+  return guard([&] {
+    need(eig != nullptr, "eig is NULL");
+    if (k) *k = eig->k;
+    if (evals) std::memcpy(evals, eig->evals.data(), eig->k * sizeof(double));
+    if (resid) std::memcpy(resid, eig->resid.data(), eig->k * sizeof(double));
+    return DL_OK;
+  });
+}
+
+int dl_eig_vectors(const dl_eig* eig, double* V, int mem) {
+  return guard([&] {
+    need(eig && V, "NULL argument");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    if (eig->k == 0) return DL_OK;
+    use_device(eig->ctx);
+    hipStream_t s = eig->ctx->stream;
+    const Lattice& lat = eig->lat;
+    const size_t bytes = (size_t)eig->k * lat.V * kSpin * sizeof(double2);
+    if (mem == DL_DEVICE) {
+      unpack_spinor(s, lat, eig->Y.get(), reinterpret_cast<double2*>(V), eig->k);
+    } else {
+      DBuf<double2> stage((size_t)eig->k * lat.V * kSpin);
+      unpack_spinor(s, lat, eig->Y.get(), stage.get(), eig->k);
+      DL_HIP(hipMemcpyAsync(V, stage.get(), bytes, hipMemcpyDeviceToHost, s));
+      DL_HIP(hipStreamSynchronize(s));
+    }
+    DL_HIP(hipStreamSynchronize(s));
+    return DL_OK;
+  });
+}
+
+void dl_eig_destroy(dl_eig* eig) { delete eig; }
+
+int dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w, double* c, int subtract, int mem) {
+  return guard([&] {
+    need(ctx && V && w && c, "NULL argument");
+    need(n > 0 && nv > 0 && nv <= 512, "need n > 0 and 0 < nv <= 512");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    use_device(ctx);
+    hipStream_t s = ctx->stream;
+    DBuf<double2> Vd, wd, cd(nv);
+    const double2 *vp = reinterpret_cast<const double2*>(V);
+    double2* wp = reinterpret_cast<double2*>(w);
+    double2* cp = reinterpret_cast<double2*>(c);
+    if (mem == DL_HOST) {
+      Vd.alloc((size_t)nv * n);
+      wd.alloc(n);
+      DL_HIP(hipMemcpyAsync(Vd.get(), V, (size_t)nv * n * sizeof(double2), hipMemcpyHostToDevice, s));
+      DL_HIP(hipMemcpyAsync(wd.get(), w, (size_t)n * sizeof(double2), hipMemcpyHostToDevice, s));
+      vp = Vd.get();
+      wp = wd.get();
+      cp = cd.get();
+    }
+    DBuf<double> part((size_t)2 * nv * tsk_nblocks(n));
+    int nb;
+    {
+      TimeScope ts(ctx, T_TSK_DOTS);
+      nb = tsk_dots(s, n, nv, vp, n, nullptr, wp, part.get());
+    }
+    sum_partials(s, part.get(), nb, 2 * nv, reinterpret_cast<double*>(cp));
+    if (subtract) {
+      TimeScope ts(ctx, T_TSK_UPDATE);
+      tsk_update(s, n, nv, vp, n, nullptr, cp, -1.0, wp);
+    }
+    if (mem == DL_HOST) {
+      DL_HIP(hipMemcpyAsync(c, cp, (size_t)nv * sizeof(double2), hipMemcpyDeviceToHost, s));
+      if (subtract) DL_HIP(hipMemcpyAsync(w, wp, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, s));
+    }
+    DL_HIP(hipStreamSynchronize(s));
+    return DL_OK;
+  });
+}
+
+int dl_tsk_combine(dl_ctx* ctx, long n, int nv, const double* V, const double* G, int ny, double* Y, int mem) {
+  return guard([&] {
+    need(ctx && V && G && Y, "NULL argument");
+    need(n > 0 && nv > 0 && nv <= 512 && ny > 0, "need n > 0, 0 < nv <= 512, ny > 0");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    use_device(ctx);
+    hipStream_t s = ctx->stream;
+    DBuf<double2> Vd, Yd;
+    DBuf<double> Gd((size_t)nv * ny);
+    const double2* vp = reinterpret_cast<const double2*>(V);
+    double2* yp = reinterpret_cast<double2*>(Y);
+    if (mem == DL_HOST) {
+      Vd.alloc((size_t)nv * n);
+      Yd.alloc((size_t)ny * n);
+      DL_HIP(hipMemcpyAsync(Vd.get(), V, (size_t)nv * n * sizeof(double2), hipMemcpyHostToDevice, s));
+      vp = Vd.get();
+      yp = Yd.get();
+      DL_HIP(hipMemcpyAsync(Gd.get(), G, (size_t)nv * ny * sizeof(double), hipMemcpyHostToDevice, s));
+    } else {
+      DL_HIP(hipMemcpyAsync(Gd.get(), G, (size_t)nv * ny * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    {
+      TimeScope ts(ctx, T_TSK_UPDATE);
+      tsk_combine(s, n, nv, vp, n, nullptr, Gd.get(), ny, ny, yp, n, nullptr, 0);
+    }
+    if (mem == DL_HOST)
+      DL_HIP(hipMemcpyAsync(Y, yp, (size_t)ny * n * sizeof(double2), hipMemcpyDeviceToHost, s));
+    DL_HIP(hipStreamSynchronize(s));
+    return DL_OK;
+  });
+}
+
+int dl_small_eigh(dl_ctx* ctx, int n, const double* A, double* evals, double* Z) {
+  return guard([&] {
+    need(ctx && A && evals && Z, "NULL argument");
+    need(n >= 1 && n <= 512, "n must be in [1, 512]");
+    use_device(ctx);
+    hipStream_t s = ctx->stream;
+    DBuf<double> Ad((size_t)n * n), Zd((size_t)n * n), ev(n), work(small_eigh_work(n));
+    DL_HIP(hipMemcpyAsync(Ad.get(), A, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+      TimeScope ts(ctx, T_SMALL);
+      small_eigh(s, n, Ad.get(), Zd.get(), ev.get(), work.get());
+    }
+    DL_HIP(hipMemcpyAsync(evals, ev.get(), n * sizeof(double), hipMemcpyDeviceToHost, s));
+    DL_HIP(hipMemcpyAsync(Z, Zd.get(), (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost, s));
+    DL_HIP(hipStreamSynchronize(s));
+    return DL_OK;
+  });
+}
+
+}  // extern "C"

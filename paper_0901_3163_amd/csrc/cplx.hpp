@@ -1,0 +1,69 @@
+// Complex arithmetic on double2 / float2 and wavefront reductions for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dl {
+
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i * a
+__device__ __forceinline__ double2 c_i(double2 a) { return make_double2(-a.y, a.x); }
+// a * b
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// acc + a * b
+__device__ __forceinline__ double2 c_fma(double2 a, double2 b, double2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc + conj(a) * b
+__device__ __forceinline__ double2 c_fmac(double2 a, double2 b, double2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+// acc + s * a (real s)
+__device__ __forceinline__ double2 c_axpy(double s, double2 a, double2 acc) {
+  return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a block of kBlock threads; result valid in thread 0.  Fixed order.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* lds /* NT/64 */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) r += lds[w];
+  }
+  __syncthreads();
+  return r;
+}
+
+// Map the hardware block index to a logical block so that each of the 8 XCDs
+// (blocks are dealt round-robin to XCDs) works on one contiguous range of the
+// lattice: neighbouring tiles then share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+}  // namespace dl

@@ -1,0 +1,51 @@
+// Operator, eigenvector-handle and solver declarations of libdeflan.
+#pragma once
+#include "internal.hpp"
+
+struct dl_op {
+  dl_ctx* ctx = nullptr;
+  dl::Lattice lat{};
+  double kappa = 0.0;
+  int kind = DL_MDAGM;
+  dl::DBuf<double2> U;          // FP64 links, tiled
+  uint64_t fingerprint = 0;     // dims, kappa, kind and a hash of the links
+};
+
+struct dl_eig {
+  dl_ctx* ctx = nullptr;
+  dl::Lattice lat{};
+  uint64_t fingerprint = 0;
+  int kind = 0;
+  int k = 0;
+  long nc = 0;
+  dl::DBuf<double2> Y;          // k tiled fields, contiguous (stride nc)
+  dl::DBuf<double> Zr, lamr;    // eigendecomposition of the real embedding of H = Y^H A Y
+  std::vector<double> evals;    // Rayleigh quotients y_i^H A y_i
+  std::vector<double> resid;    // ||A y_i - lambda_i y_i||
+};
+
+namespace dl {
+
+// Scratch owned by one solve: device scalars, reduction partials, small work.
+struct Scratch {
+  DBuf<double> sc;     // 256 device scalars
+  DBuf<double> part;   // reduction partials
+  size_t part_n = 0;
+  void ensure_part(size_t n) {
+    if (n > part_n) { part.alloc(n); part_n = n; }
+  }
+};
+
+// out = A in for the operator's Hermitian form (tmp: one field for M^dag M).
+// Returns MVPs used.
+int apply_A(dl_op* op, const double2* in, double2* out, double2* tmp);
+// out = M in (which: 0 M, 1 M^dag, 2 gamma5 M), timed as "wilson".
+void apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red = 0, double* part = nullptr);
+
+int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double tol, const dl_first_opts& o,
+                dl_eig** eig_out, dl_stats* st);
+int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
+               const dl_next_opts& o, dl_stats* st);
+dl_eig* eig_build(dl_op* op, int k, DBuf<double2>&& Y, long* mvp);
+
+}  // namespace dl

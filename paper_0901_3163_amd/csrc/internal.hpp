@@ -1,0 +1,148 @@
+// Internal declarations shared by the HIP translation units of libdeflan.
+//
+// Device layout of a lattice field (spinor or links) is site-major and tiled:
+// sites are grouped in tiles of 64 consecutive sites (one wavefront), and
+// inside a tile the complex components are outermost, so that component c of
+// the 64 sites of a tile is one contiguous 1 KiB run (FP64):
+//
+//     spinor:  elem(site, c) = ((site / 64) * 12 + c) * 64 + site % 64,  c = spin*3 + colour
+//     links:   elem(site, mu, a, b) = ((site / 64) * 36 + mu*9 + a*3 + b) * 64 + site % 64
+//
+// A wavefront reading one component of 64 consecutive sites issues one fully
+// coalesced 16-byte-per-lane load.  Padding sites of the last tile are zero and
+// stay zero under every kernel, so reductions over the padded length equal
+// reductions over the lattice.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/deflan.h"
+
+namespace dl {
+
+constexpr int kTile = 64;      // sites per tile (= wavefront size)
+constexpr int kSpin = 12;      // complex components per spinor site
+constexpr int kLinkC = 36;     // complex components per site of links (4 x 3 x 3)
+constexpr int kBlock = 256;    // threads per block of the streaming kernels
+constexpr int kMaxPartials = 16384;  // upper bound of blocks writing one reduction column
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+void set_error(const std::string& msg);
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define DL_HIP(x) ::dl::hip_check((x), #x, __FILE__, __LINE__)
+
+struct Lattice {
+  int L[4];        // Lx, Ly, Lz, Lt
+  long V;          // sites
+  long ntiles;     // ceil(V / 64)
+  long nc;         // complex elements of a padded spinor field = ntiles * 64 * 12
+  long nl;         // complex elements of padded links = ntiles * 64 * 36
+};
+
+Lattice make_lattice(const int dims[4]);
+
+// ---- device memory --------------------------------------------------------
+void* dmalloc(size_t bytes);
+void dfree(void* p);
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  explicit DBuf(size_t count) { alloc(count); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count) p = static_cast<T*>(dmalloc(count * sizeof(T)));
+    n = count;
+  }
+  void release() { if (p) dfree(p); p = nullptr; n = 0; }
+  T* get() const { return p; }
+};
+
+// ---- kernel timing --------------------------------------------------------
+enum TimerId { T_WILSON = 0, T_TSK_DOTS, T_TSK_UPDATE, T_SMALL, T_COUNT };
+
+struct Timers {
+  bool enabled = false;
+  struct Pair { hipEvent_t a, b; int id; };
+  std::vector<Pair> pending;
+  std::vector<hipEvent_t> pool;
+  long launches[T_COUNT] = {0};
+  double ms[T_COUNT] = {0};
+  hipEvent_t take();
+  void begin(hipStream_t s, int id, hipEvent_t* a);
+  void end(hipStream_t s, int id, hipEvent_t a);
+  void collect();  // sync pending events and accumulate
+  void reset();
+  ~Timers();
+};
+
+}  // namespace dl
+
+struct dl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  dl::Timers timers;
+  // scratch used by reductions: partial sums and a pinned host mirror
+  dl::DBuf<double> partials;   // kMaxPartials * 2 * 512 doubles
+  double* pinned = nullptr;    // 4096 doubles of pinned host memory
+};
+
+namespace dl {
+
+// RAII scope that brackets kernel launches with timing events when enabled.
+struct TimeScope {
+  dl_ctx* ctx;
+  int id;
+  hipEvent_t a = nullptr;
+  TimeScope(dl_ctx* c, int i) : ctx(c), id(i) {
+    if (ctx->timers.enabled) ctx->timers.begin(ctx->stream, id, &a);
+  }
+  ~TimeScope() {
+    if (ctx->timers.enabled && a) ctx->timers.end(ctx->stream, id, a);
+  }
+};
+
+// ---- launchers: layout ------------------------------------------------------
+void pack_spinor(hipStream_t s, const Lattice& lat, const double2* host_layout, double2* tiled, int nfield);
+void unpack_spinor(hipStream_t s, const Lattice& lat, const double2* tiled, double2* host_layout, int nfield);
+void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, double2* tiled);
+
+// ---- launchers: Wilson operator (FP64) -------------------------------------
+// which: 0 M, 1 M^dag, 2 gamma5 M.  red: 0 none, 1 ||out||^2 partials, 2 Re<in,out> partials.
+// Returns the number of partials written to `part` (0 if red == 0).
+int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,
+               const double2* in, double2* out, int red, double* part);
+void gamma5_f64(hipStream_t s, const Lattice& lat, const double2* in, double2* out);
+
+// ---- launchers: BLAS-1 ------------------------------------------------------
+int nblocks_for(long n);  // partial count used by the streaming reductions for length n
+// partial sums
+int dot_partials(hipStream_t s, long n, const double2* a, const double2* b, double* part);  // complex, 2 per block
+int norm2_partials(hipStream_t s, long n, const double2* a, double* part);                  // 1 per block
+// Partials are stored column-major: part[col * nparts + block].
+// out[col] = sum_i part[col * nparts + i] (fixed order); grid = width blocks
+void sum_partials(hipStream_t s, const double* part, int nparts, int width, double* out);
+
+void copy(hipStream_t s, long n, const double2* a, double2* b);
+void zero(hipStream_t s, long n, double2* a);
+
+}  // namespace dl

@@ -1,0 +1,313 @@
+"""Thin ctypes binding of libdeflan.so (include/deflan.h).
+
+Every function here only marshals arguments: it converts numpy arrays (host
+memory, ``DL_HOST``) or torch complex128 device tensors (``DL_DEVICE``) to
+pointers, calls the C entry point of the same name and turns a negative status
+into an exception.  All arithmetic runs in the library's HIP kernels; there is
+no fallback path.  If the shared library is missing, importing this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdeflan.so")
+
+DL_OK, DL_NOT_CONVERGED = 0, 1
+DL_E_INVALID, DL_E_HIP, DL_E_NOMEM, DL_E_BREAKDOWN, DL_E_NONFINITE, DL_E_MISMATCH = -1, -2, -3, -4, -5, -6
+DL_MDAGM, DL_G5M = 0, 1
+DL_FP64, DL_FP32, DL_BF16 = 0, 1, 2
+DL_HOST, DL_DEVICE = 0, 1
+DL_APPLY_M, DL_APPLY_MDAG, DL_APPLY_G5M, DL_APPLY_MDAGM = 0, 1, 2, 3
+STOP_RULES = {0: "linear", 1: "eigen", 2: "mvp_factor", 3: "max_mvp", 4: "breakdown", -1: "none"}
+
+
+class DeflanError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"deflan error {code}: {msg}")
+        self.code = code
+
+
+class dl_first_opts(C.Structure):
+    _fields_ = [("eig_tol", C.c_double), ("past_conv_factor", C.c_double), ("max_mvp", C.c_long)]
+
+
+class dl_next_opts(C.Structure):
+    _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
+                ("x0_given", C.c_int), ("max_mvp", C.c_long)]
+
+
+class dl_stats(C.Structure):
+    _fields_ = [("status", C.c_int), ("stop_rule", C.c_int), ("cycles", C.c_int), ("reserved", C.c_int),
+                ("mvp", C.c_long), ("mvp_lin", C.c_long), ("iters", C.c_long),
+                ("relres", C.c_double), ("time_s", C.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d["stop_rule"] = STOP_RULES.get(self.stop_rule, str(self.stop_rule))
+        return d
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0901_3163_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I, L, D = C.c_void_p, C.c_int, C.c_long, C.c_double
+    sig = {
+        "dl_last_error": (C.c_char_p, []),
+        "dl_version": (I, []),
+        "dl_ctx_create": (I, [I, P, C.POINTER(P)]),
+        "dl_ctx_destroy": (None, [P]),
+        "dl_ctx_sync": (I, [P]),
+        "dl_timing": (I, [P, I]),
+        "dl_kernel_time": (I, [P, C.c_char_p, C.POINTER(L), C.POINTER(D)]),
+        "dl_op_create": (I, [P, C.POINTER(I), P, I, D, I, C.POINTER(P)]),
+        "dl_op_destroy": (None, [P]),
+        "dl_op_size": (L, [P]),
+        "dl_apply": (I, [P, I, P, P, I]),
+        "dl_solve_first": (I, [P, P, P, I, I, I, D, C.POINTER(dl_first_opts), C.POINTER(P), C.POINTER(dl_stats)]),
+        "dl_solve_next": (I, [P, P, I, P, P, I, D, C.POINTER(dl_next_opts), C.POINTER(dl_stats)]),
+        "dl_eig_create": (I, [P, I, P, I, C.POINTER(P)]),
+        "dl_eig_info": (I, [P, C.POINTER(I), P, P]),
+        "dl_eig_vectors": (I, [P, P, I]),
+        "dl_eig_destroy": (None, [P]),
+        "dl_tsk_project": (I, [P, L, I, P, P, P, I, I]),
+        "dl_tsk_combine": (I, [P, L, I, P, P, I, P, I]),
+        "dl_small_eigh": (I, [P, I, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "dl_ctx_sync", "dl_timing",
+            "dl_kernel_time", "dl_op_create", "dl_op_destroy", "dl_op_size", "dl_apply", "dl_solve_first",
+            "dl_solve_next", "dl_eig_create", "dl_eig_info", "dl_eig_vectors", "dl_eig_destroy",
+            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh")
+
+
+def _check(rc):
+    if rc < 0:
+        raise DeflanError(rc, lib.dl_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    """(pointer, mem) of a numpy array (host) or a torch tensor (device if on GPU)."""
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data_as(C.c_void_p), DL_HOST
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(a.data_ptr()), (DL_DEVICE if a.is_cuda else DL_HOST)
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _c128(a):
+    if isinstance(a, np.ndarray):
+        return np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def _empty_like(a, shape=None):
+    shape = a.shape if shape is None else shape
+    if isinstance(a, np.ndarray):
+        return np.zeros(shape, dtype=np.complex128)
+    import torch
+    return torch.zeros(shape, dtype=torch.complex128, device=a.device)
+
+
+# ---------------------------------------------------------------------------
+class Context:
+    """dl_ctx: one HIP device and stream (hip_stream: an int handle or None)."""
+
+    def __init__(self, device: int = 0, hip_stream=None):
+        h = C.c_void_p()
+        _check(lib.dl_ctx_create(device, C.c_void_p(hip_stream) if hip_stream else None, C.byref(h)))
+        self.h = h
+
+    def sync(self):
+        _check(lib.dl_ctx_sync(self.h))
+
+    def timing(self, enable: bool = True):
+        _check(lib.dl_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, name: str):
+        n, ms = C.c_long(), C.c_double()
+        _check(lib.dl_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.dl_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Eig:
+    """dl_eig: eigenvectors kept from the first right-hand side."""
+
+    def __init__(self, h, op):
+        self.h = h
+        self.op = op
+
+    def info(self):
+        k = C.c_int()
+        _check(lib.dl_eig_info(self.h, C.byref(k), None, None))
+        ev = np.zeros(k.value)
+        rs = np.zeros(k.value)
+        _check(lib.dl_eig_info(self.h, C.byref(k), ev.ctypes.data_as(C.c_void_p), rs.ctypes.data_as(C.c_void_p)))
+        return ev, rs
+
+    @property
+    def k(self):
+        k = C.c_int()
+        _check(lib.dl_eig_info(self.h, C.byref(k), None, None))
+        return k.value
+
+    def vectors(self):
+        V = np.zeros((self.k, self.op.V, 4, 3), dtype=np.complex128)
+        if self.k:
+            p, mem = _ptr(V)
+            _check(lib.dl_eig_vectors(self.h, p, mem))
+        return V
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.dl_eig_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """dl_op: the Wilson matrix with links U, hopping parameter kappa, Hermitian form kind."""
+
+    def __init__(self, ctx: Context, dims, links, kappa: float, kind: int):
+        self.ctx = ctx
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        links = _c128(links)
+        p, mem = _ptr(links)
+        d = (C.c_int * 4)(*self.dims)
+        h = C.c_void_p()
+        _check(lib.dl_op_create(ctx.h, d, p, mem, float(kappa), int(kind), C.byref(h)))
+        self.h = h
+        self.kind = kind
+        self.kappa = kappa
+
+    def apply(self, which: int, psi):
+        psi = _c128(psi)
+        out = _empty_like(psi)
+        pi, mem = _ptr(psi)
+        po, _ = _ptr(out)
+        _check(lib.dl_apply(self.h, int(which), pi, po, mem))
+        return out
+
+    def solve_first(self, b, m: int, k: int, tol: float, eig_tol=None, past_conv_factor=None, max_mvp=None,
+                    want_eig=True):
+        b = _c128(b)
+        x = _empty_like(b)
+        o = dl_first_opts(eig_tol or 0.0, past_conv_factor or 0.0, int(max_mvp or 0))
+        st = dl_stats()
+        eh = C.c_void_p()
+        pb, mem = _ptr(b)
+        px, _ = _ptr(x)
+        rc = _check(lib.dl_solve_first(self.h, pb, px, mem, int(m), int(k), float(tol), C.byref(o),
+                                       C.byref(eh) if want_eig else None, C.byref(st)))
+        eig = Eig(eh, self) if want_eig else None
+        return x, eig, dict(st.as_dict(), rc=rc)
+
+    def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
+                   reliable_every=None):
+        B = _c128(B)
+        nrhs = B.shape[0]
+        X = _empty_like(B) if x0 is None else _c128(x0).copy()
+        o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
+                         int(max_mvp or 0))
+        st = (dl_stats * max(nrhs, 1))()
+        pB, mem = _ptr(B)
+        pX, _ = _ptr(X)
+        rc = _check(lib.dl_solve_next(self.h, eig.h if eig is not None else None, nrhs, pB, pX, mem, float(tol),
+                                      C.byref(o), st))
+        return X, [st[i].as_dict() for i in range(nrhs)], rc
+
+    def eig_create(self, Vecs):
+        Vecs = _c128(Vecs)
+        p, mem = _ptr(Vecs)
+        h = C.c_void_p()
+        _check(lib.dl_eig_create(self.h, int(Vecs.shape[0]), p, mem, C.byref(h)))
+        return Eig(h, self)
+
+    @property
+    def n(self):
+        return int(lib.dl_op_size(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.dl_op_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- kernel-level entry points ------------------------------------------------
+def dl_tsk_project(ctx: Context, V, w, subtract: bool = False):
+    """c = V^H w (and w <- w - V c if subtract); V: [nv][n] complex, w: [n]."""
+    V = _c128(V)
+    w = _c128(w).copy() if isinstance(w, np.ndarray) else w.clone()
+    c = _empty_like(w, (V.shape[0],))
+    pV, mem = _ptr(V)
+    pw, _ = _ptr(w)
+    pc, _ = _ptr(c)
+    _check(lib.dl_tsk_project(ctx.h, int(V.shape[1]), int(V.shape[0]), pV, pw, pc, 1 if subtract else 0, mem))
+    return c, w
+
+
+def dl_tsk_combine(ctx: Context, V, G):
+    """Y = V G for V [nv][n] complex and real G [nv][ny]; Y: [ny][n]."""
+    V = _c128(V)
+    if isinstance(G, np.ndarray):
+        G = np.ascontiguousarray(G, dtype=np.float64)
+    Y = _empty_like(V, (G.shape[1], V.shape[1]))
+    pV, mem = _ptr(V)
+    pG, _ = _ptr(G)
+    pY, _ = _ptr(Y)
+    _check(lib.dl_tsk_combine(ctx.h, int(V.shape[1]), int(V.shape[0]), pV, pG, int(G.shape[1]), pY, mem))
+    return Y
+
+
+def dl_small_eigh(ctx: Context, A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    ev = np.zeros(n)
+    Z = np.zeros((n, n))
+    _check(lib.dl_small_eigh(ctx.h, n, A.ctypes.data_as(C.c_void_p), ev.ctypes.data_as(C.c_void_p),
+                             Z.ctypes.data_as(C.c_void_p)))
+    return ev, Z
