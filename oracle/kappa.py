@@ -9,8 +9,13 @@ value of M) equals a target.  f(kappa) = min |lambda(gamma5 M(kappa))| is not
 monotone -- it dips at an avoided crossing and rises again -- so the search
 scans for the first dip and bisects on its lower side.
 
-Small lattices use the dense spectrum (exact).  ``python -m oracle.kappa``
-writes ``tests/golden/kappa.json``; it calls only oracle code.
+Small lattices use the dense spectrum (exact).  Large lattices use the
+smallest eigenvalue of M^dag M (= min |lambda(gamma5 M)|^2) from the plain
+Lanczos recurrence, whose smallest Ritz value decreases monotonically to
+lambda_min (Cauchy interlacing), with the C transcription of M, and a secant
+iteration in kappa on the lower side of the critical point.
+``python -m oracle.kappa [small|large]`` writes ``tests/golden/kappa.json``;
+it calls only oracle code.
 """
 from __future__ import annotations
 
@@ -97,13 +102,76 @@ def search_small(dims, target, seeds=range(10), eps=0.5, log=print):
     raise RuntimeError("no seed reaches the target")
 
 
+def lanczos_min_eig(apply, n, seed=0, rtol=1e-4, check=200, max_steps=40000):
+    """Smallest eigenvalue of a Hermitian positive definite operator (plain Lanczos, no re-orthogonalisation).
+
+    Returns (theta_min, steps).  Stops when the smallest Ritz value changed by
+    less than rtol (relative) over the last ``check`` steps.
+    """
+    import scipy.linalg as sla
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    v /= np.linalg.norm(v)
+    vp = np.zeros_like(v)
+    beta = 0.0
+    al, be = [], []
+    last = np.inf
+    for j in range(max_steps):
+        w = apply(v) - beta * vp
+        a = float(np.real(np.vdot(v, w)))
+        w -= a * v
+        b = float(np.linalg.norm(w))
+        al.append(a)
+        be.append(b)
+        if (j + 1) % check == 0:
+            th = float(sla.eigvalsh_tridiagonal(np.array(al), np.array(be[:-1]), select="i",
+                                                select_range=(0, 0))[0])
+            if abs(last - th) <= rtol * abs(th):
+                return th, j + 1
+            last = th
+        vp, v = v, w / b
+        beta = b
+    return last, max_steps
+
+
+def search_large(dims, target, seed=0, eps=0.5, k0=0.140, k1=0.145, rel=0.05, log=print):
+    """Secant iteration on f(kappa) = sqrt(lambda_min(M^dag M)) - target, lower side of kappa_c."""
+    from lattice_inputs import su3_links
+    from .cwilson import CWilson
+    U = su3_links(dims, seed, eps)
+    n = 12 * int(np.prod(dims))
+
+    def f(kappa):
+        t0 = time.time()
+        op = CWilson(U, dims, kappa)
+        th, steps = lanczos_min_eig(op.MdagM, n)
+        val = float(np.sqrt(max(th, 0.0)))
+        log(f"kappa {kappa:.7f}: min|lambda| {val:.5e} ({steps} Lanczos steps, {time.time() - t0:.0f}s)")
+        return val
+
+    pts = [(k0, f(k0)), (k1, f(k1))]
+    for _ in range(8):
+        (ka, fa), (kb, fb) = pts[-2], pts[-1]
+        if abs(fb - target) <= rel * target:
+            return dict(dims=list(dims), seed=int(seed), eps=eps, target=target, kappa=float(kb),
+                        min_abs_eig=float(fb), method="lanczos-secant")
+        kc = kb + (target - fb) * (kb - ka) / (fb - fa)
+        kc = min(kc, kb + 2 * (kb - ka)) if kb > ka else kc
+        pts.append((kc, f(kc)))
+    raise RuntimeError("secant search did not reach the target")
+
+
 def main(argv=None):
+    argv = argv or ["small"]
     out = os.path.join(os.path.dirname(__file__), "..", "tests", "golden", "kappa.json")
     res = {}
     if os.path.exists(out):
         with open(out) as fh:
             res = json.load(fh)
-    res["4x4x4x4"] = search_small((4, 4, 4, 4), 1e-3)
+    if "small" in argv:
+        res["4x4x4x4"] = search_small((4, 4, 4, 4), 1e-3)
+    if "large" in argv:
+        res["16x16x16x32"] = search_large((16, 16, 16, 32), 1e-4, log=lambda m: print(m, flush=True))
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
     print(json.dumps(res, indent=1))

@@ -52,6 +52,7 @@ Lattice make_lattice(const int dims[4]);
 // ---- device memory --------------------------------------------------------
 void* dmalloc(size_t bytes);
 void dfree(void* p);
+void dzero(void* p, size_t bytes);  // synchronous clear of a fresh allocation
 
 template <class T>
 struct DBuf {
@@ -69,7 +70,10 @@ struct DBuf {
   ~DBuf() { release(); }
   void alloc(size_t count) {
     release();
-    if (count) p = static_cast<T*>(dmalloc(count * sizeof(T)));
+    if (count) {
+      p = static_cast<T*>(dmalloc(count * sizeof(T)));
+      dzero(p, count * sizeof(T));
+    }
     n = count;
   }
   void release() { if (p) dfree(p); p = nullptr; n = 0; }

@@ -31,6 +31,8 @@ void* dmalloc(size_t bytes) {
   return p;
 }
 
+void dzero(void* p, size_t bytes) { DL_HIP(hipMemset(p, 0, bytes)); }
+
 void dfree(void* p) {
   if (p) (void)hipFree(p);
 }

@@ -135,10 +135,15 @@ __device__ __forceinline__ void hop_dir(const double2* __restrict__ U, const dou
 template <int WHICH, int RED>
 __global__ void __launch_bounds__(kBlock)
 k_wilson_f64(const double2* __restrict__ U, const double2* __restrict__ in, double2* __restrict__ out,
-             double kappa, int Lx, int Ly, int Lz, int Lt, long V, double* __restrict__ part) {
+             double kappa, int Lx, int Ly, int Lz, int Lt, long V, long Vpad, double* __restrict__ part) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const long site = (long)lb * kBlock + threadIdx.x;
   double red = 0.0;
+  if (site >= V && site < Vpad) {
+    // padding sites of the last tile are kept at zero
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[sp_idx(site, c)] = make_double2(0.0, 0.0);
+  }
   if (site < V) {
     const int x = site % Lx;
     const int y = (site / Lx) % Ly;
@@ -180,11 +185,11 @@ static void launch_which(hipStream_t s, const Lattice& lat, const double2* U, do
   const dim3 grid(nb), block(kBlock);
   const int* L = lat.L;
   if (red == 0)
-    hipLaunchKernelGGL((k_wilson_f64<WHICH, 0>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, part);
+    hipLaunchKernelGGL((k_wilson_f64<WHICH, 0>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, part);
   else if (red == 1)
-    hipLaunchKernelGGL((k_wilson_f64<WHICH, 1>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, part);
+    hipLaunchKernelGGL((k_wilson_f64<WHICH, 1>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, part);
   else
-    hipLaunchKernelGGL((k_wilson_f64<WHICH, 2>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, part);
+    hipLaunchKernelGGL((k_wilson_f64<WHICH, 2>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, part);
 }
 
 int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,

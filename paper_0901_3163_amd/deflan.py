@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -138,6 +139,7 @@ class Context:
         h = C.c_void_p()
         _check(lib.dl_ctx_create(device, C.c_void_p(hip_stream) if hip_stream else None, C.byref(h)))
         self.h = h
+        self._children = weakref.WeakSet()  # operators and handles that must be freed first
 
     def sync(self):
         _check(lib.dl_ctx_sync(self.h))
@@ -152,6 +154,12 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            kids = list(self._children)
+            for ch in kids:  # eigenvector handles before operators
+                if isinstance(ch, Eig):
+                    ch.close()
+            for ch in kids:
+                ch.close()
             lib.dl_ctx_destroy(self.h)
             self.h = None
 
@@ -168,6 +176,7 @@ class Eig:
     def __init__(self, h, op):
         self.h = h
         self.op = op
+        op.ctx._children.add(self)
 
     def info(self):
         k = C.c_int()
@@ -215,6 +224,7 @@ class Operator:
         h = C.c_void_p()
         _check(lib.dl_op_create(ctx.h, d, p, mem, float(kappa), int(kind), C.byref(h)))
         self.h = h
+        ctx._children.add(self)
         self.kind = kind
         self.kappa = kappa
 
