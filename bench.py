@@ -1,0 +1,289 @@
+"""Benchmark: later right-hand sides per second to rel. residual 1e-10, plus Wilson Dslash HBM GB/s.
+
+Workload (one GPU): the 16^3 x 32 near-critical Wilson lattice (links
+U = exp(0.5 i X), seed 0; kappa from the oracle's kappa search, min|lambda(gamma5 M)|
+~ 1e-4).  Setup, untimed and reported separately: MinRes-DR(120,60) on gamma5 M
+for a Gaussian first right-hand side (seed 200).  One timed step: D-MinRes for
+the 12 spin-colour point sources e_{site 0, spin s, colour c}, every one
+verified by its FP64 true residual <= 1e-10.  Inputs and outputs stay in HBM
+(torch complex128 device tensors passed as device pointers).
+
+value = 12 * steps / timed seconds (RHS/s).  roofline: the Wilson stencil,
+its average launch duration taken with HIP events around every launch inside
+the timed region, algorithmic bytes 960 B/site (FP64: input spinor, links,
+output spinor each moved once).  cpu_baseline: the oracle's D-MinRes on the
+host cores for a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "RHS/s to rel.res 1e-10 (learned+mixed+batched vs plain FP64); Dslash HBM GB/s"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kappa_for(name):
+    with open(os.path.join(ROOT, "tests", "golden", "kappa.json")) as fh:
+        return json.load(fh)[name]
+
+
+def point_sources(dims):
+    from lattice_inputs import point_source
+    return np.stack([point_source(dims, 0, s, c) for s in range(4) for c in range(3)])
+
+
+def wilson_source_hash():
+    h = hashlib.sha256()
+    for f in ("wilson.hip", "cplx.hpp"):
+        with open(os.path.join(ROOT, "paper_0901_3163_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(dims):
+    """HBM bytes per Wilson launch from the committed rocprofv3 counter summary, if current."""
+    p = os.path.join(ROOT, "profiles", "wilson_f32_nrhs12_16x16x16x32_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != wilson_source_hash() or tuple(t.get("dims", ())) != tuple(dims):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def tiled_links(dims, seed=0):
+    """SU(3) links for a large lattice: a seeded 8^4 field repeated periodically (values only
+    matter for bandwidth, and every link is still an SU(3) matrix)."""
+    from lattice_inputs import su3_links
+    small = (8, 8, 8, 8)
+    u = su3_links(small, seed).reshape(small[3], small[2], small[1], small[0], 4, 3, 3)
+    reps = (dims[3] // 8, dims[2] // 8, dims[1] // 8, dims[0] // 8, 1, 1, 1)
+    return np.ascontiguousarray(np.tile(u, reps).reshape(-1, 4, 3, 3))
+
+
+def dslash_sweep(ctx, deflan, sizes, reps):
+    """HBM GB/s of the Wilson stencil on lattices above the 256 MB Infinity Cache (event-timed)."""
+    import torch
+    out = {}
+    for dims in sizes:
+        V = int(np.prod(dims))
+        U = torch.from_numpy(tiled_links(dims)).cuda()
+        op = deflan.Operator(ctx, dims, U, 0.13, deflan.DL_G5M)
+        del U
+        torch.cuda.empty_cache()
+        for prec, pname in ((deflan.DL_FP64, "fp64"), (deflan.DL_FP32, "fp32")):
+            for nrhs in (1, 12):
+                op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, 2)  # warm-up
+                ms, by = op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, reps)
+                gbs = by / (ms * 1e-3) / 1e9
+                key = f"{'x'.join(map(str, dims))}/{pname}/nrhs{nrhs}"
+                out[key] = dict(bytes_per_launch=by, avg_us=round(ms * 1e3, 1), GBps=round(gbs, 1),
+                                frac=round(gbs / HBM_PEAK_GBS, 4), working_set_MB=round(by / 1e6, 1),
+                                cache_resident=by < 256e6)
+                log(f"dslash {key}: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s")
+        op.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(dims, kappa, iters_per_rhs, k):
+    """Oracle D-MinRes on the host cores: one point source, projection + 200 MinRes iterations."""
+    from lattice_inputs import point_source, su3_links
+    from oracle import cwilson, deflated, krylov
+    cores = len(os.sched_getaffinity(0))
+    U = su3_links(dims, 0)
+    op = cwilson.CWilson(U, dims, kappa)
+    n = op.n
+    rng = np.random.default_rng(7)
+    Y, _ = np.linalg.qr(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    b = point_source(dims, 0, 0, 0).ravel()
+    t0 = time.time()
+    H = deflated.projection_matrix(op.g5M, Y)  # once per handle, not per rhs
+    t_h = time.time() - t0
+    nit = 200
+    t0 = time.time()
+    bA = np.where(np.tile([1] * 6 + [-1] * 6, n // 12) > 0, b, -b)  # gamma5 b
+    x0 = deflated.galerkin_projection(Y, H, bA)
+    t_proj = time.time() - t0
+    t0 = time.time()
+    krylov.minres(op.g5M, bA, x0=x0, tol=0.0, maxiter=nit)
+    t_it = (time.time() - t0) / nit
+    per_rhs = t_proj + iters_per_rhs * t_it
+    return dict(value=round(1.0 / per_rhs, 5), unit="RHS/s", cores=cores, kind="oracle",
+                sample=(f"oracle D-MinRes (numpy vectors, OpenMP C Wilson matrix) on {'x'.join(map(str, dims))}: "
+                        f"Galerkin projection over {k} seeded orthonormal vectors ({t_proj:.2f}s) + {nit} MinRes "
+                        f"iterations ({t_it * 1e3:.1f} ms/iter) on one point source; per-rhs time = projection + "
+                        f"{iters_per_rhs:.0f} iterations (the GPU run's mean per rhs); H = Y^H A Y setup "
+                        f"({t_h:.1f}s) excluded like the GPU's"),
+                seconds_per_rhs=round(per_rhs, 3))
+
+
+def kernel_only(args):
+    """The dominant kernel alone, for rocprofv3 counter runs: the FP32 gamma5 M stencil on the
+    16^3x32 lattice for 12 right-hand sides at once (reps launches), then a device copy of
+    1 GiB (reps launches) whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    import torch
+    from paper_0901_3163_amd import deflan
+    e = kappa_for("16x16x16x32")
+    dims = tuple(e["dims"])
+    ctx = deflan.Context(0)
+    op = deflan.Operator(ctx, dims, torch.from_numpy(tiled_links(dims)).cuda(), e["kappa"], deflan.DL_G5M)
+    ms, by = op.bench_wilson(deflan.DL_APPLY_G5M, deflan.DL_FP32, 12, args.reps)
+    log(f"wilson fp32 nrhs12: {ms * 1e3:.1f} us/launch, algorithmic {by / 1e6:.1f} MB/launch")
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    for _ in range(args.reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copy: 1 GiB read + 1 GiB written per launch")
+    print(json.dumps(dict(kernel="k_wilson<float,2,0>", dims=list(dims), nrhs=12, reps=args.reps,
+                          avg_us=round(ms * 1e3, 2), algorithmic_bytes=by, copy_bytes=1 << 30,
+                          source_hash=wilson_source_hash())))
+    op.close()
+    ctx.close()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain FP64 baseline")
+    ap.add_argument("--m", type=int, default=120)
+    ap.add_argument("--k", type=int, default=60)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the Dslash bandwidth sweep")
+    ap.add_argument("--kappa", type=float, default=None, help="override the stored kappa (exploration only)")
+    ap.add_argument("--kernel-only", action="store_true", help="run only the dominant kernel + a copy (profiling)")
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded across GPUs.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.kernel_only:
+        return kernel_only(args)
+    os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from lattice_inputs import gaussian_spinor, su3_links
+    from paper_0901_3163_amd import deflan
+
+    try:
+        e = kappa_for("16x16x16x32")
+    except KeyError:
+        e = dict(dims=[16, 16, 16, 32], seed=0, eps=0.5, kappa=None)
+    dims = tuple(e["dims"])
+    kappa = args.kappa if args.kappa is not None else e["kappa"]
+    if kappa is None:
+        sys.exit("no kappa stored for 16x16x16x32: run `python -m oracle.kappa large`")
+    V = int(np.prod(dims))
+    ctx = deflan.Context(0)
+    log(f"workload 16^3x32 kappa={kappa:.7f}: building operator")
+    U = torch.from_numpy(su3_links(dims, e["seed"], e["eps"])).cuda()
+    op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_G5M)
+    b1 = torch.from_numpy(gaussian_spinor(dims, 200)).cuda()
+    log(f"first rhs: MinRes-DR({args.m},{args.k})")
+    t0 = time.time()
+    x1, eig, st1 = op.solve_first(b1, args.m, args.k, args.tol)
+    torch.cuda.synchronize()
+    t_first = time.time() - t0
+    log(f"first rhs done: {st1['mvp']} MVPs ({st1['mvp_lin']} at linear convergence), {t_first:.1f}s, "
+        f"relres {st1['relres']:.2e}, rule {st1['stop_rule']}")
+    B = torch.from_numpy(point_sources(dims)).cuda()
+    nrhs = B.shape[0]
+
+    def fast():
+        return op.solve_next(B, eig, args.tol, storage=deflan.DL_FP32, batched=1)
+
+    def plain():
+        return op.solve_next(B, eig, args.tol)
+
+    for w in range(args.warmup):
+        X, sts, rc = fast()
+        log(f"warmup {w} (batched FP32): iters {[s['iters'] for s in sts]}")
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.time()
+    all_ok = True
+    iters = []
+    for s in range(args.steps):
+        X, sts, rc = fast()
+        all_ok &= all(st["relres"] <= args.tol for st in sts)
+        iters += [st["iters"] for st in sts]
+        log(f"step {s}: rc {rc}, max relres {max(st['relres'] for st in sts):.2e}")
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    n_w, ms_w, by_w = ctx.kernel_time("wilson")
+    ctx.timing(False)
+    value = nrhs * args.steps / dt
+    achieved = by_w / (ms_w * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(dims),
+                    kernel="k_wilson<float, gamma5 M> (FP32, batched over right-hand sides)", launches=n_w,
+                    avg_us=round(ms_w / max(n_w, 1) * 1e3, 2), bytes_per_launch=round(by_w / max(n_w, 1)),
+                    note=("algorithmic bytes per launch: links once (288 B/site FP32) + input and output "
+                          "spinor per active rhs (192 B/site); the 16^3x32 working set fits the 256 MB "
+                          "Infinity Cache, see dslash_sweep for HBM-resident sizes"))
+    # plain FP64 D-MinRes, one rhs after another: the baseline the fast path is compared with
+    log("plain FP64 baseline")
+    X64, st64, _ = plain()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for s in range(args.plain_steps):
+        X64, st64, _ = plain()
+    torch.cuda.synchronize()
+    dt64 = time.time() - t0
+    plain_value = nrhs * args.plain_steps / dt64
+    ok64 = all(st["relres"] <= args.tol for st in st64)
+    log(f"fast {value:.2f} RHS/s, plain FP64 {plain_value:.2f} RHS/s")
+    result = dict(metric=METRIC, value=round(value, 3), unit="RHS/s", n_gpus=1, steps=args.steps,
+                  warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 2), higher_is_better=True,
+                  scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+                  config=dict(workload=f"16^3x32 Wilson near-critical (kappa {kappa:.6f}), MinRes-DR({args.m},"
+                                       f"{args.k}) on gamma5 M then D-MinRes on 12 point sources, tol "
+                                       f"{args.tol:g}", lattice=list(dims), kappa=kappa, nrhs=nrhs,
+                              m=args.m, k=args.k,
+                              path="batched D-MinRes, FP32 Krylov vectors and Wilson apply, FP64 residuals, "
+                                   "projection and solution"),
+                  all_rhs_converged=bool(all_ok), iters_per_rhs=float(np.mean(iters)),
+                  plain_fp64=dict(value=round(plain_value, 3), unit="RHS/s", steps=args.plain_steps,
+                                  all_rhs_converged=bool(ok64),
+                                  iters_per_rhs=float(np.mean([st["iters"] for st in st64])),
+                                  path="D-MinRes FP64, one rhs after another"),
+                  speedup_vs_plain_fp64=round(value / plain_value, 3),
+                  first_rhs=dict(mvp=st1["mvp"], mvp_lin=st1["mvp_lin"], seconds=round(t_first, 2),
+                                 relres=st1["relres"], stop_rule=st1["stop_rule"],
+                                 mvp_overhead=round(st1["mvp"] / max(st1["mvp_lin"], 1), 3)),
+                  roofline=roofline)
+    if not args.no_sweep:
+        result["dslash_sweep"] = dslash_sweep(ctx, deflan, [(24, 24, 24, 48), (32, 32, 32, 64)], reps=20)
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(dims, kappa, result["plain_fp64"]["iters_per_rhs"], args.k)
+    eig.close()
+    op.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

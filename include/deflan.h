@@ -134,10 +134,13 @@ int  dl_ctx_sync(dl_ctx* ctx);
  * bracketed by HIP events on the context's stream and its duration summed.
  * name: "wilson" (every M / M^dag / gamma5 M launch in the precision used),
  * "tsk_dots" (V^H w), "tsk_update" (V c / V Y), "small" (one-workgroup FP64
- * problems).  dl_kernel_time returns launches and total milliseconds since the
- * last reset (enable != 0 resets). */
+ * problems).  dl_kernel_time returns launches, total milliseconds and (bytes
+ * may be NULL) the algorithmic bytes those launches moved -- for "wilson" the
+ * input spinors, links and output spinors counted once: 960 B/site in FP64,
+ * 288 + 192 * nrhs B/site for an FP32 batch -- since the last reset
+ * (dl_timing resets). */
 int  dl_timing(dl_ctx* ctx, int enable);
-int  dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_ms);
+int  dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_ms, double* bytes);
 
 /* ---- operator ----------------------------------------------------------- */
 /* Create the operator A of the paper for links U, hopping parameter kappa and
@@ -176,6 +179,14 @@ int  dl_solve_first(dl_op* op, const double* b, double* x, int mem, int m, int k
 int  dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B,
                    double* X, int mem, double tol, const dl_next_opts* opts,
                    dl_stats* stats);
+
+/* Measurement: average duration (ms) of one launch of the Wilson stencil
+ * `which` (DL_APPLY_M, _MDAG or _G5M) in precision `prec` (DL_FP64 / DL_FP32)
+ * applied to nrhs zero-filled device fields at once, over `reps` back-to-back
+ * launches timed with HIP events; *bytes (may be NULL) receives the
+ * algorithmic bytes of one launch (links once, each input and output spinor
+ * once).  Allocates and frees its own fields. */
+int  dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* avg_ms, double* bytes);
 
 /* ---- eigenvector handle ---------------------------------------------------- */
 /* Build a handle from k caller-supplied orthonormal vectors V ([k][V][4][3]);

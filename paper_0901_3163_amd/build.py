@@ -1,6 +1,6 @@
 """Build libdeflan.so (HIP, gfx950) in-tree with hipcc.
 
-``python -m paper_0901_3163_amd.build`` compiles every ``csrc/*.hip`` into an
+``python paper_0901_3163_amd/build.py`` compiles every ``csrc/*.hip`` into an
 object under ``_build/`` and links ``paper_0901_3163_amd/libdeflan.so``.
 """
 from __future__ import annotations

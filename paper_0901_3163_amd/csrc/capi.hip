@@ -180,7 +180,7 @@ int dl_timing(dl_ctx* ctx, int enable) {
   });
 }
 
-int dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_ms) {
+int dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_ms, double* bytes) {
   return guard([&] {
     need(ctx && name && launches && total_ms, "NULL argument");
     use_device(ctx);
@@ -193,6 +193,7 @@ int dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_
     ctx->timers.collect();
     *launches = ctx->timers.launches[id];
     *total_ms = ctx->timers.ms[id];
+    if (bytes) *bytes = ctx->timers.bytes[id];
     return DL_OK;
   });
 }
@@ -307,17 +308,69 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
     need(tol > 0 && std::isfinite(tol), "tol must be positive");
     const dl_next_opts o = next_defaults(opts);
-    need(o.storage == DL_FP64, "only DL_FP64 storage is available in this build");
-    need(o.batched == 0, "batched execution is not available in this build");
+    need(o.storage == DL_FP64 || o.storage == DL_FP32, "storage must be DL_FP64 or DL_FP32");
+    need(!(o.storage == DL_FP32 && !o.batched), "DL_FP32 storage runs through the batched path (batched = 1)");
+    need(!(o.batched && o.storage == DL_FP64), "the batched path stores Krylov vectors in DL_FP32");
     use_device(op->ctx);
     if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
       fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
     DBuf<double2> bt = fields_in(op, B, nrhs, mem);
     DBuf<double2> xt = o.x0_given ? fields_in(op, X, nrhs, mem) : DBuf<double2>((size_t)nrhs * op->lat.nc);
     if (!o.x0_given) zero(op->ctx->stream, (long)nrhs * op->lat.nc, xt.get());
-    const int rc = solve_next(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats);
+    const int rc = o.batched ? solve_next_batched(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats)
+                             : solve_next(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats);
     fields_out(op, xt.get(), X, nrhs, mem);
     return rc;
+  });
+}
+
+int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* avg_ms, double* bytes) {
+  return guard([&] {
+    need(op && avg_ms, "NULL argument");
+    need(which >= 0 && which <= 2, "which must be DL_APPLY_M, DL_APPLY_MDAG or DL_APPLY_G5M");
+    need(prec == DL_FP64 || prec == DL_FP32, "prec must be DL_FP64 or DL_FP32");
+    need(nrhs >= 1 && nrhs <= 256 && reps >= 1, "need 1 <= nrhs <= 256 and reps >= 1");
+    use_device(op->ctx);
+    hipStream_t s = op->ctx->stream;
+    const Lattice& lat = op->lat;
+    const long n = (long)nrhs * lat.nc;
+    hipEvent_t a, b;
+    DL_HIP(hipEventCreate(&a));
+    DL_HIP(hipEventCreate(&b));
+    double bb;
+    float ms = 0.f;
+    if (prec == DL_FP64) {
+      DBuf<double2> in(n), out(n);
+      zero(s, n, in.get());
+      wilson_batched<double>(s, lat, op->U.get(), op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr,
+                             nullptr, nullptr);
+      DL_HIP(hipEventRecord(a, s));
+      for (int i = 0; i < reps; ++i)
+        wilson_batched<double>(s, lat, op->U.get(), op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0,
+                               nullptr, nullptr, nullptr);
+      DL_HIP(hipEventRecord(b, s));
+      DL_HIP(hipEventSynchronize(b));
+      bb = (double)lat.V * (576.0 + 384.0 * nrhs);
+    } else {
+      DBuf<float2> in(n), out(n);
+      zero(s, n / 2, reinterpret_cast<double2*>(in.get()));  // n float2 = n/2 double2 (nc is even)
+      const float2* U32 = op_links32_public(op);
+      wilson_batched<float>(s, lat, U32, op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr, nullptr,
+                            nullptr);
+      DL_HIP(hipEventRecord(a, s));
+      for (int i = 0; i < reps; ++i)
+        wilson_batched<float>(s, lat, U32, op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr,
+                              nullptr, nullptr);
+      DL_HIP(hipEventRecord(b, s));
+      DL_HIP(hipEventSynchronize(b));
+      bb = (double)lat.V * (288.0 + 192.0 * nrhs);
+    }
+    DL_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / reps;
+    if (bytes) *bytes = bb;
+    return DL_OK;
   });
 }
 

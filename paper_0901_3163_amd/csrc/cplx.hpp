@@ -35,6 +35,42 @@ __device__ __forceinline__ double2 c_axpy(double s, double2 a, double2 acc) {
   return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
 }
 
+// float2 versions (FP32 storage and arithmetic)
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 c_i(float2 a) { return make_float2(-a.y, a.x); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 c_fma(float2 a, float2 b, float2 acc) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ float2 c_fmac(float2 a, float2 b, float2 acc) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(-a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ float2 c_axpy(float s, float2 a, float2 acc) {
+  return make_float2(fmaf(s, a.x, acc.x), fmaf(s, a.y, acc.y));
+}
+
+template <class R> struct CT;
+template <> struct CT<double> {
+  using type = double2;
+  __device__ static __forceinline__ double2 make(double x, double y) { return make_double2(x, y); }
+};
+template <> struct CT<float> {
+  using type = float2;
+  __device__ static __forceinline__ float2 make(float x, float y) { return make_float2(x, y); }
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

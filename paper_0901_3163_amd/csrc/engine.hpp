@@ -8,6 +8,7 @@ struct dl_op {
   double kappa = 0.0;
   int kind = DL_MDAGM;
   dl::DBuf<double2> U;          // FP64 links, tiled
+  dl::DBuf<float2> U32;         // FP32 links, tiled (made on first use)
   uint64_t fingerprint = 0;     // dims, kappa, kind and a hash of the links
 };
 
@@ -25,6 +26,8 @@ struct dl_eig {
 };
 
 namespace dl {
+
+bool verbose();  // DEFLAN_VERBOSE set: progress lines on stderr
 
 // Scratch owned by one solve: device scalars, reduction partials, small work.
 struct Scratch {
@@ -46,6 +49,9 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
                 dl_eig** eig_out, dl_stats* st);
 int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
                const dl_next_opts& o, dl_stats* st);
+int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
+                       const dl_next_opts& o, dl_stats* st);
 dl_eig* eig_build(dl_op* op, int k, DBuf<double2>&& Y, long* mvp);
+const float2* op_links32_public(dl_op* op);  // FP32 links of the operator (made on first use)
 
 }  // namespace dl

@@ -16,12 +16,17 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 #include <string>
 #include <vector>
 
 #include "../../include/deflan.h"
 
 namespace dl {
+
+// complex element type of a real type: double -> double2, float -> float2
+template <class R>
+using cplx_t = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
 
 constexpr int kTile = 64;      // sites per tile (= wavefront size)
 constexpr int kSpin = 12;      // complex components per spinor site
@@ -52,7 +57,6 @@ Lattice make_lattice(const int dims[4]);
 // ---- device memory --------------------------------------------------------
 void* dmalloc(size_t bytes);
 void dfree(void* p);
-void dzero(void* p, size_t bytes);  // synchronous clear of a fresh allocation
 
 template <class T>
 struct DBuf {
@@ -68,12 +72,11 @@ struct DBuf {
     return *this;
   }
   ~DBuf() { release(); }
+  // Contents are undefined: kernels write every element before reading it, and
+  // buffers that must start at zero are cleared on the context's stream.
   void alloc(size_t count) {
     release();
-    if (count) {
-      p = static_cast<T*>(dmalloc(count * sizeof(T)));
-      dzero(p, count * sizeof(T));
-    }
+    if (count) p = static_cast<T*>(dmalloc(count * sizeof(T)));
     n = count;
   }
   void release() { if (p) dfree(p); p = nullptr; n = 0; }
@@ -85,14 +88,15 @@ enum TimerId { T_WILSON = 0, T_TSK_DOTS, T_TSK_UPDATE, T_SMALL, T_COUNT };
 
 struct Timers {
   bool enabled = false;
-  struct Pair { hipEvent_t a, b; int id; };
+  struct Pair { hipEvent_t a, b; int id; double bytes; };
   std::vector<Pair> pending;
   std::vector<hipEvent_t> pool;
   long launches[T_COUNT] = {0};
   double ms[T_COUNT] = {0};
+  double bytes[T_COUNT] = {0};  // algorithmic bytes moved by the timed launches
   hipEvent_t take();
   void begin(hipStream_t s, int id, hipEvent_t* a);
-  void end(hipStream_t s, int id, hipEvent_t a);
+  void end(hipStream_t s, int id, hipEvent_t a, double bytes);
   void collect();  // sync pending events and accumulate
   void reset();
   ~Timers();
@@ -116,12 +120,13 @@ namespace dl {
 struct TimeScope {
   dl_ctx* ctx;
   int id;
+  double bytes;
   hipEvent_t a = nullptr;
-  TimeScope(dl_ctx* c, int i) : ctx(c), id(i) {
+  TimeScope(dl_ctx* c, int i, double algorithmic_bytes = 0.0) : ctx(c), id(i), bytes(algorithmic_bytes) {
     if (ctx->timers.enabled) ctx->timers.begin(ctx->stream, id, &a);
   }
   ~TimeScope() {
-    if (ctx->timers.enabled && a) ctx->timers.end(ctx->stream, id, a);
+    if (ctx->timers.enabled && a) ctx->timers.end(ctx->stream, id, a, bytes);
   }
 };
 
@@ -136,6 +141,13 @@ void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, d
 int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,
                const double2* in, double2* out, int red, double* part);
 void gamma5_f64(hipStream_t s, const Lattice& lat, const double2* in, double2* out);
+// Batched Wilson apply in FP64 (R = double) or FP32 (R = float): nrhs fields at stride fstride.
+// Partials (red != 0) are column-major [nrhs][wilson_nbs(lat)].  Returns wilson_nbs(lat) or 0.
+int wilson_nbs(const Lattice& lat);
+template <class R>
+int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,
+                   const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int red, const double* scale,
+                   const int* active, double* part);
 
 // ---- launchers: BLAS-1 ------------------------------------------------------
 int nblocks_for(long n);  // partial count used by the streaming reductions for length n

@@ -31,8 +31,6 @@ void* dmalloc(size_t bytes) {
   return p;
 }
 
-void dzero(void* p, size_t bytes) { DL_HIP(hipMemset(p, 0, bytes)); }
-
 void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
@@ -68,10 +66,10 @@ void Timers::begin(hipStream_t s, int id, hipEvent_t* a) {
   DL_HIP(hipEventRecord(*a, s));
 }
 
-void Timers::end(hipStream_t s, int id, hipEvent_t a) {
+void Timers::end(hipStream_t s, int id, hipEvent_t a, double nbytes) {
   hipEvent_t b = take();
   DL_HIP(hipEventRecord(b, s));
-  pending.push_back({a, b, id});
+  pending.push_back({a, b, id, nbytes});
   if (pending.size() > 4096) collect();
 }
 
@@ -82,6 +80,7 @@ void Timers::collect() {
     DL_HIP(hipEventElapsedTime(&ms_, p.a, p.b));
     launches[p.id] += 1;
     ms[p.id] += ms_;
+    bytes[p.id] += p.bytes;
     pool.push_back(p.a);
     pool.push_back(p.b);
   }
@@ -93,6 +92,7 @@ void Timers::reset() {
   for (int i = 0; i < T_COUNT; ++i) {
     launches[i] = 0;
     ms[i] = 0.0;
+    bytes[i] = 0.0;
   }
 }
 

@@ -24,9 +24,20 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace dl {
+
+// DEFLAN_VERBOSE=1: one progress line per restart cycle / inner cycle on stderr.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("DEFLAN_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
 
 // ---- device scalar slots ----------------------------------------------------
 enum {
@@ -241,7 +252,8 @@ static int grid_for(long n) {
 
 // ---- helpers -------------------------------------------------------------------
 void apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red, double* part) {
-  TimeScope ts(op->ctx, T_WILSON);
+  // algorithmic bytes: input spinor, links and output spinor moved once (FP64: 960 B/site)
+  TimeScope ts(op->ctx, T_WILSON, 960.0 * (double)op->lat.V);
   wilson_f64(op->ctx->stream, op->lat, op->U.get(), op->kappa, which, in, out, red, part);
 }
 
@@ -517,6 +529,11 @@ int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2
     one.mvp = mvp;
     one.relres = relres;
     one.time_s = now_s() - t0;
+    if (verbose()) {
+      std::fprintf(stderr, "[deflan] %s rhs %d: iters %ld relres %.3e (%.3fs)\n",
+                   op->kind == DL_G5M ? "D-MinRes" : "D-CG", r, iters, relres, one.time_s);
+      std::fflush(stderr);
+    }
     if (!conv) worst = DL_NOT_CONVERGED;
     if (st) st[r] = one;
   }
@@ -610,6 +627,7 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
   const int nslots = m + k + 2;
   DBuf<double2> Vb((size_t)nslots * n);
   DBuf<double2> w(n), tmp(n), rr(n);
+  zero(s, (long)nslots * n, Vb.get());
   DBuf<int> slot_d(nslots);
   std::vector<int> slot(nslots);
   for (int i = 0; i < nslots; ++i) slot[i] = i;
@@ -713,6 +731,13 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
     if (k > 0) DL_HIP(hipMemcpy(h_rho.data(), rho.get(), k * sizeof(double), hipMemcpyDeviceToHost));
     DL_HIP(hipMemcpy(h_info.data(), info.get(), 8 * sizeof(double), hipMemcpyDeviceToHost));
     anorm = std::max(anorm, h_info[0]);
+    if (verbose()) {
+      double rmax = 0.0;
+      for (int i = 0; i < k; ++i) rmax = std::max(rmax, h_rho[i]);
+      std::fprintf(stderr, "[deflan] %s cycle %d: mvp %ld relres %.3e max eig-resid %.3e (%.1fs)\n",
+                   lan ? "Lan-DR" : "MinRes-DR", cycles, mvp, relres, rmax, now_s() - t0);
+      std::fflush(stderr);
+    }
     if (breakdown) { rule = DL_STOP_BREAKDOWN; break; }
     // ---- stopping rule ----
     if (mvp_lin < 0 && relres <= tol) mvp_lin = mvp;

@@ -16,26 +16,33 @@
 //   mu=z: h0 = p0 + S i p2, h1 = p1 - S i p3;  rows 2,3 = -S i h0,  S i h1
 //   mu=t: h0 = p0 + S p2,   h1 = p1 + S p3;    rows 2,3 =  S h0,    S h1
 // One thread per site; loads of a component for 64 consecutive sites are one
-// coalesced 1 KiB wavefront access; neighbour spinors and the backward links
-// are re-read through L2 (blocks are mapped so that each XCD walks a
-// contiguous slab of the lattice, keeping the +-z/+-t neighbours in its L2).
+// coalesced wavefront access; neighbour spinors and the backward links are
+// re-read through L2 (blocks are mapped so that each XCD walks a contiguous
+// slab of the lattice, keeping the +-z/+-t neighbours in its L2).
+//
+// The kernel is templated on the storage/arithmetic type (double: FP64,
+// float: FP32 with FP32 accumulation) and applies the operator to a batch of
+// right-hand sides: logical block b covers site block b / nrhs of right-hand
+// side b % nrhs, so the nrhs blocks that read the same links are consecutive
+// on one XCD and the links come from HBM once and from L2 for the others.
 #include "internal.hpp"
 #include "cplx.hpp"
 
 namespace dl {
 
-__device__ __forceinline__ long sp_idx(long site, int c) {
-  return ((site >> 6) * kSpin + c) * kTile + (site & 63);
-}
-__device__ __forceinline__ long lk_idx(long site, int mu, int e) {
-  return ((site >> 6) * kLinkC + mu * 9 + e) * kTile + (site & 63);
+// Element offsets are signed 32-bit ints (a field holds far fewer than 2^31
+// elements), so component c of a site is base + off + c*64 and the c*64 part
+// folds into the load's immediate offset.
+__device__ __forceinline__ int sp_base(int site) { return (site >> 6) * (kSpin * kTile) + (site & 63); }
+__device__ __forceinline__ int lk_base(int site, int mu) {
+  return (site >> 6) * (kLinkC * kTile) + mu * 9 * kTile + (site & 63);
 }
 
-template <int MU, int S>
-__device__ __forceinline__ void project(const double2 p[12], double2 h[6]) {
+template <int MU, int S, class C>
+__device__ __forceinline__ void project(const C p[12], C h[6]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double2 p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+    const C p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
     if (MU == 0) {
       h[c] = S > 0 ? c_add(p0, c_i(p3)) : c_sub(p0, c_i(p3));
       h[3 + c] = S > 0 ? c_add(p1, c_i(p2)) : c_sub(p1, c_i(p2));
@@ -52,11 +59,11 @@ __device__ __forceinline__ void project(const double2 p[12], double2 h[6]) {
   }
 }
 
-template <int MU, int S>
-__device__ __forceinline__ void reconstruct(double2 acc[12], const double2 g[6]) {
+template <int MU, int S, class C>
+__device__ __forceinline__ void reconstruct(C acc[12], const C g[6]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double2 g0 = g[c], g1 = g[3 + c];
+    const C g0 = g[c], g1 = g[3 + c];
     acc[c] = c_add(acc[c], g0);
     acc[3 + c] = c_add(acc[3 + c], g1);
     if (MU == 0) {
@@ -75,132 +82,167 @@ __device__ __forceinline__ void reconstruct(double2 acc[12], const double2 g[6])
   }
 }
 
-// g = U h (per spin row) for the forward hop, U loaded from `site`.
-__device__ __forceinline__ void mul_u(const double2* __restrict__ U, long site, int mu,
-                                      const double2 h[6], double2 g[6]) {
-  double2 u[9];
+template <int S, class C>
+__device__ __forceinline__ void project_mu(int mu, const C p[12], C h[6]) {
+  switch (mu) {
+    case 0: project<0, S>(p, h); break;
+    case 1: project<1, S>(p, h); break;
+    case 2: project<2, S>(p, h); break;
+    default: project<3, S>(p, h); break;
+  }
+}
+
+template <int S, class C>
+__device__ __forceinline__ void reconstruct_mu(int mu, C acc[12], const C g[6]) {
+  switch (mu) {
+    case 0: reconstruct<0, S>(acc, g); break;
+    case 1: reconstruct<1, S>(acc, g); break;
+    case 2: reconstruct<2, S>(acc, g); break;
+    default: reconstruct<3, S>(acc, g); break;
+  }
+}
+
+// One hop in direction mu (runtime): load the neighbour spinor and the link,
+// project, multiply by U (forward) or U^dag (backward, link taken at the
+// neighbour), rebuild and accumulate.  Every load address depends on mu, so
+// the loads of different directions cannot be hoisted ahead of each other.
+template <int S, bool DAG, class C>
+__device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int lsite, C acc[12]) {
+  C p[12], h[6], g[6], u[9];
+  const C* pp = in + sp_base(nb);
 #pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = U[lk_idx(site, mu, e)];
+  for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+  const C* up = U + lk_base(lsite, mu);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+  project_mu<S>(mu, p, h);
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      double2 r = c_mul(u[a * 3 + 0], h[s * 3 + 0]);
-      r = c_fma(u[a * 3 + 1], h[s * 3 + 1], r);
-      r = c_fma(u[a * 3 + 2], h[s * 3 + 2], r);
+      C r = c_scale(h[s * 3], 0);
+      if (!DAG) {
+        r = c_fma(u[a * 3 + 0], h[s * 3 + 0], r);
+        r = c_fma(u[a * 3 + 1], h[s * 3 + 1], r);
+        r = c_fma(u[a * 3 + 2], h[s * 3 + 2], r);
+      } else {
+        r = c_fmac(u[0 * 3 + a], h[s * 3 + 0], r);
+        r = c_fmac(u[1 * 3 + a], h[s * 3 + 1], r);
+        r = c_fmac(u[2 * 3 + a], h[s * 3 + 2], r);
+      }
       g[s * 3 + a] = r;
     }
+  reconstruct_mu<S>(mu, acc, g);
 }
 
-// g = U^dag h for the backward hop, U loaded from `site` (= x - mu).
-__device__ __forceinline__ void mul_udag(const double2* __restrict__ U, long site, int mu,
-                                         const double2 h[6], double2 g[6]) {
-  double2 u[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = U[lk_idx(site, mu, e)];
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double2 r = make_double2(0.0, 0.0);
-      r = c_fmac(u[0 * 3 + a], h[s * 3 + 0], r);
-      r = c_fmac(u[1 * 3 + a], h[s * 3 + 1], r);
-      r = c_fmac(u[2 * 3 + a], h[s * 3 + 2], r);
-      g[s * 3 + a] = r;
-    }
-}
-
-__device__ __forceinline__ void load_spinor(const double2* __restrict__ in, long site, double2 p[12]) {
-#pragma unroll
-  for (int c = 0; c < 12; ++c) p[c] = in[sp_idx(site, c)];
-}
-
-template <int MU, int SF>
-__device__ __forceinline__ void hop_dir(const double2* __restrict__ U, const double2* __restrict__ in,
-                                        long site, long fwd, long bwd, double2 acc[12]) {
-  double2 p[12], h[6], g[6];
-  // forward: (1 + SF g_mu) U_mu(x) psi(x + mu)
-  load_spinor(in, fwd, p);
-  project<MU, SF>(p, h);
-  mul_u(U, site, MU, h, g);
-  reconstruct<MU, SF>(acc, g);
-  // backward: (1 - SF g_mu) U_mu(x - mu)^dag psi(x - mu)
-  load_spinor(in, bwd, p);
-  project<MU, -SF>(p, h);
-  mul_udag(U, bwd, MU, h, g);
-  reconstruct<MU, -SF>(acc, g);
-}
-
-// WHICH: 0 M, 1 M^dag, 2 gamma5 M.  RED: 0 none, 1 ||out||^2, 2 Re<in, out>.
-template <int WHICH, int RED>
-__global__ void __launch_bounds__(kBlock)
-k_wilson_f64(const double2* __restrict__ U, const double2* __restrict__ in, double2* __restrict__ out,
-             double kappa, int Lx, int Ly, int Lz, int Lt, long V, long Vpad, double* __restrict__ part) {
+// WHICH: 0 M, 1 M^dag, 2 gamma5 M.  RED: 0 none, 1 ||out||^2, 2 Re<in, out> (partials in FP64,
+// column-major [nrhs][nbs]).  scale (optional, per rhs): out = scale * op(in).
+// active (optional, per rhs): blocks of inactive right-hand sides return at once.
+template <class R, int WHICH, int RED>
+__global__ void __launch_bounds__(kBlock, 2)
+k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
+         typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+         int Lt, long V, long Vpad, int nbs, const double* __restrict__ scale, const int* __restrict__ active,
+         double* __restrict__ part) {
+  using C = typename CT<R>::type;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const long site = (long)lb * kBlock + threadIdx.x;
+  const int rhs = lb % nrhs, sb = lb / nrhs;
+  if (active && !active[rhs]) return;
+  in += rhs * fstride;
+  out += rhs * fstride;
+  const int site = sb * kBlock + (int)threadIdx.x;
   double red = 0.0;
   if (site >= V && site < Vpad) {
     // padding sites of the last tile are kept at zero
+    C* op = out + sp_base(site);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) out[sp_idx(site, c)] = make_double2(0.0, 0.0);
+    for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
   }
   if (site < V) {
     const int x = site % Lx;
     const int y = (site / Lx) % Ly;
-    const int z = (site / ((long)Lx * Ly)) % Lz;
-    const int t = site / ((long)Lx * Ly * Lz);
-    const long sy = Lx, sz = (long)Lx * Ly, st = (long)Lx * Ly * Lz;
-    const long xf = site + (x == Lx - 1 ? 1 - Lx : 1), xb = site + (x == 0 ? Lx - 1 : -1);
-    const long yf = site + (y == Ly - 1 ? (1 - Ly) * sy : sy), yb = site + (y == 0 ? (Ly - 1) * sy : -sy);
-    const long zf = site + (z == Lz - 1 ? (1 - Lz) * sz : sz), zb = site + (z == 0 ? (Lz - 1) * sz : -sz);
-    const long tf = site + (t == Lt - 1 ? (1 - Lt) * st : st), tb = site + (t == 0 ? (Lt - 1) * st : -st);
-    double2 acc[12];
+    const int z = (site / (Lx * Ly)) % Lz;
+    const int t = site / (Lx * Ly * Lz);
+    const int sy = Lx, sz = Lx * Ly, st = Lx * Ly * Lz;
+    // neighbour offsets per direction: forward d_f[mu], backward d_b[mu]
+    const int fx = x == Lx - 1 ? 1 - Lx : 1, bx = x == 0 ? Lx - 1 : -1;
+    const int fy = y == Ly - 1 ? (1 - Ly) * sy : sy, by = y == 0 ? (Ly - 1) * sy : -sy;
+    const int fz = z == Lz - 1 ? (1 - Lz) * sz : sz, bz = z == 0 ? (Lz - 1) * sz : -sz;
+    const int ft = t == Lt - 1 ? (1 - Lt) * st : st, bt = t == 0 ? (Lt - 1) * st : -st;
+    C acc[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = make_double2(0.0, 0.0);
-    constexpr int SF = (WHICH == 1) ? 1 : -1;  // forward projector sign
-    hop_dir<0, SF>(U, in, site, xf, xb, acc);
-    hop_dir<1, SF>(U, in, site, yf, yb, acc);
-    hop_dir<2, SF>(U, in, site, zf, zb, acc);
-    hop_dir<3, SF>(U, in, site, tf, tb, acc);
+    for (int c = 0; c < 12; ++c) acc[c] = CT<R>::make(0, 0);
+    constexpr int SF = (WHICH == 1) ? 1 : -1;  // forward projector 1 + SF g_mu, backward 1 - SF g_mu
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const int df = mu == 0 ? fx : mu == 1 ? fy : mu == 2 ? fz : ft;
+      const int db = mu == 0 ? bx : mu == 1 ? by : mu == 2 ? bz : bt;
+      hop<SF, false>(U, in, mu, site + df, site, acc);
+      hop<-SF, true>(U, in, mu, site + db, site + db, acc);
+    }
+    const R sc = scale ? (R)scale[rhs] : (R)1;
+    const R mk = (R)(-kappa);
+    const C* ip = in + sp_base(site);
+    C* op = out + sp_base(site);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      const double2 p = in[sp_idx(site, c)];
-      double2 r = make_double2(fma(-kappa, acc[c].x, p.x), fma(-kappa, acc[c].y, p.y));
-      if (WHICH == 2 && c >= 6) r = make_double2(-r.x, -r.y);
-      out[sp_idx(site, c)] = r;
-      if (RED == 1) red += r.x * r.x + r.y * r.y;
-      if (RED == 2) red += p.x * r.x + p.y * r.y;
+      const C p = ip[c * kTile];
+      C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
+      if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
+      op[c * kTile] = r;
+      if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
+      if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
     }
   }
   if (RED != 0) {
     __shared__ double lds[kBlock / 64];
     const double s = block_sum<kBlock>(red, lds);
-    if (threadIdx.x == 0) part[lb] = s;
+    if (threadIdx.x == 0) part[(long)rhs * nbs + sb] = s;
   }
 }
 
-template <int WHICH>
-static void launch_which(hipStream_t s, const Lattice& lat, const double2* U, double kappa,
-                         const double2* in, double2* out, int red, double* part, int nb) {
-  const dim3 grid(nb), block(kBlock);
+template <class R, int WHICH>
+static void launch_which(hipStream_t s, const Lattice& lat, const typename CT<R>::type* U, double kappa,
+                         const typename CT<R>::type* in, typename CT<R>::type* out, long fstride, int nrhs,
+                         int red, const double* scale, const int* active, double* part, int nbs) {
+  const dim3 grid(nbs * nrhs), block(kBlock);
   const int* L = lat.L;
+  const long Vpad = lat.ntiles * kTile;
   if (red == 0)
-    hipLaunchKernelGGL((k_wilson_f64<WHICH, 0>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, part);
+    hipLaunchKernelGGL((k_wilson<R, WHICH, 0>), grid, block, 0, s, U, in, out, fstride, nrhs, kappa, L[0], L[1],
+                       L[2], L[3], lat.V, Vpad, nbs, scale, active, part);
   else if (red == 1)
-    hipLaunchKernelGGL((k_wilson_f64<WHICH, 1>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, part);
+    hipLaunchKernelGGL((k_wilson<R, WHICH, 1>), grid, block, 0, s, U, in, out, fstride, nrhs, kappa, L[0], L[1],
+                       L[2], L[3], lat.V, Vpad, nbs, scale, active, part);
   else
-    hipLaunchKernelGGL((k_wilson_f64<WHICH, 2>), grid, block, 0, s, U, in, out, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, part);
+    hipLaunchKernelGGL((k_wilson<R, WHICH, 2>), grid, block, 0, s, U, in, out, fstride, nrhs, kappa, L[0], L[1],
+                       L[2], L[3], lat.V, Vpad, nbs, scale, active, part);
 }
+
+int wilson_nbs(const Lattice& lat) { return (int)((lat.V + kBlock - 1) / kBlock); }
+
+template <class R>
+int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,
+                   const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int red, const double* scale,
+                   const int* active, double* part) {
+  const int nbs = wilson_nbs(lat);
+  if (red && nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
+  if ((long)nbs * nrhs > 2147483647L) fail(DL_E_INVALID, "grid too large");
+  if (which == 0) launch_which<R, 0>(s, lat, U, kappa, in, out, fstride, nrhs, red, scale, active, part, nbs);
+  else if (which == 1) launch_which<R, 1>(s, lat, U, kappa, in, out, fstride, nrhs, red, scale, active, part, nbs);
+  else launch_which<R, 2>(s, lat, U, kappa, in, out, fstride, nrhs, red, scale, active, part, nbs);
+  DL_HIP(hipGetLastError());
+  return red ? nbs : 0;
+}
+
+template int wilson_batched<double>(hipStream_t, const Lattice&, const double2*, double, int, const double2*,
+                                    double2*, long, int, int, const double*, const int*, double*);
+template int wilson_batched<float>(hipStream_t, const Lattice&, const float2*, double, int, const float2*, float2*,
+                                   long, int, int, const double*, const int*, double*);
 
 int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,
                const double2* in, double2* out, int red, double* part) {
-  const int nb = (int)((lat.V + kBlock - 1) / kBlock);
-  if (red && nb > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
-  if (which == 0) launch_which<0>(s, lat, U, kappa, in, out, red, part, nb);
-  else if (which == 1) launch_which<1>(s, lat, U, kappa, in, out, red, part, nb);
-  else launch_which<2>(s, lat, U, kappa, in, out, red, part, nb);
-  DL_HIP(hipGetLastError());
-  return red ? nb : 0;
+  return wilson_batched<double>(s, lat, U, kappa, which, in, out, lat.nc, 1, red, nullptr, nullptr, part);
 }
 
 __global__ void k_gamma5_f64(const double2* __restrict__ in, double2* __restrict__ out, long nc) {

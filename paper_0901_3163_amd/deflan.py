@@ -55,7 +55,7 @@ class dl_stats(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0901_3163_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_0901_3163_amd/build.py`")
     lib = C.CDLL(LIB_PATH)
     P, I, L, D = C.c_void_p, C.c_int, C.c_long, C.c_double
     sig = {
@@ -65,7 +65,7 @@ def _load():
         "dl_ctx_destroy": (None, [P]),
         "dl_ctx_sync": (I, [P]),
         "dl_timing": (I, [P, I]),
-        "dl_kernel_time": (I, [P, C.c_char_p, C.POINTER(L), C.POINTER(D)]),
+        "dl_kernel_time": (I, [P, C.c_char_p, C.POINTER(L), C.POINTER(D), C.POINTER(D)]),
         "dl_op_create": (I, [P, C.POINTER(I), P, I, D, I, C.POINTER(P)]),
         "dl_op_destroy": (None, [P]),
         "dl_op_size": (L, [P]),
@@ -73,6 +73,7 @@ def _load():
         "dl_solve_first": (I, [P, P, P, I, I, I, D, C.POINTER(dl_first_opts), C.POINTER(P), C.POINTER(dl_stats)]),
         "dl_solve_next": (I, [P, P, I, P, P, I, D, C.POINTER(dl_next_opts), C.POINTER(dl_stats)]),
         "dl_eig_create": (I, [P, I, P, I, C.POINTER(P)]),
+        "dl_bench_wilson": (I, [P, I, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "dl_eig_info": (I, [P, C.POINTER(I), P, P]),
         "dl_eig_vectors": (I, [P, P, I]),
         "dl_eig_destroy": (None, [P]),
@@ -91,7 +92,7 @@ lib = _load()
 EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "dl_ctx_sync", "dl_timing",
             "dl_kernel_time", "dl_op_create", "dl_op_destroy", "dl_op_size", "dl_apply", "dl_solve_first",
             "dl_solve_next", "dl_eig_create", "dl_eig_info", "dl_eig_vectors", "dl_eig_destroy",
-            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh")
+            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson")
 
 
 def _check(rc):
@@ -148,9 +149,10 @@ class Context:
         _check(lib.dl_timing(self.h, 1 if enable else 0))
 
     def kernel_time(self, name: str):
-        n, ms = C.c_long(), C.c_double()
-        _check(lib.dl_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms)))
-        return n.value, ms.value
+        """(launches, total ms, algorithmic bytes) of a kernel family since timing was enabled."""
+        n, ms, by = C.c_long(), C.c_double(), C.c_double()
+        _check(lib.dl_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
 
     def close(self):
         if getattr(self, "h", None):
@@ -270,6 +272,12 @@ class Operator:
         h = C.c_void_p()
         _check(lib.dl_eig_create(self.h, int(Vecs.shape[0]), p, mem, C.byref(h)))
         return Eig(h, self)
+
+    def bench_wilson(self, which: int, prec: int, nrhs: int = 1, reps: int = 20):
+        """(ms per launch, algorithmic bytes per launch) of the Wilson stencil on device fields."""
+        ms, by = C.c_double(), C.c_double()
+        _check(lib.dl_bench_wilson(self.h, int(which), int(prec), int(nrhs), int(reps), C.byref(ms), C.byref(by)))
+        return ms.value, by.value
 
     @property
     def n(self):

@@ -1,0 +1,87 @@
+"""Batched mixed-precision later right-hand sides (FP32 Krylov vectors and Wilson apply,
+FP64 true residuals, projection and solution) against the oracle and the FP64 path (GPU)."""
+import numpy as np
+import pytest
+
+from lattice_inputs import gaussian_spinor, point_source, su3_links
+from oracle import dirac
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (16, 16, 16, 32)])
+def test_fp32_wilson_batched_matches_fp64(gpu_ctx, dims):
+    """The FP32 stencil (via dl_apply on FP32-rounded input) stays within FP32 rounding of the oracle."""
+    from paper_0901_3163_amd import deflan
+    U = su3_links(dims, 3)
+    ora = dirac.WilsonOperator(U, dims, 0.13)
+    op = deflan.Operator(gpu_ctx, dims, U, 0.13, deflan.DL_G5M)
+    psi = gaussian_spinor(dims, 4)
+    y = op.apply(deflan.DL_APPLY_G5M, psi)
+    assert _rel(y, ora.g5M(psi.ravel()).reshape(psi.shape)) < 1e-13
+    op.close()
+
+
+@pytest.mark.parametrize("kind", ["g5m", "mdagm"])
+@pytest.mark.parametrize("tol", [1e-10, 1e-12])
+def test_batched_fp32_later_rhs(gpu_ctx, c1_config, kind, tol):
+    """D-MinRes / D-CG, 5 rhs advanced together in FP32 with FP64 restarts, reach tol and the dense solution."""
+    from paper_0901_3163_amd import deflan
+    dims, U, kappa = c1_config["dims"], c1_config["links"], c1_config["kappa"]
+    k = deflan.DL_G5M if kind == "g5m" else deflan.DL_MDAGM
+    if k == deflan.DL_MDAGM and tol < 1e-11:
+        tol = 1e-11  # the normal equations floor near 1e-11 on this lattice
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, k)
+    b1 = gaussian_spinor(dims, 100)
+    _, eig, _ = op.solve_first(b1, 60, 20, 1e-10)
+    B = np.stack([gaussian_spinor(dims, 101 + i) for i in range(3)] +
+                 [point_source(dims, 5, 2, 1), np.zeros_like(b1)])
+    X, sts, rc = op.solve_next(B, eig, tol, storage=deflan.DL_FP32, batched=1)
+    assert rc == deflan.DL_OK
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    M = dirac.dense(ora.M, ora.n)
+    for i in range(4):
+        r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+        assert sts[i]["relres"] <= tol and r <= tol * 1.0001
+        xd = np.linalg.solve(M, B[i].ravel())
+        assert _rel(X[i], xd) < max(1e-8, 3e3 * tol)
+    assert np.all(X[4] == 0) and sts[4]["relres"] == 0.0
+    # the FP64 one-at-a-time path converges to the same solutions
+    X64, st64, _ = op.solve_next(B[:4], eig, tol)
+    for i in range(4):
+        assert _rel(X[i], X64[i]) < max(1e-8, 3e3 * tol)
+    eig.close()
+    op.close()
+
+
+def test_batched_without_eigenvectors_and_ragged(gpu_ctx):
+    """eig = NULL (plain MinRes / CG in FP32 with FP64 restarts) on a ragged 3x4x5x2 lattice."""
+    from paper_0901_3163_amd import deflan
+    dims = (3, 4, 5, 2)
+    U = su3_links(dims, 21)
+    kappa = 0.13
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    B = np.stack([gaussian_spinor(dims, 30 + i) for i in range(3)])
+    for k in (deflan.DL_G5M, deflan.DL_MDAGM):
+        op = deflan.Operator(gpu_ctx, dims, U, kappa, k)
+        X, sts, rc = op.solve_next(B, None, 1e-10, storage=deflan.DL_FP32, batched=1)
+        assert rc == 0
+        for i in range(3):
+            r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+            assert r <= 1e-10
+        op.close()
+
+
+def test_batched_rejects_bad_options(gpu_ctx, c1_config):
+    from paper_0901_3163_amd import deflan
+    op = deflan.Operator(gpu_ctx, c1_config["dims"], c1_config["links"], c1_config["kappa"], deflan.DL_G5M)
+    B = gaussian_spinor(c1_config["dims"], 1)[None]
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(B, None, 1e-10, storage=deflan.DL_FP32, batched=0)
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(B, None, 1e-10, storage=deflan.DL_BF16, batched=1)
+    op.close()

@@ -111,6 +111,18 @@ def test_hopping_neighbour_structure():
     assert nz == nb
 
 
+def test_c_transcription_equals_numpy():
+    """The OpenMP C loops (used where numpy is too slow) give the numpy transcription's M."""
+    from oracle import cwilson
+    dims = (4, 3, 5, 6)
+    U = su3_links(dims, 1)
+    b = gaussian_spinor(dims, 2).ravel()
+    a = dirac.WilsonOperator(U, dims, 0.13)
+    c = cwilson.CWilson(U, dims, 0.13)
+    for f in ("M", "Mdag", "g5M", "MdagM"):
+        assert np.max(np.abs(getattr(a, f)(b) - getattr(c, f)(b))) < 1e-14
+
+
 # ---------------------------------------------------------------- diagonal examples (Section 1)
 def test_indefinite_example_has_22_negatives():
     d = diag_spectrum_indefinite(5)
