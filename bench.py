@@ -88,13 +88,14 @@ def dslash_sweep(ctx, deflan, sizes, reps):
         torch.cuda.empty_cache()
         for prec, pname in ((deflan.DL_FP64, "fp64"), (deflan.DL_FP32, "fp32")):
             for nrhs in (1, 12):
+                variant, order, _ = op.tune_wilson(prec, nrhs, reps=5)  # the project's autotuner
                 op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, 2)  # warm-up
                 ms, by = op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, reps)
                 gbs = by / (ms * 1e-3) / 1e9
                 key = f"{'x'.join(map(str, dims))}/{pname}/nrhs{nrhs}"
                 out[key] = dict(bytes_per_launch=by, avg_us=round(ms * 1e3, 1), GBps=round(gbs, 1),
                                 frac=round(gbs / HBM_PEAK_GBS, 4), working_set_MB=round(by / 1e6, 1),
-                                cache_resident=by < 256e6)
+                                cache_resident=by < 256e6, tuned_variant=variant, tuned_order=order)
                 log(f"dslash {key}: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s")
         op.close()
         torch.cuda.empty_cache()

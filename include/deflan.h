@@ -188,6 +188,15 @@ int  dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B,
  * once).  Allocates and frees its own fields. */
 int  dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* avg_ms, double* bytes);
 
+/* Autotuner: time every launch shape of the Wilson stencil (threads per block,
+ * occupancy hint, block order) for this operator's lattice in precision `prec`
+ * with `nrhs` right-hand sides (reps event-timed launches each), keep the
+ * fastest for the process and append it to the tuning cache file
+ * ($DEFLAN_TUNE_CACHE, else $HOME/.cache/deflan/tune.txt).  Without an explicit
+ * call the library tunes on first use (DEFLAN_AUTOTUNE=0: default shape).
+ * variant / order / best_us (may be NULL) receive the choice and its time. */
+int  dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* order, double* best_us);
+
 /* ---- eigenvector handle ---------------------------------------------------- */
 /* Build a handle from k caller-supplied orthonormal vectors V ([k][V][4][3]);
  * H = V^H A V is formed with k MVPs in FP64. */

@@ -340,7 +340,7 @@ struct Batch {
   Batch(dl_op* o, int nrhs) : op(o), nr(nrhs), n(o->lat.nc), s(o->ctx->stream) {
     st.alloc((size_t)nr * NS);
     G = bgrid(n);
-    const size_t np = (size_t)nr * std::max(G, wilson_nbs(op->lat));
+    const size_t np = (size_t)nr * std::max(G, wilson_max_nbs(op->lat));
     part.alloc(np);
     part2.alloc(np);
     active.alloc(nr);
@@ -384,18 +384,20 @@ const float2* op_links32_public(dl_op* op) {
   return op->U32.get();
 }
 
-static void wilson32(dl_op* op, int which, const float2* in, float2* out, int nr, int nact, int red, double* part,
-                     const int* active, const double* scale = nullptr) {
+static int wilson32(dl_op* op, int which, const float2* in, float2* out, int nr, int nact, int red, double* part,
+                    const int* active, const double* scale = nullptr) {
+  const WilsonCfg cfg = wilson_cfg(op, DL_FP32, nr);
   // algorithmic bytes: links once per site (288 B FP32) + input and output spinor per active rhs (192 B)
   TimeScope ts(op->ctx, T_WILSON, (double)op->lat.V * (288.0 + 192.0 * nact));
-  wilson_batched<float>(op->ctx->stream, op->lat, op_links32(op), op->kappa, which, in, out, op->lat.nc, nr, red,
-                        scale, active, part);
+  return wilson_batched<float>(op->ctx->stream, op->lat, op_links32(op), op->kappa, which, in, out, op->lat.nc, nr,
+                               red, scale, active, part, cfg);
 }
 
 static void wilson64b(dl_op* op, int which, const double2* in, double2* out, int nr, int nact, const int* active) {
+  const WilsonCfg cfg = wilson_cfg(op, DL_FP64, nr);
   TimeScope ts(op->ctx, T_WILSON, (double)op->lat.V * (576.0 + 384.0 * nact));
   wilson_batched<double>(op->ctx->stream, op->lat, op->U.get(), op->kappa, which, in, out, op->lat.nc, nr, 0,
-                         nullptr, active, nullptr);
+                         nullptr, active, nullptr, cfg);
 }
 
 // r64 = b - M x64 for active rhs; refreshes st[B_RR], st[B_NRM], st[B_INV].
@@ -522,14 +524,13 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
     for (int r = 0; r < nr; ++r) target[r] = std::max(inner_drop * bt.get(r, B_NRM), 0.5 * tol * bnorm[r]);
     std::vector<int> inner_active = bt.h_active;
     const int G = bt.G;
-    const int nbs = wilson_nbs(op->lat);
     if (mr) {
       float2 *u = f[0].get(), *up = f[1].get(), *w = f[2].get(), *d1 = f[3].get(), *d2 = f[4].get(),
              *e = f[5].get();
       hipLaunchKernelGGL(k_b_minres_start, dim3(G, nr), dim3(kBlock), 0, s, n, R64.get(), u, up, d1, d2, e,
                          bt.st.get(), bt.invs.get(), bt.active.get());
       for (int it = 0; it < 100000; ++it) {
-        wilson32(op, 2, u, w, nr, bt.n_active(), 2, bt.part.get(), bt.active.get(), bt.invs.get());
+        const int nbs = wilson32(op, 2, u, w, nr, bt.n_active(), 2, bt.part.get(), bt.active.get(), bt.invs.get());
         hipLaunchKernelGGL(k_b_fin_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
                            bt.active.get());
         hipLaunchKernelGGL(k_b_lanczos3, dim3(G, nr), dim3(kBlock), 0, s, n, bt.st.get(), u, up, w,
@@ -567,7 +568,7 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
       float2 *r32 = f[0].get(), *sv = f[1].get(), *p = f[2].get(), *q = f[3].get(), *e = f[4].get();
       hipLaunchKernelGGL(k_b_cg_start, dim3(G, nr), dim3(kBlock), 0, s, n, R64.get(), r32, e, bt.st.get(),
                          bt.active.get());
-      wilson32(op, 1, r32, sv, nr, bt.n_active(), 1, bt.part.get(), bt.active.get());
+      const int nbs = wilson32(op, 1, r32, sv, nr, bt.n_active(), 1, bt.part.get(), bt.active.get());
       hipLaunchKernelGGL(k_b_fin_store, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(), (int)B_SS);
       hipLaunchKernelGGL(k_b_copy_f32, dim3(G, nr), dim3(kBlock), 0, s, n, sv, p, bt.active.get());
       for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];

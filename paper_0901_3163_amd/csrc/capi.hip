@@ -334,6 +334,7 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
     hipStream_t s = op->ctx->stream;
     const Lattice& lat = op->lat;
     const long n = (long)nrhs * lat.nc;
+    const WilsonCfg cfg = wilson_cfg(op, prec, nrhs);
     hipEvent_t a, b;
     DL_HIP(hipEventCreate(&a));
     DL_HIP(hipEventCreate(&b));
@@ -343,11 +344,11 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
       DBuf<double2> in(n), out(n);
       zero(s, n, in.get());
       wilson_batched<double>(s, lat, op->U.get(), op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr,
-                             nullptr, nullptr);
+                             nullptr, nullptr, cfg);
       DL_HIP(hipEventRecord(a, s));
       for (int i = 0; i < reps; ++i)
         wilson_batched<double>(s, lat, op->U.get(), op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0,
-                               nullptr, nullptr, nullptr);
+                               nullptr, nullptr, nullptr, cfg);
       DL_HIP(hipEventRecord(b, s));
       DL_HIP(hipEventSynchronize(b));
       bb = (double)lat.V * (576.0 + 384.0 * nrhs);
@@ -356,11 +357,11 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
       zero(s, n / 2, reinterpret_cast<double2*>(in.get()));  // n float2 = n/2 double2 (nc is even)
       const float2* U32 = op_links32_public(op);
       wilson_batched<float>(s, lat, U32, op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr, nullptr,
-                            nullptr);
+                            nullptr, cfg);
       DL_HIP(hipEventRecord(a, s));
       for (int i = 0; i < reps; ++i)
         wilson_batched<float>(s, lat, U32, op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr,
-                              nullptr, nullptr);
+                              nullptr, nullptr, cfg);
       DL_HIP(hipEventRecord(b, s));
       DL_HIP(hipEventSynchronize(b));
       bb = (double)lat.V * (288.0 + 192.0 * nrhs);
@@ -370,6 +371,21 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
     (void)hipEventDestroy(b);
     *avg_ms = ms / reps;
     if (bytes) *bytes = bb;
+    return DL_OK;
+  });
+}
+
+int dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* order, double* best_us) {
+  return guard([&] {
+    need(op != nullptr, "op is NULL");
+    need(prec == DL_FP64 || prec == DL_FP32, "prec must be DL_FP64 or DL_FP32");
+    need(nrhs >= 1 && nrhs <= 256 && reps >= 1, "need 1 <= nrhs <= 256 and reps >= 1");
+    use_device(op->ctx);
+    double us = 0.0;
+    const WilsonCfg c = tune_wilson(op, prec, nrhs, reps, &us);
+    if (variant) *variant = c.variant;
+    if (order) *order = c.order;
+    if (best_us) *best_us = us;
     return DL_OK;
   });
 }

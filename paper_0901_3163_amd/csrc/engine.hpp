@@ -1,5 +1,7 @@
 // Operator, eigenvector-handle and solver declarations of libdeflan.
 #pragma once
+#include <map>
+
 #include "internal.hpp"
 
 struct dl_op {
@@ -10,6 +12,7 @@ struct dl_op {
   dl::DBuf<double2> U;          // FP64 links, tiled
   dl::DBuf<float2> U32;         // FP32 links, tiled (made on first use)
   uint64_t fingerprint = 0;     // dims, kappa, kind and a hash of the links
+  std::map<int, dl::WilsonCfg> wcfg;  // tuned stencil launch shape per (precision, batch size)
 };
 
 struct dl_eig {
@@ -42,8 +45,14 @@ struct Scratch {
 // out = A in for the operator's Hermitian form (tmp: one field for M^dag M).
 // Returns MVPs used.
 int apply_A(dl_op* op, const double2* in, double2* out, double2* tmp);
-// out = M in (which: 0 M, 1 M^dag, 2 gamma5 M), timed as "wilson".
-void apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red = 0, double* part = nullptr);
+// out = M in (which: 0 M, 1 M^dag, 2 gamma5 M), timed as "wilson"; returns the partial count
+// per rhs of a fused reduction (0 if red == 0).
+int apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red = 0, double* part = nullptr);
+
+// Stencil launch shape for (precision, batch size): the tuned choice (tuning on first use
+// unless DEFLAN_AUTOTUNE=0), and the explicit tuner.
+WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs);
+WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us);
 
 int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double tol, const dl_first_opts& o,
                 dl_eig** eig_out, dl_stats* st);

@@ -135,19 +135,29 @@ void pack_spinor(hipStream_t s, const Lattice& lat, const double2* host_layout, 
 void unpack_spinor(hipStream_t s, const Lattice& lat, const double2* tiled, double2* host_layout, int nfield);
 void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, double2* tiled);
 
-// ---- launchers: Wilson operator (FP64) -------------------------------------
+// ---- launchers: Wilson operator ------------------------------------------------
+// Launch shape of the stencil: variant = (threads per block, occupancy hint) among
+// {(256,2), (128,2), (512,1), (256,1)}; order = block order (0: rhs fastest, XCD-contiguous;
+// 1: sites fastest, XCD-contiguous; 2: rhs fastest, hardware order).  Chosen by the autotuner.
+constexpr int kWilsonVariants = 4;
+constexpr int kWilsonOrders = 3;
+struct WilsonCfg {
+  int variant = 0;
+  int order = 0;
+};
 // which: 0 M, 1 M^dag, 2 gamma5 M.  red: 0 none, 1 ||out||^2 partials, 2 Re<in,out> partials.
-// Returns the number of partials written to `part` (0 if red == 0).
+// Returns the number of partials per rhs written to `part` (0 if red == 0).
 int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,
-               const double2* in, double2* out, int red, double* part);
+               const double2* in, double2* out, int red, double* part, WilsonCfg cfg = WilsonCfg());
 void gamma5_f64(hipStream_t s, const Lattice& lat, const double2* in, double2* out);
 // Batched Wilson apply in FP64 (R = double) or FP32 (R = float): nrhs fields at stride fstride.
 // Partials (red != 0) are column-major [nrhs][wilson_nbs(lat)].  Returns wilson_nbs(lat) or 0.
-int wilson_nbs(const Lattice& lat);
+int wilson_nbs(const Lattice& lat, const WilsonCfg& cfg);
+int wilson_max_nbs(const Lattice& lat);  // partials per rhs of the widest-grid variant
 template <class R>
 int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,
                    const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int red, const double* scale,
-                   const int* active, double* part);
+                   const int* active, double* part, WilsonCfg cfg = WilsonCfg());
 
 // ---- launchers: BLAS-1 ------------------------------------------------------
 int nblocks_for(long n);  // partial count used by the streaming reductions for length n

@@ -251,10 +251,11 @@ static int grid_for(long n) {
 }
 
 // ---- helpers -------------------------------------------------------------------
-void apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red, double* part) {
+int apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red, double* part) {
+  const WilsonCfg cfg = wilson_cfg(op, DL_FP64, 1);
   // algorithmic bytes: input spinor, links and output spinor moved once (FP64: 960 B/site)
   TimeScope ts(op->ctx, T_WILSON, 960.0 * (double)op->lat.V);
-  wilson_f64(op->ctx->stream, op->lat, op->U.get(), op->kappa, which, in, out, red, part);
+  return wilson_f64(op->ctx->stream, op->lat, op->U.get(), op->kappa, which, in, out, red, part, cfg);
 }
 
 int apply_A(dl_op* op, const double2* in, double2* out, double2* tmp) {
@@ -352,9 +353,8 @@ static InnerResult minres_run(dl_op* op, const double2* b, double2* x, double bn
   h[M_ETA] = beta1;
   write_scalars(op->ctx, S.sc.get(), S_COUNT, h);
   while (res.mvp < max_mvp) {
-    apply_wilson(op, 2, v, w, 2, S.part.get());
+    const int nbw = apply_wilson(op, 2, v, w, 2, S.part.get());
     res.mvp += 1;
-    const int nbw = (int)((op->lat.V + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_fin_store, dim3(1), dim3(kBlock), 0, s, S.part.get(), nbw, S.sc.get(), (int)M_ALPHA);
     hipLaunchKernelGGL(k_lanczos3, dim3(nb), dim3(kBlock), 0, s, n, S.sc.get(), v, vp, w, S.part.get());
     hipLaunchKernelGGL(k_fin_minres_rot, dim3(1), dim3(kBlock), 0, s, S.part.get(), nb, S.sc.get());
@@ -384,11 +384,10 @@ static InnerResult cgls_run(dl_op* op, const double2* b, double2* x, double bnor
   double2 *r = w6[0].get(), *sv = w6[1].get(), *p = w6[2].get(), *q = w6[3].get();
   InnerResult res;
   const int nb = nblocks_for(n);
-  const int nbw = (int)((op->lat.V + kBlock - 1) / kBlock);
   apply_wilson(op, 0, x, q);
   hipLaunchKernelGGL(k_resid, dim3(nb), dim3(kBlock), 0, s, n, b, q, r, S.part.get());
   hipLaunchKernelGGL(k_fin_store, dim3(1), dim3(kBlock), 0, s, S.part.get(), nb, S.sc.get(), (int)S_RN2);
-  apply_wilson(op, 1, r, sv, 1, S.part.get());
+  const int nbw = apply_wilson(op, 1, r, sv, 1, S.part.get());
   hipLaunchKernelGGL(k_fin_store, dim3(1), dim3(kBlock), 0, s, S.part.get(), nbw, S.sc.get(), (int)S_SS);
   copy(s, n, sv, p);
   res.mvp += 2;

@@ -1,0 +1,179 @@
+// Autotuner for the Wilson stencil's launch shape.
+//
+// For one (device architecture, lattice extents, precision, batch size) the
+// tuner times every (variant, block order) candidate with HIP events on the
+// context's stream -- a warm-up launch, then `reps` back-to-back launches on
+// device fields -- and keeps the fastest.  Choices live in a process-wide
+// table (so every operator of a process makes the same choice and results are
+// reproducible within a run) and in a text cache file, one line per key:
+//
+//     <arch> <Lx>x<Ly>x<Lz>x<Lt> <prec> <nrhs> <variant> <order> <us>
+//
+// The file is $DEFLAN_TUNE_CACHE, else $HOME/.cache/deflan/tune.txt.
+// DEFLAN_AUTOTUNE=0 disables tuning (the default shape is used).
+#include "engine.hpp"
+
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <sys/stat.h>
+
+namespace dl {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, std::pair<WilsonCfg, double>> g_table;
+bool g_loaded = false;
+
+std::string cache_path() {
+  const char* e = std::getenv("DEFLAN_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h && *h ? h : "/tmp") + "/.cache/deflan/tune.txt";
+}
+
+bool autotune_enabled() {
+  const char* e = std::getenv("DEFLAN_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+std::string arch_name(int device) {
+  static std::map<int, std::string> names;  // guarded by g_mu's callers or first use
+  auto it = names.find(device);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t p;
+  std::string a = "unknown";
+  if (hipGetDeviceProperties(&p, device) == hipSuccess) {
+    a = p.gcnArchName;
+    const size_t c = a.find(':');
+    if (c != std::string::npos) a = a.substr(0, c);
+  }
+  names[device] = a;
+  return a;
+}
+
+std::string make_key(const std::string& arch, const Lattice& lat, int prec, int nrhs) {
+  std::ostringstream os;
+  os << arch << ' ' << lat.L[0] << 'x' << lat.L[1] << 'x' << lat.L[2] << 'x' << lat.L[3] << ' ' << prec << ' ' << nrhs;
+  return os.str();
+}
+
+void load_cache() {
+  if (g_loaded) return;
+  g_loaded = true;
+  std::ifstream in(cache_path());
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream is(line);
+    std::string arch, dims;
+    int prec, nrhs, v, o;
+    double us;
+    if (!(is >> arch >> dims >> prec >> nrhs >> v >> o >> us)) continue;
+    if (v < 0 || v >= kWilsonVariants || o < 0 || o >= kWilsonOrders) continue;
+    std::ostringstream k;
+    k << arch << ' ' << dims << ' ' << prec << ' ' << nrhs;
+    g_table[k.str()] = {WilsonCfg{v, o}, us};
+  }
+}
+
+void append_cache(const std::string& key, const WilsonCfg& c, double us) {
+  const std::string path = cache_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    // create the directory chain (best effort; an unwritable cache only costs re-tuning)
+    std::string dir = path.substr(0, slash);
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  std::ofstream out(path, std::ios::app);
+  if (out) out << key << ' ' << c.variant << ' ' << c.order << ' ' << us << '\n';
+}
+
+template <class R>
+double time_cfg(dl_op* op, const cplx_t<R>* U, const cplx_t<R>* in, cplx_t<R>* out, int nrhs, WilsonCfg c, int reps,
+                hipEvent_t a, hipEvent_t b) {
+  hipStream_t s = op->ctx->stream;
+  wilson_batched<R>(s, op->lat, U, op->kappa, 2, in, out, op->lat.nc, nrhs, 0, nullptr, nullptr, nullptr, c);
+  DL_HIP(hipEventRecord(a, s));
+  for (int i = 0; i < reps; ++i)
+    wilson_batched<R>(s, op->lat, U, op->kappa, 2, in, out, op->lat.nc, nrhs, 0, nullptr, nullptr, nullptr, c);
+  DL_HIP(hipEventRecord(b, s));
+  DL_HIP(hipEventSynchronize(b));
+  float ms = 0.f;
+  DL_HIP(hipEventElapsedTime(&ms, a, b));
+  return 1e3 * ms / reps;
+}
+
+}  // namespace
+
+WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) {
+  op->wcfg.erase(prec * 100000 + nrhs);
+  const Lattice& lat = op->lat;
+  const long n = (long)nrhs * lat.nc;
+  hipEvent_t a, b;
+  DL_HIP(hipEventCreate(&a));
+  DL_HIP(hipEventCreate(&b));
+  WilsonCfg best;
+  double best_t = 1e300;
+  DBuf<double2> in, out;  // FP64: n double2 each; FP32 uses the first half as float2
+  in.alloc(prec == DL_FP64 ? n : (n + 1) / 2);
+  out.alloc(prec == DL_FP64 ? n : (n + 1) / 2);
+  zero(op->ctx->stream, (long)in.n, in.get());
+  for (int v = 0; v < kWilsonVariants; ++v)
+    for (int o = 0; o < kWilsonOrders; ++o) {
+      if (nrhs == 1 && o == 1) continue;  // identical to order 0 for one rhs
+      const WilsonCfg c{v, o};
+      double t;
+      if (prec == DL_FP64)
+        t = time_cfg<double>(op, op->U.get(), in.get(), out.get(), nrhs, c, reps, a, b);
+      else
+        t = time_cfg<float>(op, op_links32_public(op), reinterpret_cast<float2*>(in.get()),
+                            reinterpret_cast<float2*>(out.get()), nrhs, c, reps, a, b);
+      if (verbose()) {
+        std::fprintf(stderr, "[deflan] tune %s nrhs %d variant %d order %d: %.1f us\n",
+                     prec == DL_FP64 ? "fp64" : "fp32", nrhs, v, o, t);
+        std::fflush(stderr);
+      }
+      if (t < best_t) {
+        best_t = t;
+        best = c;
+      }
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (best_us) *best_us = best_t;
+  op->wcfg[prec * 100000 + nrhs] = best;
+  std::lock_guard<std::mutex> g(g_mu);
+  const std::string key = make_key(arch_name(op->ctx->device), lat, prec, nrhs);
+  g_table[key] = {best, best_t};
+  append_cache(key, best, best_t);
+  return best;
+}
+
+WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs) {
+  const int okey = prec * 100000 + nrhs;
+  auto oc = op->wcfg.find(okey);
+  if (oc != op->wcfg.end()) return oc->second;
+  const std::string key = make_key(arch_name(op->ctx->device), op->lat, prec, nrhs);
+  WilsonCfg c;
+  bool found = false;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    load_cache();
+    auto it = g_table.find(key);
+    if (it != g_table.end()) {
+      c = it->second.first;
+      found = true;
+    }
+  }
+  if (!found && autotune_enabled()) c = tune_wilson(op, prec, nrhs, 10, nullptr);
+  op->wcfg[okey] = c;
+  return c;
+}
+
+}  // namespace dl

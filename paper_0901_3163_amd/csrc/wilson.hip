@@ -138,19 +138,23 @@ __device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int
 // WHICH: 0 M, 1 M^dag, 2 gamma5 M.  RED: 0 none, 1 ||out||^2, 2 Re<in, out> (partials in FP64,
 // column-major [nrhs][nbs]).  scale (optional, per rhs): out = scale * op(in).
 // active (optional, per rhs): blocks of inactive right-hand sides return at once.
-template <class R, int WHICH, int RED>
-__global__ void __launch_bounds__(kBlock, 2)
+// Launch shape: NT threads per block, OCC the occupancy hint (waves per SIMD the
+// register budget must allow); ORDER 0: rhs fastest, XCD-contiguous blocks; 1: sites
+// fastest, XCD-contiguous; 2: rhs fastest, hardware block order.
+template <class R, int WHICH, int RED, int NT, int OCC>
+__global__ void __launch_bounds__(NT, OCC)
 k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
          typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
-         int Lt, long V, long Vpad, int nbs, const double* __restrict__ scale, const int* __restrict__ active,
-         double* __restrict__ part) {
+         int Lt, long V, long Vpad, int nbs, int order, const double* __restrict__ scale,
+         const int* __restrict__ active, double* __restrict__ part) {
   using C = typename CT<R>::type;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int rhs = lb % nrhs, sb = lb / nrhs;
+  const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int rhs = order == 1 ? lb / nbs : lb % nrhs;
+  const int sb = order == 1 ? lb % nbs : lb / nrhs;
   if (active && !active[rhs]) return;
   in += rhs * fstride;
   out += rhs * fstride;
-  const int site = sb * kBlock + (int)threadIdx.x;
+  const int site = sb * NT + (int)threadIdx.x;
   double red = 0.0;
   if (site >= V && site < Vpad) {
     // padding sites of the last tile are kept at zero
@@ -164,7 +168,7 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
     const int z = (site / (Lx * Ly)) % Lz;
     const int t = site / (Lx * Ly * Lz);
     const int sy = Lx, sz = Lx * Ly, st = Lx * Ly * Lz;
-    // neighbour offsets per direction: forward d_f[mu], backward d_b[mu]
+    // neighbour offsets per direction
     const int fx = x == Lx - 1 ? 1 - Lx : 1, bx = x == 0 ? Lx - 1 : -1;
     const int fy = y == Ly - 1 ? (1 - Ly) * sy : sy, by = y == 0 ? (Ly - 1) * sy : -sy;
     const int fz = z == Lz - 1 ? (1 - Lz) * sz : sz, bz = z == 0 ? (Lz - 1) * sz : -sz;
@@ -173,6 +177,8 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = CT<R>::make(0, 0);
     constexpr int SF = (WHICH == 1) ? 1 : -1;  // forward projector 1 + SF g_mu, backward 1 - SF g_mu
+    // A runtime loop over the four directions (loads depend on mu) keeps the
+    // compiler from hoisting all 168 neighbour/link loads ahead of the arithmetic.
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
       const int df = mu == 0 ? fx : mu == 1 ? fy : mu == 2 ? fz : ft;
@@ -195,54 +201,69 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
     }
   }
   if (RED != 0) {
-    __shared__ double lds[kBlock / 64];
-    const double s = block_sum<kBlock>(red, lds);
+    __shared__ double lds[NT / 64];
+    const double s = block_sum<NT>(red, lds);
     if (threadIdx.x == 0) part[(long)rhs * nbs + sb] = s;
   }
 }
 
-template <class R, int WHICH>
-static void launch_which(hipStream_t s, const Lattice& lat, const typename CT<R>::type* U, double kappa,
-                         const typename CT<R>::type* in, typename CT<R>::type* out, long fstride, int nrhs,
-                         int red, const double* scale, const int* active, double* part, int nbs) {
-  const dim3 grid(nbs * nrhs), block(kBlock);
+// Launch-shape variants: (threads per block, occupancy hint).
+static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256};
+
+template <class R, int WHICH, int RED, int NT, int OCC>
+static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
+                       cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+                       double* part, int nbs) {
   const int* L = lat.L;
-  const long Vpad = lat.ntiles * kTile;
-  if (red == 0)
-    hipLaunchKernelGGL((k_wilson<R, WHICH, 0>), grid, block, 0, s, U, in, out, fstride, nrhs, kappa, L[0], L[1],
-                       L[2], L[3], lat.V, Vpad, nbs, scale, active, part);
-  else if (red == 1)
-    hipLaunchKernelGGL((k_wilson<R, WHICH, 1>), grid, block, 0, s, U, in, out, fstride, nrhs, kappa, L[0], L[1],
-                       L[2], L[3], lat.V, Vpad, nbs, scale, active, part);
-  else
-    hipLaunchKernelGGL((k_wilson<R, WHICH, 2>), grid, block, 0, s, U, in, out, fstride, nrhs, kappa, L[0], L[1],
-                       L[2], L[3], lat.V, Vpad, nbs, scale, active, part);
+  hipLaunchKernelGGL((k_wilson<R, WHICH, RED, NT, OCC>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
+                     kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, nbs, order, scale, active, part);
 }
 
-int wilson_nbs(const Lattice& lat) { return (int)((lat.V + kBlock - 1) / kBlock); }
+template <class R, int WHICH, int RED>
+static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa,
+                           const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int order,
+                           const double* scale, const int* active, double* part, int nbs) {
+  switch (variant) {
+    case 1: launch_one<R, WHICH, RED, 128, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    case 2: launch_one<R, WHICH, RED, 512, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    case 3: launch_one<R, WHICH, RED, 256, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    default: launch_one<R, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+  }
+}
+
+int wilson_nbs(const Lattice& lat, const WilsonCfg& cfg) {
+  const int nt = kVariantNT[cfg.variant % kWilsonVariants];
+  return (int)((lat.V + nt - 1) / nt);
+}
+
+int wilson_max_nbs(const Lattice& lat) { return (int)((lat.V + 127) / 128); }
 
 template <class R>
 int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,
                    const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int red, const double* scale,
-                   const int* active, double* part) {
-  const int nbs = wilson_nbs(lat);
+                   const int* active, double* part, WilsonCfg cfg) {
+  const int v = cfg.variant % kWilsonVariants;
+  const int nbs = wilson_nbs(lat, cfg);
   if (red && nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
   if ((long)nbs * nrhs > 2147483647L) fail(DL_E_INVALID, "grid too large");
-  if (which == 0) launch_which<R, 0>(s, lat, U, kappa, in, out, fstride, nrhs, red, scale, active, part, nbs);
-  else if (which == 1) launch_which<R, 1>(s, lat, U, kappa, in, out, fstride, nrhs, red, scale, active, part, nbs);
-  else launch_which<R, 2>(s, lat, U, kappa, in, out, fstride, nrhs, red, scale, active, part, nbs);
+  const int o = cfg.order;
+#define DL_W(WH, RD) launch_variant<R, WH, RD>(v, s, lat, U, kappa, in, out, fstride, nrhs, o, scale, active, part, nbs)
+  if (which == 0) { if (red == 0) DL_W(0, 0); else if (red == 1) DL_W(0, 1); else DL_W(0, 2); }
+  else if (which == 1) { if (red == 0) DL_W(1, 0); else if (red == 1) DL_W(1, 1); else DL_W(1, 2); }
+  else { if (red == 0) DL_W(2, 0); else if (red == 1) DL_W(2, 1); else DL_W(2, 2); }
+#undef DL_W
   DL_HIP(hipGetLastError());
   return red ? nbs : 0;
 }
 
 template int wilson_batched<double>(hipStream_t, const Lattice&, const double2*, double, int, const double2*,
-                                    double2*, long, int, int, const double*, const int*, double*);
+                                    double2*, long, int, int, const double*, const int*, double*, WilsonCfg);
 template int wilson_batched<float>(hipStream_t, const Lattice&, const float2*, double, int, const float2*, float2*,
-                                   long, int, int, const double*, const int*, double*);
+                                   long, int, int, const double*, const int*, double*, WilsonCfg);
 
 int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,
-               const double2* in, double2* out, int red, double* part) {
-  return wilson_batched<double>(s, lat, U, kappa, which, in, out, lat.nc, 1, red, nullptr, nullptr, part);
+               const double2* in, double2* out, int red, double* part, WilsonCfg cfg) {
+  return wilson_batched<double>(s, lat, U, kappa, which, in, out, lat.nc, 1, red, nullptr, nullptr, part, cfg);
 }
 
 __global__ void k_gamma5_f64(const double2* __restrict__ in, double2* __restrict__ out, long nc) {

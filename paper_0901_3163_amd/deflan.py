@@ -74,6 +74,7 @@ def _load():
         "dl_solve_next": (I, [P, P, I, P, P, I, D, C.POINTER(dl_next_opts), C.POINTER(dl_stats)]),
         "dl_eig_create": (I, [P, I, P, I, C.POINTER(P)]),
         "dl_bench_wilson": (I, [P, I, I, I, I, C.POINTER(D), C.POINTER(D)]),
+        "dl_tune_wilson": (I, [P, I, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
         "dl_eig_info": (I, [P, C.POINTER(I), P, P]),
         "dl_eig_vectors": (I, [P, P, I]),
         "dl_eig_destroy": (None, [P]),
@@ -92,7 +93,7 @@ lib = _load()
 EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "dl_ctx_sync", "dl_timing",
             "dl_kernel_time", "dl_op_create", "dl_op_destroy", "dl_op_size", "dl_apply", "dl_solve_first",
             "dl_solve_next", "dl_eig_create", "dl_eig_info", "dl_eig_vectors", "dl_eig_destroy",
-            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson")
+            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson")
 
 
 def _check(rc):
@@ -278,6 +279,12 @@ class Operator:
         ms, by = C.c_double(), C.c_double()
         _check(lib.dl_bench_wilson(self.h, int(which), int(prec), int(nrhs), int(reps), C.byref(ms), C.byref(by)))
         return ms.value, by.value
+
+    def tune_wilson(self, prec: int, nrhs: int = 1, reps: int = 10):
+        """Run the stencil autotuner; returns (variant, order, best microseconds)."""
+        v, o, us = C.c_int(), C.c_int(), C.c_double()
+        _check(lib.dl_tune_wilson(self.h, int(prec), int(nrhs), int(reps), C.byref(v), C.byref(o), C.byref(us)))
+        return v.value, o.value, us.value
 
     @property
     def n(self):
