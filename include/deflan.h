@@ -83,6 +83,7 @@ extern "C" {
 typedef struct dl_ctx dl_ctx;
 typedef struct dl_op  dl_op;
 typedef struct dl_eig dl_eig;
+typedef struct dl_net dl_net;
 
 /* Options for the first right-hand side.  Pass NULL for the defaults. */
 typedef struct {
@@ -102,6 +103,10 @@ typedef struct {
                                the multi-rhs kernels (links read once per site for all rhs) */
   int    x0_given;          /* 1: X holds initial guesses on entry (default 0: x0 = 0) */
   long   max_mvp;           /* per-rhs MVP cap; default 1000000 */
+  dl_net* net;              /* learned initial guess (batched path only; NULL = projection only):
+                               x0 = net(b), then the Galerkin projection; per rhs the library keeps
+                               whichever of that and the projection-only start has the smaller
+                               true residual ||b - M x0|| (costs one extra projection per rhs) */
 } dl_next_opts;
 
 /* Per-solve statistics. */
@@ -109,7 +114,7 @@ typedef struct {
   int    status;            /* DL_OK or DL_NOT_CONVERGED */
   int    stop_rule;         /* DL_STOP_* (solve_first) */
   int    cycles;            /* restart cycles (solve_first) */
-  int    reserved;
+  int    guess;             /* solve_next with a network: 1 if the learned start was kept */
   long   mvp;               /* applications of M or M^dag (M^dag M counts 2; gamma5 is free) */
   long   mvp_lin;           /* MVPs when the linear system first met tol (solve_first) */
   long   iters;             /* Krylov iterations */
@@ -206,6 +211,40 @@ int  dl_eig_info(const dl_eig* eig, int* k, double* evals, double* resid);
 /* Copy the k eigenvectors out ([k][V][4][3] complex128). */
 int  dl_eig_vectors(const dl_eig* eig, double* V, int mem);
 void dl_eig_destroy(dl_eig* eig);
+
+/* ---- learned initial guess ---------------------------------------------------
+ * Not part of the paper's method: an optional starting vector for the later
+ * right-hand sides, refined by the paper's Galerkin projection (Section 2) and
+ * Krylov solve.  A gauge-covariant parallel-transport convolution network in FP32:
+ * features are colour triplets per site and channel (the spinor b is 4 channels,
+ * one per spin); layer l maps
+ *     out[o](x) = sum_h sum_i W_h[o][i] (T_h in[i])(x),
+ * h over {0, +x, -x, +y, -y, +z, -z, +t, -t}, T_0 = 1, (T_{+mu} a)(x) = U_mu(x) a(x+mu),
+ * (T_{-mu} a)(x) = U_mu(x-mu)^dag a(x-mu); widths 4 -> 16 -> 16 -> 4 with
+ * f(z) = z / sqrt(1 + |z|^2) (colour norm per site and channel) after layers 1 and 2.
+ * net(b) = s N(b / s) with s = ||b|| / sqrt(V).
+ * Weights: complex128 interleaved, layers concatenated, each [9 hops][C_out][C_in]
+ * in the hop order above; dl_net_num_weights() complex numbers in all.
+ * A network belongs to one context; its scratch grows to the largest batch used. */
+int  dl_net_num_weights(void);
+/* Create a network with the given weights (host, rounded to FP32). */
+int  dl_net_create(dl_ctx* ctx, const double* weights, dl_net** out);
+/* Copy the current weights out (host, complex128). */
+int  dl_net_get_weights(const dl_net* net, double* weights);
+/* Replace the weights (host) and reset the optimiser state. */
+int  dl_net_set_weights(dl_net* net, const double* weights);
+void dl_net_destroy(dl_net* net);
+/* Y = net(B) for nrhs fields B ([nrhs][V][4][3] complex128) on op's lattice and links. */
+int  dl_net_apply(dl_net* net, dl_op* op, int nrhs, const double* B, double* Y, int mem);
+/* loss = (1/n) sum_j ||M (net(b_j) - x_j)||^2 / ||b_j||^2 over n pairs (B, X), with M in FP32;
+ * grad (host complex128, may be NULL) = dloss/dRe W + i dloss/dIm W.  b_j = 0 is invalid. */
+int  dl_net_loss_grad(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem,
+                      double* loss, double* grad);
+/* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the same loss; step s uses
+ * the pairs [g*batch, (g+1)*batch) with g = s mod (n / batch).  losses ([steps], host, may
+ * be NULL) receives each step's minibatch loss before the update.  1 <= batch <= n. */
+int  dl_net_train(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem,
+                  int batch, int steps, double lr, double* losses);
 
 /* ---- kernel-level entry points (used by the parity tests) --------------- */
 /* c = V^H w for nv vectors V ([nv][N]) and one vector w ([N]); c: nv complex.

@@ -15,6 +15,7 @@
 // correction e with A e = gamma5 r64 (MinRes) or M e = r64 (CG on the normal
 // equations), and x64 += e closes each cycle.
 #include "engine.hpp"
+#include "ptc.hpp"
 #include "cplx.hpp"
 #include "small.hpp"
 #include "tsk.hpp"
@@ -488,18 +489,54 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
   }
   if (!o.x0_given) zero(s, (long)nr * n, X);
   bt.push_active();
+  // FP64 true residual, projection, FP64 true residual again (X in place, R: its residual)
+  auto start = [&](double2* Xs, double2* Rs) {
+    true_residual(bt, B, Xs, Rs, T64.get());
+    for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
+    project_batch(bt, eig, Rs, Xs, T64.get(), cbuf, S);
+    if (eig && eig->k > 0) {
+      for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r] * (mr ? 0 : 1);
+      true_residual(bt, B, Xs, Rs, T64.get());
+      for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
+    }
+  };
+  std::vector<int> used_net(nr, 0);
+  bool started = false;
+  if (o.net && bt.n_active() > 0) {
+    // Learned initial guess: start from net(b) + projection or from the projection alone,
+    // whichever has the smaller FP64 true residual.
+    dl_net* net = o.net;
+    if (net->ctx != op->ctx) fail(DL_E_INVALID, "network and operator belong to different contexts");
+    start(X, R64.get());
+    bt.pull_state();
+    std::vector<double> rp(nr);
+    for (int r = 0; r < nr; ++r) rp[r] = bt.get(r, B_NRM);
+    DBuf<double2> XN((size_t)nr * n), RN((size_t)nr * n);
+    net_apply(net, op, nr, B, XN.get());
+    start(XN.get(), RN.get());
+    bt.pull_state();
+    for (int r = 0; r < nr; ++r) {
+      if (!bt.h_active[r]) continue;
+      if (bt.get(r, B_NRM) < rp[r]) {
+        used_net[r] = 1;
+        copy(s, n, XN.get() + (long)r * n, X + (long)r * n);
+      }
+    }
+    // residual state of the chosen starts
+    true_residual(bt, B, X, R64.get(), T64.get());
+    for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
+    started = true;
+    if (verbose()) {
+      int cnt = 0;
+      for (int r = 0; r < nr; ++r) cnt += used_net[r];
+      std::fprintf(stderr, "[deflan] learned guess kept for %d/%d rhs (%.2fs)\n", cnt, nr, now_s() - t0);
+      std::fflush(stderr);
+    }
+  }
   const double inner_drop = 1e-4;      // reduction of the inner residual estimate per cycle
   const int check = 8;
   for (int cycle = 0; cycle < 40 && bt.n_active() > 0; ++cycle) {
-    // FP64 true residual, projection, FP64 true residual again
-    true_residual(bt, B, X, R64.get(), T64.get());
-    for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
-    project_batch(bt, eig, R64.get(), X, T64.get(), cbuf, S);
-    if (eig && eig->k > 0) {
-      for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r] * (mr ? 0 : 1);
-      true_residual(bt, B, X, R64.get(), T64.get());
-      for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
-    }
+    if (!(cycle == 0 && started)) start(X, R64.get());
     bt.pull_state();
     for (int r = 0; r < nr; ++r) {
       if (!bt.h_active[r]) continue;
@@ -623,6 +660,7 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
     one.status = one.relres <= tol ? DL_OK : DL_NOT_CONVERGED;
     one.iters = iters[r];
     one.mvp = mvp[r] + (bnorm[r] == 0.0 ? 0 : 1);
+    one.guess = used_net[r];
     one.time_s = t1 - t0;
     if (one.status != DL_OK) worst = DL_NOT_CONVERGED;
     if (st) st[r] = one;

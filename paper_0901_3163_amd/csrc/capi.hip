@@ -4,13 +4,16 @@
 // interleaved complex128 layout and the device's tiled site-major layout, runs
 // the solver on the context's stream and maps C++ errors to DL_* status codes.
 #include "engine.hpp"
+#include "ptc.hpp"
 #include "small.hpp"
 #include "tsk.hpp"
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <exception>
 #include <new>
+#include <vector>
 
 namespace dl {
 const std::string& last_error();
@@ -110,8 +113,36 @@ dl_next_opts next_defaults(const dl_next_opts* o) {
     d.batched = o->batched;
     d.x0_given = o->x0_given;
     if (o->max_mvp > 0) d.max_mvp = o->max_mvp;
+    d.net = o->net;
   }
   return d;
+}
+
+// host complex128 weights <-> device FP32 complex weights
+void weights_to_device(dl_net* net, const double* w) {
+  const int nw = net_num_weights();
+  std::vector<float2> h(nw);
+  for (int i = 0; i < nw; ++i) {
+    if (!std::isfinite(w[2 * i]) || !std::isfinite(w[2 * i + 1])) fail(DL_E_NONFINITE, "non-finite weight");
+    h[i] = make_float2((float)w[2 * i], (float)w[2 * i + 1]);
+  }
+  DL_HIP(hipMemcpyAsync(net->W.get(), h.data(), nw * sizeof(float2), hipMemcpyHostToDevice, net->ctx->stream));
+  DL_HIP(hipStreamSynchronize(net->ctx->stream));
+}
+
+void weights_to_host(const float2* d, double* w, hipStream_t s) {
+  const int nw = net_num_weights();
+  std::vector<float2> h(nw);
+  DL_HIP(hipMemcpyAsync(h.data(), d, nw * sizeof(float2), hipMemcpyDeviceToHost, s));
+  DL_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < nw; ++i) {
+    w[2 * i] = h[i].x;
+    w[2 * i + 1] = h[i].y;
+  }
+}
+
+void check_net_op(const dl_net* net, const dl_op* op) {
+  need(net->ctx == op->ctx, "network and operator belong to different contexts");
 }
 
 }  // namespace
@@ -311,6 +342,9 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     need(o.storage == DL_FP64 || o.storage == DL_FP32, "storage must be DL_FP64 or DL_FP32");
     need(!(o.storage == DL_FP32 && !o.batched), "DL_FP32 storage runs through the batched path (batched = 1)");
     need(!(o.batched && o.storage == DL_FP64), "the batched path stores Krylov vectors in DL_FP32");
+    need(!o.net || o.batched, "the learned initial guess runs on the batched path (batched = 1)");
+    need(!(o.net && o.x0_given), "x0_given and a learned initial guess exclude each other");
+    if (o.net) check_net_op(o.net, op);
     use_device(op->ctx);
     if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
       fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
@@ -386,6 +420,121 @@ int dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* o
     if (variant) *variant = c.variant;
     if (order) *order = c.order;
     if (best_us) *best_us = us;
+    return DL_OK;
+  });
+}
+
+int dl_net_num_weights(void) { return net_num_weights(); }
+
+int dl_net_create(dl_ctx* ctx, const double* weights, dl_net** out) {
+  return guard([&] {
+    need(ctx && weights && out, "NULL argument");
+    use_device(ctx);
+    auto* net = new dl_net();
+    try {
+      net->ctx = ctx;
+      const int nw = net_num_weights();
+      net->W.alloc(nw);
+      net->G.alloc(nw);
+      net->Wt.alloc(nw);
+      net->m.alloc(2 * nw);
+      net->v.alloc(2 * nw);
+      net_reset_adam(net);
+      weights_to_device(net, weights);
+    } catch (...) {
+      delete net;
+      throw;
+    }
+    *out = net;
+    return DL_OK;
+  });
+}
+
+int dl_net_get_weights(const dl_net* net, double* weights) {
+  return guard([&] {
+    need(net && weights, "NULL argument");
+    use_device(net->ctx);
+    weights_to_host(net->W.get(), weights, net->ctx->stream);
+    return DL_OK;
+  });
+}
+
+int dl_net_set_weights(dl_net* net, const double* weights) {
+  return guard([&] {
+    need(net && weights, "NULL argument");
+    use_device(net->ctx);
+    weights_to_device(net, weights);
+    net_reset_adam(net);
+    DL_HIP(hipStreamSynchronize(net->ctx->stream));
+    return DL_OK;
+  });
+}
+
+void dl_net_destroy(dl_net* net) {
+  if (!net) return;
+  (void)hipSetDevice(net->ctx->device);
+  (void)hipStreamSynchronize(net->ctx->stream);
+  delete net;
+}
+
+int dl_net_apply(dl_net* net, dl_op* op, int nrhs, const double* B, double* Y, int mem) {
+  return guard([&] {
+    need(net && op, "NULL argument");
+    need(nrhs >= 0, "nrhs must be >= 0");
+    if (nrhs == 0) return DL_OK;
+    need(B && Y, "NULL argument");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    check_net_op(net, op);
+    use_device(op->ctx);
+    DBuf<double2> bt = fields_in(op, B, nrhs, mem);
+    DBuf<double2> yt((size_t)nrhs * op->lat.nc);
+    net_apply(net, op, nrhs, bt.get(), yt.get());
+    fields_out(op, yt.get(), Y, nrhs, mem);
+    return DL_OK;
+  });
+}
+
+int dl_net_loss_grad(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem, double* loss,
+                     double* grad) {
+  return guard([&] {
+    need(net && op && B && X && loss, "NULL argument");
+    need(n >= 1, "need at least one pair");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    check_net_op(net, op);
+    use_device(op->ctx);
+    DBuf<double2> bt = fields_in(op, B, n, mem);
+    DBuf<double2> xt = fields_in(op, X, n, mem);
+    *loss = net_loss_grad(net, op, n, bt.get(), xt.get(), grad != nullptr);
+    if (grad) weights_to_host(net->G.get(), grad, op->ctx->stream);
+    return DL_OK;
+  });
+}
+
+int dl_net_train(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem, int batch, int steps,
+                 double lr, double* losses) {
+  return guard([&] {
+    need(net && op && B && X, "NULL argument");
+    need(n >= 1 && batch >= 1 && batch <= n, "need 1 <= batch <= n");
+    need(steps >= 0, "steps must be >= 0");
+    need(lr > 0 && std::isfinite(lr), "lr must be positive");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    check_net_op(net, op);
+    use_device(op->ctx);
+    DBuf<double2> bt = fields_in(op, B, n, mem);
+    DBuf<double2> xt = fields_in(op, X, n, mem);
+    const int ngroups = n / batch;
+    const long nc = op->lat.nc;
+    for (int st = 0; st < steps; ++st) {
+      const long g = st % ngroups;
+      const double L = net_loss_grad(net, op, batch, bt.get() + g * batch * nc, xt.get() + g * batch * nc, true);
+      if (losses) losses[st] = L;
+      net_adam_step(net, (float)lr);
+      if (verbose() && (st % 50 == 0 || st == steps - 1)) {
+        std::fprintf(stderr, "[deflan] net train step %d/%d: loss %.5e\n", st, steps, L);
+        std::fflush(stderr);
+      }
+    }
+    DL_HIP(hipStreamSynchronize(op->ctx->stream));
     return DL_OK;
   });
 }

@@ -39,16 +39,16 @@ class dl_first_opts(C.Structure):
 
 class dl_next_opts(C.Structure):
     _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
-                ("x0_given", C.c_int), ("max_mvp", C.c_long)]
+                ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p)]
 
 
 class dl_stats(C.Structure):
-    _fields_ = [("status", C.c_int), ("stop_rule", C.c_int), ("cycles", C.c_int), ("reserved", C.c_int),
+    _fields_ = [("status", C.c_int), ("stop_rule", C.c_int), ("cycles", C.c_int), ("guess", C.c_int),
                 ("mvp", C.c_long), ("mvp_lin", C.c_long), ("iters", C.c_long),
                 ("relres", C.c_double), ("time_s", C.c_double)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
         d["stop_rule"] = STOP_RULES.get(self.stop_rule, str(self.stop_rule))
         return d
 
@@ -81,6 +81,14 @@ def _load():
         "dl_tsk_project": (I, [P, L, I, P, P, P, I, I]),
         "dl_tsk_combine": (I, [P, L, I, P, P, I, P, I]),
         "dl_small_eigh": (I, [P, I, P, P, P]),
+        "dl_net_num_weights": (I, []),
+        "dl_net_create": (I, [P, P, C.POINTER(P)]),
+        "dl_net_get_weights": (I, [P, P]),
+        "dl_net_set_weights": (I, [P, P]),
+        "dl_net_destroy": (None, [P]),
+        "dl_net_apply": (I, [P, P, I, P, P, I]),
+        "dl_net_loss_grad": (I, [P, P, I, P, P, I, C.POINTER(D), P]),
+        "dl_net_train": (I, [P, P, I, P, P, I, I, I, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -93,7 +101,9 @@ lib = _load()
 EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "dl_ctx_sync", "dl_timing",
             "dl_kernel_time", "dl_op_create", "dl_op_destroy", "dl_op_size", "dl_apply", "dl_solve_first",
             "dl_solve_next", "dl_eig_create", "dl_eig_info", "dl_eig_vectors", "dl_eig_destroy",
-            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson")
+            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson",
+            "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
+            "dl_net_apply", "dl_net_loss_grad", "dl_net_train")
 
 
 def _check(rc):
@@ -158,8 +168,8 @@ class Context:
     def close(self):
         if getattr(self, "h", None):
             kids = list(self._children)
-            for ch in kids:  # eigenvector handles before operators
-                if isinstance(ch, Eig):
+            for ch in kids:  # eigenvector handles and networks before operators
+                if isinstance(ch, (Eig, Net)):
                     ch.close()
             for ch in kids:
                 ch.close()
@@ -254,12 +264,12 @@ class Operator:
         return x, eig, dict(st.as_dict(), rc=rc)
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
-                   reliable_every=None):
+                   reliable_every=None, net=None):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
         o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
-                         int(max_mvp or 0))
+                         int(max_mvp or 0), net.h if net is not None else None)
         st = (dl_stats * max(nrhs, 1))()
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
@@ -300,6 +310,75 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """dl_net: the gauge-covariant network of the learned initial guess (weights complex128 [n])."""
+
+    def __init__(self, ctx: Context, weights):
+        self.ctx = ctx
+        w = np.ascontiguousarray(weights, dtype=np.complex128)
+        if w.shape != (num_weights(),):
+            raise ValueError(f"expected {num_weights()} complex weights, got shape {w.shape}")
+        h = C.c_void_p()
+        _check(lib.dl_net_create(ctx.h, w.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def weights(self):
+        w = np.zeros(num_weights(), dtype=np.complex128)
+        _check(lib.dl_net_get_weights(self.h, w.ctypes.data_as(C.c_void_p)))
+        return w
+
+    def set_weights(self, weights):
+        w = np.ascontiguousarray(weights, dtype=np.complex128)
+        if w.shape != (num_weights(),):
+            raise ValueError(f"expected {num_weights()} complex weights, got shape {w.shape}")
+        _check(lib.dl_net_set_weights(self.h, w.ctypes.data_as(C.c_void_p)))
+
+    def apply(self, op: "Operator", B):
+        """net(b) for each field of B ([n][V][4][3])."""
+        B = _c128(B)
+        Y = _empty_like(B)
+        pB, mem = _ptr(B)
+        pY, _ = _ptr(Y)
+        _check(lib.dl_net_apply(self.h, op.h, int(B.shape[0]), pB, pY, mem))
+        return Y
+
+    def loss_grad(self, op: "Operator", B, X, grad: bool = True):
+        B, X = _c128(B), _c128(X)
+        pB, mem = _ptr(B)
+        pX, _ = _ptr(X)
+        L = C.c_double()
+        g = np.zeros(num_weights(), dtype=np.complex128) if grad else None
+        _check(lib.dl_net_loss_grad(self.h, op.h, int(B.shape[0]), pB, pX, mem, C.byref(L),
+                                    g.ctypes.data_as(C.c_void_p) if grad else None))
+        return L.value, g
+
+    def train(self, op: "Operator", B, X, batch: int, steps: int, lr: float):
+        """Adam steps on the pairs (B, X); returns the per-step minibatch losses."""
+        B, X = _c128(B), _c128(X)
+        pB, mem = _ptr(B)
+        pX, _ = _ptr(X)
+        losses = np.zeros(max(int(steps), 1))
+        _check(lib.dl_net_train(self.h, op.h, int(B.shape[0]), pB, pX, mem, int(batch), int(steps), float(lr),
+                                losses.ctypes.data_as(C.c_void_p)))
+        return losses[:int(steps)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.dl_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def num_weights() -> int:
+    return int(lib.dl_net_num_weights())
 
 
 # ---- kernel-level entry points ------------------------------------------------

@@ -1,0 +1,199 @@
+"""The learned initial guess (gauge-covariant network) on the GPU against the FP64 network oracle.
+
+Tolerances: the GPU network computes in FP32 (unit roundoff u = 6e-8).  A layer sums
+9 hops x C_in <= 144 complex products per output and three layers are chained, so
+the forward error is bounded by about 3 * 144 * u ~ 3e-5 relative (worst case, random
+signs give far less); the loss and gradient add one FP32 Wilson apply each way.
+The forward is compared at 2e-5 norm-wise, the loss at 1e-5 and the gradient at 1e-4.
+"""
+import numpy as np
+import pytest
+
+from lattice_inputs import gaussian_spinor, su3_links
+from oracle import dirac, ptc
+
+pytestmark = pytest.mark.gpu
+
+RAGGED = (4, 2, 3, 6)  # 144 sites: 3 tiles, the last one partly padding
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _ops(dims, U, kappa):
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    M = lambda v: ora.M(v.ravel()).reshape(v.shape)
+    Mdag = lambda v: ora.Mdag(v.ravel()).reshape(v.shape)
+    return ora, M, Mdag
+
+
+@pytest.mark.parametrize("dims", [RAGGED, (4, 4, 4, 4), (8, 8, 8, 8)])
+def test_forward_matches_oracle(gpu_ctx, dims):
+    from paper_0901_3163_amd import deflan
+    U = su3_links(dims, 40)
+    w = ptc.init_weights(41, scale=1.0)
+    op = deflan.Operator(gpu_ctx, dims, U, 0.12, deflan.DL_G5M)
+    net = deflan.Net(gpu_ctx, w)
+    B = np.stack([gaussian_spinor(dims, 42 + i) for i in range(3)])
+    B[1] *= 1e3  # the network is scale-equivariant: a large rhs gives a proportionally large guess
+    Y = net.apply(op, B)
+    for i in range(3):
+        assert _rel(Y[i], ptc.forward(U, w, B[i], dims)) < 2e-5
+    net.close()
+    op.close()
+
+
+def test_weights_roundtrip_and_zero_net(gpu_ctx):
+    from paper_0901_3163_amd import deflan
+    dims = RAGGED
+    U = su3_links(dims, 43)
+    w = ptc.init_weights(44)
+    net = deflan.Net(gpu_ctx, w)
+    got = net.weights()
+    assert np.max(np.abs(got - w.astype(np.complex64))) == 0.0
+    op = deflan.Operator(gpu_ctx, dims, U, 0.12, deflan.DL_G5M)
+    net.set_weights(np.zeros_like(w))
+    Y = net.apply(op, gaussian_spinor(dims, 45)[None])
+    assert np.all(Y == 0)
+    # a zero rhs gives a zero guess (no division by ||b|| = 0)
+    net.set_weights(w)
+    Y = net.apply(op, np.zeros((1,) + gaussian_spinor(dims, 45).shape, complex))
+    assert np.all(Y == 0)
+    with pytest.raises(ValueError):
+        deflan.Net(gpu_ctx, w[:-1])
+    net.close()
+    op.close()
+
+
+@pytest.mark.parametrize("dims", [RAGGED, (4, 4, 4, 4)])
+def test_loss_and_gradient_match_oracle(gpu_ctx, dims):
+    from paper_0901_3163_amd import deflan
+    U = su3_links(dims, 50)
+    kappa = 0.12
+    w = ptc.init_weights(51, scale=1.0)
+    _, M, Mdag = _ops(dims, U, kappa)
+    B = np.stack([gaussian_spinor(dims, 52 + i) for i in range(2)])
+    X = np.stack([0.4 * gaussian_spinor(dims, 60 + i) for i in range(2)])
+    Ls, Gs = zip(*[ptc.loss_and_grad(U, w, B[i], X[i], dims, M, Mdag) for i in range(2)])
+    L_orc, G_orc = float(np.mean(Ls)), np.mean(Gs, axis=0)
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_G5M)
+    net = deflan.Net(gpu_ctx, w)
+    L, G = net.loss_grad(op, B, X)
+    assert abs(L - L_orc) <= 1e-5 * L_orc
+    assert _rel(G, G_orc) < 1e-4
+    # each layer's block separately (a wrong hop order in one layer cannot hide behind another)
+    off = 0
+    for l in range(3):
+        n = 9 * ptc.WIDTHS[l + 1] * ptc.WIDTHS[l]
+        assert _rel(G[off:off + n], G_orc[off:off + n]) < 1e-4
+        off += n
+    net.close()
+    op.close()
+
+
+def test_adam_first_step_matches_formula(gpu_ctx):
+    """Step 1 of bias-corrected Adam moves each real component by -lr * g / (|g| + eps)."""
+    from paper_0901_3163_amd import deflan
+    dims = RAGGED
+    U = su3_links(dims, 70)
+    kappa = 0.12
+    w = ptc.init_weights(71, scale=1.0)
+    _, M, Mdag = _ops(dims, U, kappa)
+    B = np.stack([gaussian_spinor(dims, 72 + i) for i in range(2)])
+    X = np.stack([0.4 * gaussian_spinor(dims, 80 + i) for i in range(2)])
+    G = np.mean([ptc.loss_and_grad(U, w, B[i], X[i], dims, M, Mdag)[1] for i in range(2)], axis=0)
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_G5M)
+    net = deflan.Net(gpu_ctx, w)
+    lr = 1e-3
+    losses = net.train(op, B, X, batch=2, steps=1, lr=lr)
+    assert losses.shape == (1,)
+    w1 = net.weights()
+    w0 = w.astype(np.complex64).astype(np.complex128)
+    for part in (np.real, np.imag):
+        g = part(G)
+        big = np.abs(g) > 1e-3 * np.max(np.abs(g))
+        step = part(w1 - w0)[big]
+        assert np.max(np.abs(step + lr * np.sign(g[big]))) < 2e-3 * lr
+    net.close()
+    op.close()
+
+
+def _c1_pairs(c1, seeds):
+    ora = dirac.WilsonOperator(c1["links"], c1["dims"], c1["kappa"])
+    Md = dirac.dense(ora.M, ora.n)
+    B = np.stack([gaussian_spinor(c1["dims"], s) for s in seeds])
+    X = np.stack([np.linalg.solve(Md, b.ravel()).reshape(b.shape) for b in B])
+    return ora, B, X
+
+
+def test_training_lowers_loss_and_guess_helps_solve(gpu_ctx, c1_config):
+    """Adam on 8 (b, x) pairs of the near-critical 4^4 field lowers the loss on held-out pairs;
+    D-MinRes from net(b) + projection reaches tol and keeps the learned start."""
+    from paper_0901_3163_amd import deflan
+    c1 = c1_config
+    dims, U, kappa = c1["dims"], c1["links"], c1["kappa"]
+    ora, B, X = _c1_pairs(c1, range(500, 508))
+    _, Bh, Xh = _c1_pairs(c1, range(600, 604))
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_G5M)
+    net = deflan.Net(gpu_ctx, ptc.init_weights(7))
+    L0, _ = net.loss_grad(op, Bh, Xh, grad=False)
+    losses = net.train(op, B, X, batch=4, steps=120, lr=3e-3)
+    assert np.all(np.isfinite(losses))
+    L1, _ = net.loss_grad(op, Bh, Xh, grad=False)
+    assert L1 < 0.2 * L0
+    # the trained weights evaluated by the oracle give the same held-out loss
+    w1 = net.weights()
+    M = lambda v: ora.M(v.ravel()).reshape(v.shape)
+    Mdag = lambda v: ora.Mdag(v.ravel()).reshape(v.shape)
+    L1_orc = np.mean([ptc.loss_and_grad(U, w1, Bh[i], Xh[i], dims, M, Mdag)[0] for i in range(4)])
+    assert abs(L1 - L1_orc) <= 1e-4 * L1_orc
+    # later rhs: projection-only vs learned start, both to tol 1e-10
+    b1 = gaussian_spinor(dims, 100)
+    _, eig, _ = op.solve_first(b1, 60, 20, 1e-10)
+    Xp, stp, rc = op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1)
+    assert rc == deflan.DL_OK
+    Xn, stn, rc = op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net)
+    assert rc == deflan.DL_OK
+    for i in range(4):
+        r = np.linalg.norm(Bh[i].ravel() - ora.M(Xn[i].ravel())) / np.linalg.norm(Bh[i])
+        assert stn[i]["relres"] <= 1e-10 and r <= 1.0001e-10
+        assert _rel(Xn[i], Xh[i]) < 1e-6
+        assert stn[i]["guess"] == 1 and stp[i]["guess"] == 0
+    assert sum(s["iters"] for s in stn) <= 1.05 * sum(s["iters"] for s in stp)
+    eig.close()
+    net.close()
+    op.close()
+
+
+def test_guess_fallback_and_options(gpu_ctx, c1_config):
+    """A zero network ties with the projection-only start (kept: projection); a wild network
+    is rejected per rhs; invalid option combinations fail."""
+    from paper_0901_3163_amd import deflan
+    c1 = c1_config
+    dims, U, kappa = c1["dims"], c1["links"], c1["kappa"]
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_MDAGM)
+    b1 = gaussian_spinor(dims, 100)
+    _, eig, _ = op.solve_first(b1, 60, 20, 1e-10)
+    B = np.stack([gaussian_spinor(dims, 700 + i) for i in range(3)] + [np.zeros_like(b1)])
+    net = deflan.Net(gpu_ctx, np.zeros(deflan.num_weights(), complex))
+    X, st, rc = op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net)
+    assert rc == deflan.DL_OK
+    assert all(s["guess"] == 0 for s in st)
+    net.set_weights(ptc.init_weights(9, scale=30.0))
+    X, st, rc = op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net)
+    assert rc == deflan.DL_OK
+    for i in range(3):
+        r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+        assert r <= 1.0001e-10
+    assert np.all(X[3] == 0) and st[3]["guess"] == 0
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(B, eig, 1e-10, net=net)  # FP64 one-at-a-time path has no learned guess
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net, x0=np.zeros_like(B))
+    with pytest.raises(deflan.DeflanError):
+        net.train(op, B[:3], B[:3], batch=4, steps=1, lr=1e-3)
+    eig.close()
+    net.close()
+    op.close()
