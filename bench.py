@@ -3,16 +3,22 @@
 Workload (one GPU): the 16^3 x 32 near-critical Wilson lattice (links
 U = exp(0.5 i X), seed 0; kappa from the oracle's kappa search, min|lambda(gamma5 M)|
 ~ 1e-4).  Setup, untimed and reported separately: MinRes-DR(120,60) on gamma5 M
-for a Gaussian first right-hand side (seed 200).  One timed step: D-MinRes for
-the 12 spin-colour point sources e_{site 0, spin s, colour c}, every one
-verified by its FP64 true residual <= 1e-10.  Inputs and outputs stay in HBM
-(torch complex128 device tensors passed as device pointers).
+for a Gaussian first right-hand side (seed 200), and the training of the
+learned-guess network on 24 point sources at other sites of the same field.
+One timed step: D-MinRes for the 12 spin-colour point sources e_{site 0, spin s,
+colour c} on the fast path (FP32 Krylov vectors and Wilson apply for all 12
+together, FP64 true residuals, projection and solution, learned initial guess),
+every one verified by its FP64 true residual <= 1e-10.  Inputs and outputs stay
+in HBM (torch complex128 device tensors passed as device pointers).  The same
+solve without the learned guess and the plain FP64 one-rhs-at-a-time D-MinRes
+are timed after it as the ablation.
 
-value = 12 * steps / timed seconds (RHS/s).  roofline: the Wilson stencil,
-its average launch duration taken with HIP events around every launch inside
-the timed region, algorithmic bytes 960 B/site (FP64: input spinor, links,
-output spinor each moved once).  cpu_baseline: the oracle's D-MinRes on the
-host cores for a bounded sample of the same workload.
+value = 12 * steps / timed seconds (RHS/s).  roofline: the batched FP32 Wilson
+stencil, its average launch duration taken with HIP events on the library's
+stream around every launch inside the timed region, algorithmic bytes per launch
+= 288 B/site (links once) + 192 B/site per active rhs (input and output spinor).
+cpu_baseline: the oracle's D-MinRes on the host cores for a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -134,6 +140,39 @@ def cpu_baseline(dims, kappa, iters_per_rhs, k):
                 seconds_per_rhs=round(per_rhs, 3))
 
 
+def train_guess(ctx, op, eig, deflan, dims, args):
+    """Train the learned-guess network on (b, x) pairs of the benchmark field: b = point
+    sources at seeded random sites other than site 0 (random spin and colour), x from the
+    batched mixed-precision D-MinRes to the benchmark tolerance.  Returns (net, summary)."""
+    import torch
+    from lattice_inputs import net_weights, point_source
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(900)
+    sites = rng.choice(np.arange(1, V), size=args.train_rhs, replace=False)
+    Bt = np.stack([point_source(dims, int(s), int(rng.integers(4)), int(rng.integers(3))) for s in sites])
+    Bt = torch.from_numpy(Bt).cuda()
+    t0 = time.time()
+    Xt, st, _ = op.solve_next(Bt, eig, args.tol, storage=deflan.DL_FP32, batched=1)
+    torch.cuda.synchronize()
+    t_pairs = time.time() - t0
+    log(f"learned guess: {args.train_rhs} training pairs solved in {t_pairs:.1f}s")
+    net = deflan.Net(ctx, net_weights(args.net_seed))
+    t0 = time.time()
+    losses = net.train(op, Bt, Xt, batch=args.train_batch, steps=args.train_steps, lr=args.train_lr)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"learned guess: {args.train_steps} Adam steps in {t_train:.1f}s, loss {losses[0]:.4f} -> "
+        f"{np.mean(losses[-10:]):.4f}")
+    del Bt, Xt
+    info = dict(training_pairs=args.train_rhs, pair_seconds=round(t_pairs, 2), steps=args.train_steps,
+                batch=args.train_batch, lr=args.train_lr, train_seconds=round(t_train, 2),
+                loss_first=round(float(losses[0]), 5), loss_last10=round(float(np.mean(losses[-10:])), 5),
+                pairs="point sources at seeded random sites != 0 of the benchmark field, x from batched "
+                      "FP32/FP64 D-MinRes at the benchmark tolerance",
+                loss="mean ||M (net(b) - x)||^2 / ||b||^2")
+    return net, info
+
+
 def kernel_only(args):
     """The dominant kernel alone, for rocprofv3 counter runs: the FP32 gamma5 M stencil on the
     16^3x32 lattice for 12 right-hand sides at once (reps launches), then a device copy of
@@ -174,6 +213,12 @@ def main():
     ap.add_argument("--kappa", type=float, default=None, help="override the stored kappa (exploration only)")
     ap.add_argument("--kernel-only", action="store_true", help="run only the dominant kernel + a copy (profiling)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--train-rhs", type=int, default=24, help="training pairs of the learned guess (0: no net)")
+    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-batch", type=int, default=6)
+    ap.add_argument("--train-lr", type=float, default=3e-3)
+    ap.add_argument("--net-seed", type=int, default=7)
+    ap.add_argument("--ablation-steps", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded across GPUs.",
@@ -212,30 +257,54 @@ def main():
     B = torch.from_numpy(point_sources(dims)).cuda()
     nrhs = B.shape[0]
 
-    def fast():
-        return op.solve_next(B, eig, args.tol, storage=deflan.DL_FP32, batched=1)
+    # learned initial guess (setup, untimed): train the network on point sources at other
+    # sites of the same field, solved by the mixed-precision batched path
+    net, net_info = None, None
+    if args.train_rhs > 0:
+        net, net_info = train_guess(ctx, op, eig, deflan, dims, args)
+
+    def fast(use_net=True):
+        return op.solve_next(B, eig, args.tol, storage=deflan.DL_FP32, batched=1,
+                             net=net if use_net else None)
 
     def plain():
         return op.solve_next(B, eig, args.tol)
 
     for w in range(args.warmup):
         X, sts, rc = fast()
-        log(f"warmup {w} (batched FP32): iters {[s['iters'] for s in sts]}")
+        log(f"warmup {w} (batched FP32{' + learned guess' if net else ''}): iters {[s['iters'] for s in sts]}")
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.time()
     all_ok = True
-    iters = []
+    iters, kept = [], []
     for s in range(args.steps):
         X, sts, rc = fast()
         all_ok &= all(st["relres"] <= args.tol for st in sts)
         iters += [st["iters"] for st in sts]
+        kept += [st["guess"] for st in sts]
         log(f"step {s}: rc {rc}, max relres {max(st['relres'] for st in sts):.2e}")
     torch.cuda.synchronize()
     dt = time.time() - t0
     n_w, ms_w, by_w = ctx.kernel_time("wilson")
     ctx.timing(False)
     value = nrhs * args.steps / dt
+    # ablation: the same mixed-precision batched path without the learned guess
+    mixed = None
+    if net is not None:
+        fast(False)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for s in range(args.ablation_steps):
+            Xm, stm, _ = fast(False)
+        torch.cuda.synchronize()
+        dtm = time.time() - t0
+        mixed = dict(value=round(nrhs * args.ablation_steps / dtm, 3), unit="RHS/s", steps=args.ablation_steps,
+                     all_rhs_converged=bool(all(st["relres"] <= args.tol for st in stm)),
+                     iters_per_rhs=float(np.mean([st["iters"] for st in stm])),
+                     path="batched D-MinRes FP32/FP64 without the learned guess (projection-only start)")
+        net_info["guess_kept_per_rhs"] = float(np.mean(kept))
+        log(f"without the learned guess: {mixed['value']:.2f} RHS/s, iters {mixed['iters_per_rhs']:.1f}")
     achieved = by_w / (ms_w * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(dims),
@@ -263,9 +332,12 @@ def main():
                                        f"{args.k}) on gamma5 M then D-MinRes on 12 point sources, tol "
                                        f"{args.tol:g}", lattice=list(dims), kappa=kappa, nrhs=nrhs,
                               m=args.m, k=args.k,
-                              path="batched D-MinRes, FP32 Krylov vectors and Wilson apply, FP64 residuals, "
-                                   "projection and solution"),
+                              path=("batched D-MinRes, FP32 Krylov vectors and Wilson apply, FP64 residuals, "
+                                    "projection and solution" + (", learned initial guess (net(b) + projection, "
+                                                                  "kept per rhs when its residual is smaller)"
+                                                                  if net is not None else ""))),
                   all_rhs_converged=bool(all_ok), iters_per_rhs=float(np.mean(iters)),
+                  learned_guess=net_info, mixed_batched_no_guess=mixed,
                   plain_fp64=dict(value=round(plain_value, 3), unit="RHS/s", steps=args.plain_steps,
                                   all_rhs_converged=bool(ok64),
                                   iters_per_rhs=float(np.mean([st["iters"] for st in st64])),
@@ -280,6 +352,8 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(dims, kappa, result["plain_fp64"]["iters_per_rhs"], args.k)
+    if net is not None:
+        net.close()
     eig.close()
     op.close()
     ctx.close()

@@ -202,6 +202,13 @@ int  dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double*
  * variant / order / best_us (may be NULL) receive the choice and its time. */
 int  dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* order, double* best_us);
 
+/* out_j = op(in_j) for nrhs fields ([nrhs][V][4][3] complex128), op = M, M^dag or gamma5 M
+ * (which = DL_APPLY_M, DL_APPLY_MDAG, DL_APPLY_G5M), by the multi-rhs stencil of the batched
+ * solver: links read once per site for all fields.  prec DL_FP32 rounds the input and the
+ * links to FP32, computes in FP32 and widens the result.  The launch shape is the tuned one
+ * (the environment variable DEFLAN_WILSON_VARIANT = "v" or "v,o" forces one). */
+int  dl_apply_batched(dl_op* op, int which, int prec, int nrhs, const double* in, double* out, int mem);
+
 /* ---- eigenvector handle ---------------------------------------------------- */
 /* Build a handle from k caller-supplied orthonormal vectors V ([k][V][4][3]);
  * H = V^H A V is formed with k MVPs in FP64. */
@@ -222,7 +229,8 @@ void dl_eig_destroy(dl_eig* eig);
  * h over {0, +x, -x, +y, -y, +z, -z, +t, -t}, T_0 = 1, (T_{+mu} a)(x) = U_mu(x) a(x+mu),
  * (T_{-mu} a)(x) = U_mu(x-mu)^dag a(x-mu); widths 4 -> 16 -> 16 -> 4 with
  * f(z) = z / sqrt(1 + |z|^2) (colour norm per site and channel) after layers 1 and 2.
- * net(b) = s N(b / s) with s = ||b|| / sqrt(V).
+ * net(b) = s N(b / s) with s the root-mean-square site norm of b over the sites where b is
+ * nonzero (||b|| / sqrt(V) for a source without zeros, |b(x0)| for a point source).
  * Weights: complex128 interleaved, layers concatenated, each [9 hops][C_out][C_in]
  * in the hop order above; dl_net_num_weights() complex numbers in all.
  * A network belongs to one context; its scratch grows to the largest batch used. */

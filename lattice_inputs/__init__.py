@@ -96,3 +96,15 @@ def diag_spectrum_indefinite(seed: int = 5) -> np.ndarray:
     The paper's draw has 22 negative entries; default_rng(5) reproduces that count.
     """
     return np.random.default_rng(seed).standard_normal(1000) + 2.0
+
+
+def net_weights(seed: int, widths=(4, 16, 16, 4), scale: float = 0.3) -> np.ndarray:
+    """Seeded complex Gaussian weights of the learned-guess network: per layer an array
+    [9 hops][C_out][C_in] with entries of variance scale^2 / (9 C_in), layers concatenated."""
+    rng = np.random.default_rng(seed)
+    ws = []
+    for l in range(len(widths) - 1):
+        cin, cout = widths[l], widths[l + 1]
+        sd = scale / np.sqrt(9 * cin)
+        ws.append(sd * (rng.standard_normal((9, cout, cin)) + 1j * rng.standard_normal((9, cout, cin))) / np.sqrt(2))
+    return np.concatenate([w.ravel() for w in ws])

@@ -14,7 +14,10 @@ Wettig, 2023); the reading used here:
   (T_{+mu} psi)(x) = U_mu(x) psi(x + mu), (T_{-mu} psi)(x) = U_mu(x - mu)^dag psi(x - mu);
 * channel widths 4 -> 16 -> 16 -> 4, nonlinearity f(z) = z / sqrt(1 + |z|^2) per
   site and channel (|z| the gauge-invariant colour norm) after layers 1 and 2;
-* net(b) = s * N(b / s) with s = ||b|| / sqrt(V), so the guess scales with b.
+* net(b) = s * N(b / s) with s the root-mean-square site norm of b over the sites
+  where b is nonzero (s = ||b|| / sqrt(V) for a source without zeros, |b(x0)| for a
+  point source), so the guess scales with b and every source reaches the network at
+  unit scale.
 
 Loss on a pair (b, x) with M x = b: L = ||M (net(b) - x)||^2 / ||b||^2, the error in
 the M^dag M norm.  Gradients use the real-gradient convention G = dL/dRe + i dL/dIm.
@@ -23,6 +26,8 @@ The backward pass is written out by hand (adjoint of T_h is T_{-h}).
 from __future__ import annotations
 
 import numpy as np
+
+from lattice_inputs import net_weights
 
 WIDTHS = (4, 16, 16, 4)
 HOPS = [(None, 0), (0, 1), (0, -1), (1, 1), (1, -1), (2, 1), (2, -1), (3, 1), (3, -1)]
@@ -49,14 +54,8 @@ def split_weights(w, widths=WIDTHS):
 
 
 def init_weights(seed: int, widths=WIDTHS, scale=0.3) -> np.ndarray:
-    """Seeded complex Gaussian weights, variance scale^2 / (9 C_in) per layer."""
-    rng = np.random.default_rng(seed)
-    ws = []
-    for l in range(len(widths) - 1):
-        cin, cout = widths[l], widths[l + 1]
-        sd = scale / np.sqrt(9 * cin)
-        ws.append(sd * (rng.standard_normal((9, cout, cin)) + 1j * rng.standard_normal((9, cout, cin))) / np.sqrt(2))
-    return np.concatenate([w.ravel() for w in ws])
+    """Seeded complex Gaussian weights (the shared input generator)."""
+    return net_weights(seed, widths, scale)
 
 
 def _shape(dims):
@@ -105,11 +104,17 @@ def nonlin_backward(z, g):
     return gf * g + 2.0 * dgf * re * z
 
 
+def input_scale(b):
+    """Root-mean-square site norm of b over its nonzero sites (0 for b = 0)."""
+    site_n2 = np.sum(np.abs(b) ** 2, axis=(1, 2))
+    nz = np.count_nonzero(site_n2)
+    return 0.0 if nz == 0 else float(np.sqrt(np.sum(site_n2) / nz))
+
+
 def forward(U, w, b, dims, keep=False):
     """net(b) for b [V, 4, 3]; with keep=True also the intermediate activations."""
     Ws = split_weights(w)
-    V = b.shape[0]
-    s = np.linalg.norm(b) / np.sqrt(V)
+    s = input_scale(b)
     a0 = b / s
     z1 = layer(U, Ws[0], a0, dims)
     a1 = nonlin(z1)

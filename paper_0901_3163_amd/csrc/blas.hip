@@ -145,4 +145,22 @@ void zero(hipStream_t s, long n, double2* a) {
   DL_HIP(hipGetLastError());
 }
 
+__global__ void k_round_f32(long n, const double2* __restrict__ a, float2* __restrict__ b) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+__global__ void k_widen_f64(long n, const float2* __restrict__ a, double2* __restrict__ b) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    b[i] = make_double2(a[i].x, a[i].y);
+}
+
+void round_f32(hipStream_t s, long n, const double2* a, float2* b) {
+  hipLaunchKernelGGL(k_round_f32, dim3(2048), dim3(256), 0, s, n, a, b);
+  DL_HIP(hipGetLastError());
+}
+void widen_f64(hipStream_t s, long n, const float2* a, double2* b) {
+  hipLaunchKernelGGL(k_widen_f64, dim3(2048), dim3(256), 0, s, n, a, b);
+  DL_HIP(hipGetLastError());
+}
+
 }  // namespace dl

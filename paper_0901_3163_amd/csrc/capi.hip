@@ -358,6 +358,39 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
   });
 }
 
+int dl_apply_batched(dl_op* op, int which, int prec, int nrhs, const double* in, double* out, int mem) {
+  return guard([&] {
+    need(op != nullptr, "op is NULL");
+    need(which >= 0 && which <= 2, "which must be DL_APPLY_M, DL_APPLY_MDAG or DL_APPLY_G5M");
+    need(prec == DL_FP64 || prec == DL_FP32, "prec must be DL_FP64 or DL_FP32");
+    need(nrhs >= 0, "nrhs must be >= 0");
+    if (nrhs == 0) return DL_OK;
+    need(in && out, "NULL argument");
+    need(in != out, "in and out may not alias");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    use_device(op->ctx);
+    hipStream_t s = op->ctx->stream;
+    const Lattice& lat = op->lat;
+    const long n = (long)nrhs * lat.nc;
+    DBuf<double2> t = fields_in(op, in, nrhs, mem);
+    DBuf<double2> r(n);
+    const WilsonCfg cfg = wilson_cfg(op, prec, nrhs);
+    if (prec == DL_FP64) {
+      wilson_batched<double>(s, lat, op->U.get(), op->kappa, which, t.get(), r.get(), lat.nc, nrhs, 0, nullptr,
+                             nullptr, nullptr, cfg);
+    } else {
+      DBuf<float2> a32(n), b32(n);
+      round_f32(s, n, t.get(), a32.get());
+      wilson_batched<float>(s, lat, op_links32_public(op), op->kappa, which, a32.get(), b32.get(), lat.nc, nrhs, 0,
+                            nullptr, nullptr, nullptr, cfg);
+      widen_f64(s, n, b32.get(), r.get());
+      DL_HIP(hipStreamSynchronize(s));
+    }
+    fields_out(op, r.get(), out, nrhs, mem);
+    return DL_OK;
+  });
+}
+
 int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* avg_ms, double* bytes) {
   return guard([&] {
     need(op && avg_ms, "NULL argument");

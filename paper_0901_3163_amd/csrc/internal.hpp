@@ -136,10 +136,13 @@ void unpack_spinor(hipStream_t s, const Lattice& lat, const double2* tiled, doub
 void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, double2* tiled);
 
 // ---- launchers: Wilson operator ------------------------------------------------
-// Launch shape of the stencil: variant = (threads per block, occupancy hint) among
-// {(256,2), (128,2), (512,1), (256,1)}; order = block order (0: rhs fastest, XCD-contiguous;
-// 1: sites fastest, XCD-contiguous; 2: rhs fastest, hardware order).  Chosen by the autotuner.
-constexpr int kWilsonVariants = 4;
+// Launch shape of the stencil: variant 0-3 = one thread per site with (threads per block,
+// occupancy hint) among {(256,2), (128,2), (512,1), (256,1)}; 4-6 = one thread per (x,y,z)
+// site marching through time chunks of 4, 8, 16 slices; 7-10 = the marching form with 64
+// sites per block, links staged in LDS and shared by (rhs per block, T) = (4, 8), (4, 16),
+// (8, 8), (2, 8); order = block order (0: rhs fastest, XCD-contiguous; 1: sites fastest,
+// XCD-contiguous; 2: rhs fastest, hardware order).  Chosen by the autotuner.
+constexpr int kWilsonVariants = 11;
 constexpr int kWilsonOrders = 3;
 struct WilsonCfg {
   int variant = 0;
@@ -170,5 +173,7 @@ void sum_partials(hipStream_t s, const double* part, int nparts, int width, doub
 
 void copy(hipStream_t s, long n, const double2* a, double2* b);
 void zero(hipStream_t s, long n, double2* a);
+void round_f32(hipStream_t s, long n, const double2* a, float2* b);  // b = (float) a
+void widen_f64(hipStream_t s, long n, const float2* a, double2* b);  // b = (double) a
 
 }  // namespace dl

@@ -8,7 +8,8 @@
 // (T_{+mu} a)(x) = U_mu(x) a(x + mu) and (T_{-mu} a)(x) = U_mu(x - mu)^dag a(x - mu),
 // optionally followed by f(z) = z / sqrt(1 + |z|^2) per site and channel (|z| the
 // gauge-invariant colour norm).  Widths 4 -> 16 -> 16 -> 4; the input is scaled by
-// 1/s with s = ||b|| / sqrt(V) and the output by s, so net(c b) = c net(b).
+// 1/s with s the root-mean-square site norm of b over its nonzero sites and the output
+// by s, so net(c b) = c net(b) and point and extended sources both enter at unit scale.
 //
 // Backward pass: the adjoint of T_h is T_{-h} and channel mixing commutes with the
 // transport, so the data gradient is the forward kernel with W'_{-h} = W_h^H.  The
@@ -264,18 +265,32 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// per-item ||a||^2 partials of FP64 fields, part[item * gridDim.x + block]
-__global__ void __launch_bounds__(kBlock) k_norm2_items_f64(const double2* __restrict__ a, long n,
-                                                              double* __restrict__ part) {
+// Per item: ||b||^2 partials (part[item * gridDim.x + block]) and partial counts of the sites
+// where b is nonzero (part[(nitems + item) * gridDim.x + block]); thread = site of the tiled field.
+__global__ void __launch_bounds__(kBlock) k_site_stats(const double2* __restrict__ a, long nc, long Vpad,
+                                                         int nitems, double* __restrict__ part) {
   const int item = blockIdx.y;
-  double acc = 0.0;
-  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-    const double2 v = a[item * n + i];
-    acc += v.x * v.x + v.y * v.y;
+  a += item * nc;
+  double acc = 0.0, cnt = 0.0;
+  for (long site = (long)blockIdx.x * kBlock + threadIdx.x; site < Vpad; site += (long)gridDim.x * kBlock) {
+    const long base = (site >> 6) * (kSpin * kTile) + (site & 63);
+    double n2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < kSpin; ++c) {
+      const double2 v = a[base + c * kTile];
+      n2 += v.x * v.x + v.y * v.y;
+    }
+    acc += n2;
+    cnt += n2 > 0.0 ? 1.0 : 0.0;
   }
   __shared__ double lds[kBlock / 64];
   const double s = block_sum<kBlock>(acc, lds);
-  if (threadIdx.x == 0) part[(long)item * gridDim.x + blockIdx.x] = s;
+  __syncthreads();
+  const double c = block_sum<kBlock>(cnt, lds);
+  if (threadIdx.x == 0) {
+    part[(long)item * gridDim.x + blockIdx.x] = s;
+    part[(long)(nitems + item) * gridDim.x + blockIdx.x] = c;
+  }
 }
 // per-item ||a||^2 partials of FP32 fields
 __global__ void __launch_bounds__(kBlock) k_norm2_items_f32(const float2* __restrict__ a, long n,
@@ -290,16 +305,21 @@ __global__ void __launch_bounds__(kBlock) k_norm2_items_f32(const float2* __rest
   const double s = block_sum<kBlock>(acc, lds);
   if (threadIdx.x == 0) part[(long)item * gridDim.x + blockIdx.x] = s;
 }
-// s[item] = sqrt(sum of partials / V), inv_s = 1/s (0 for a zero field); one thread per item
-__global__ void k_net_scales(const double* __restrict__ part, int nparts, int nitems, double V, double* s,
-                             double* inv_s) {
+// Input scale per item: the root-mean-square site norm over the sites where b is nonzero,
+// s = sqrt(||b||^2 / n_nonzero), inv_s = 1/s (0 for b = 0), bn2 = ||b||^2; one thread per item.
+__global__ void k_net_scales(const double* __restrict__ part, int nparts, int nitems, double* s, double* inv_s,
+                             double* bn2) {
   const int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= nitems) return;
-  double t = 0.0;
-  for (int g = 0; g < nparts; ++g) t += part[(long)it * nparts + g];
-  const double sv = sqrt(t / V);
+  double t = 0.0, c = 0.0;
+  for (int g = 0; g < nparts; ++g) {
+    t += part[(long)it * nparts + g];
+    c += part[(long)(nitems + it) * nparts + g];
+  }
+  const double sv = c > 0.0 ? sqrt(t / c) : 0.0;
   s[it] = sv;
   inv_s[it] = sv > 0.0 ? 1.0 / sv : 0.0;
+  bn2[it] = t;
 }
 // b32 = (float)(b64 * sc[item])
 __global__ void k_to_f32_scaled(const double2* __restrict__ a, float2* __restrict__ b, long n,
@@ -333,6 +353,7 @@ __global__ void k_scale_items_f32(float2* a, long n, const float* __restrict__ s
 }
 
 constexpr int kStreamBlocks = 512;  // blocks per item of the streaming kernels here
+constexpr int kStatBlocks = 128;    // blocks per item of the site statistics
 constexpr int kWgradBlocks = 64;    // chunk groups of the weight-gradient kernel
 
 long act_len(const Lattice& lat, int C) { return lat.ntiles * kTile * C * 3; }
@@ -390,9 +411,10 @@ void forward(dl_net* net, dl_op* op, int nitems, const double2* B, float2* Y, bo
   a.ensure(lat, nitems);
   const float2* U = op_links32_public(op);
   const long n = lat.nc;
-  hipLaunchKernelGGL(k_norm2_items_f64, dim3(kStreamBlocks, nitems), dim3(kBlock), 0, s, B, n, a.part.get());
-  hipLaunchKernelGGL(k_net_scales, dim3((nitems + 63) / 64), dim3(64), 0, s, a.part.get(), kStreamBlocks, nitems,
-                     (double)lat.V, a.s.get(), a.inv_s.get());
+  hipLaunchKernelGGL(k_site_stats, dim3(kStatBlocks, nitems), dim3(kBlock), 0, s, B, n, lat.ntiles * kTile, nitems,
+                     a.part.get());
+  hipLaunchKernelGGL(k_net_scales, dim3((nitems + 63) / 64), dim3(64), 0, s, a.part.get(), kStatBlocks, nitems,
+                     a.s.get(), a.inv_s.get(), a.bn2.get());
   hipLaunchKernelGGL(k_to_f32_scaled, dim3(kStreamBlocks, nitems), dim3(256), 0, s, B, a.a0.get(), n,
                      (const double*)a.inv_s.get());
   DL_HIP(hipGetLastError());
@@ -437,6 +459,7 @@ void NetActs::ensure(const Lattice& lat, int nitems) {
   part.alloc((size_t)nitems * std::max<size_t>(wg, kStreamBlocks));
   s.alloc(nitems);
   inv_s.alloc(nitems);
+  bn2.alloc(nitems);
   gsc.alloc(nitems);
 }
 
@@ -456,21 +479,22 @@ double net_loss_grad(dl_net* net, dl_op* op, int nitems, const double2* B, const
   a.ensure(lat, nitems);
   const float2* U = op_links32_public(op);
   forward(net, op, nitems, B, a.y.get(), grad);
-  // d = net(b) - x; r = M d; loss = mean ||r||^2 / ||b||^2 with ||b||^2 = V s^2
+  // d = net(b) - x; r = M d; loss = mean ||r||^2 / ||b||^2
   hipLaunchKernelGGL(k_sub_f32_f64, dim3(kStreamBlocks, nitems), dim3(256), 0, s, a.y.get(), X, a.g4.get(), n);
   wilson_batched<float>(s, lat, U, op->kappa, 0, a.g4.get(), a.r.get(), n, nitems, 0, nullptr, nullptr, nullptr,
                         wilson_cfg(op, DL_FP32, nitems));
   hipLaunchKernelGGL(k_norm2_items_f32, dim3(kStreamBlocks, nitems), dim3(kBlock), 0, s, a.r.get(), n, a.part.get());
-  std::vector<double> hr((size_t)kStreamBlocks * nitems), hs(nitems);
+  std::vector<double> hr((size_t)kStreamBlocks * nitems), hs(nitems), hb(nitems);
   DL_HIP(hipMemcpyAsync(hr.data(), a.part.get(), hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   DL_HIP(hipMemcpyAsync(hs.data(), a.s.get(), nitems * sizeof(double), hipMemcpyDeviceToHost, s));
+  DL_HIP(hipMemcpyAsync(hb.data(), a.bn2.get(), nitems * sizeof(double), hipMemcpyDeviceToHost, s));
   DL_HIP(hipStreamSynchronize(s));
   double L = 0.0;
   std::vector<float> gsc(nitems);
   for (int it = 0; it < nitems; ++it) {
     double rr = 0.0;
     for (int g = 0; g < kStreamBlocks; ++g) rr += hr[(size_t)it * kStreamBlocks + g];
-    const double bn2 = (double)lat.V * hs[it] * hs[it];
+    const double bn2 = hb[it];
     if (bn2 == 0.0) fail(DL_E_INVALID, "training pair with b = 0");
     L += rr / bn2 / nitems;
     // dL/dy = 2 M^dag r / (||b||^2 nitems) and y = s a3, so dL/da3 = s dL/dy

@@ -17,7 +17,7 @@ struct NetActs {
   DBuf<float2> a0, z1, a1, z2, a2;   // input / pre-activations / activations
   DBuf<float2> g16a, g16b, g4, y, r; // gradients and loss work
   DBuf<double> part;                 // reduction partials
-  DBuf<double> s, inv_s;             // per-item input scale s = ||b|| / sqrt(V) and 1/s
+  DBuf<double> s, inv_s, bn2;        // per-item input scale s (RMS site norm over the support), 1/s, ||b||^2
   DBuf<float> gsc;                   // per-item gradient scale of the loss
   void ensure(const Lattice& lat, int nitems);
 };

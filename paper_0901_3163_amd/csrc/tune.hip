@@ -128,6 +128,7 @@ WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) 
     for (int o = 0; o < kWilsonOrders; ++o) {
       if (nrhs == 1 && o == 1) continue;  // identical to order 0 for one rhs
       const WilsonCfg c{v, o};
+      if (wilson_nbs(lat, c) > kMaxPartials) continue;  // the fused reductions need the partials
       double t;
       if (prec == DL_FP64)
         t = time_cfg<double>(op, op->U.get(), in.get(), out.get(), nrhs, c, reps, a, b);
@@ -156,6 +157,12 @@ WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) 
 }
 
 WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs) {
+  // DEFLAN_WILSON_VARIANT=v or v,o forces a launch shape (checked on every call)
+  if (const char* e = std::getenv("DEFLAN_WILSON_VARIANT")) {
+    int v = -1, o = 0;
+    if (std::sscanf(e, "%d,%d", &v, &o) >= 1 && v >= 0 && v < kWilsonVariants && o >= 0 && o < kWilsonOrders)
+      return WilsonCfg{v, o};
+  }
   const int okey = prec * 100000 + nrhs;
   auto oc = op->wcfg.find(okey);
   if (oc != op->wcfg.end()) return oc->second;

@@ -28,6 +28,8 @@
 #include "internal.hpp"
 #include "cplx.hpp"
 
+#include <algorithm>
+
 namespace dl {
 
 // Element offsets are signed 32-bit ints (a field holds far fewer than 2^31
@@ -102,20 +104,9 @@ __device__ __forceinline__ void reconstruct_mu(int mu, C acc[12], const C g[6]) 
   }
 }
 
-// One hop in direction mu (runtime): load the neighbour spinor and the link,
-// project, multiply by U (forward) or U^dag (backward, link taken at the
-// neighbour), rebuild and accumulate.  Every load address depends on mu, so
-// the loads of different directions cannot be hoisted ahead of each other.
-template <int S, bool DAG, class C>
-__device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int lsite, C acc[12]) {
-  C p[12], h[6], g[6], u[9];
-  const C* pp = in + sp_base(nb);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
-  const C* up = U + lk_base(lsite, mu);
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
-  project_mu<S>(mu, p, h);
+// g = U h (DAG false) or U^dag h (DAG true) on a half spinor (two colour vectors).
+template <bool DAG, class C>
+__device__ __forceinline__ void mul_half(const C u[9], const C h[6], C g[6]) {
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -132,7 +123,28 @@ __device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int
       }
       g[s * 3 + a] = r;
     }
+}
+
+// One hop in direction mu (runtime): load the neighbour spinor and the link (its 9
+// components at up[e * ustride]), project, multiply by U (forward) or U^dag (backward,
+// link taken at the neighbour), rebuild and accumulate.  Every load address depends on
+// mu, so the loads of different directions cannot be hoisted ahead of each other.
+template <int S, bool DAG, class C>
+__device__ __forceinline__ void hop_at(const C* up, int ustride, const C* in, int mu, int nb, C acc[12]) {
+  C p[12], h[6], g[6], u[9];
+  const C* pp = in + sp_base(nb);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = up[e * ustride];
+  project_mu<S>(mu, p, h);
+  mul_half<DAG>(u, h, g);
   reconstruct_mu<S>(mu, acc, g);
+}
+
+template <int S, bool DAG, class C>
+__device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int lsite, C acc[12]) {
+  hop_at<S, DAG>(U + lk_base(lsite, mu), kTile, in, mu, nb, acc);
 }
 
 // WHICH: 0 M, 1 M^dag, 2 gamma5 M.  RED: 0 none, 1 ||out||^2, 2 Re<in, out> (partials in FP64,
@@ -207,8 +219,288 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
   }
 }
 
-// Launch-shape variants: (threads per block, occupancy hint).
-static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256};
+// t-marching form of the same operator.  A thread owns one (x, y, z) site and walks
+// T consecutive time slices t0 .. t0+T-1 of it.  The forward-t neighbour psi(t+1)
+// loaded at step t is the centre spinor of step t+1, and the backward-t hop of step
+// t+1, U_t(t)^dag (1 + S g_t) psi(t), is formed at step t from the centre spinor and
+// the forward link U_t(t) already in registers.  Every spinor and link is therefore
+// read once along t; the x, y, z neighbours lie in the same time slice, which the
+// blocks of one XCD walk together, so they come from L2.  A block is NT consecutive
+// (x, y, z) sites of one time chunk of one right-hand side; logical block = (site block,
+// rhs) with the same order options as k_wilson.
+template <class R, int WHICH, int RED, int NT>
+__global__ void __launch_bounds__(NT)
+k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
+            typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+            int Lt, long V, long Vpad, int T, int nb3, int nbs, int order, const double* __restrict__ scale,
+            const int* __restrict__ active, double* __restrict__ part) {
+  using C = typename CT<R>::type;
+  const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int rhs = order == 1 ? lb / nbs : lb % nrhs;
+  const int sb = order == 1 ? lb % nbs : lb / nrhs;
+  if (active && !active[rhs]) return;
+  in += rhs * fstride;
+  out += rhs * fstride;
+  const int b3 = sb % nb3, tc = sb / nb3;
+  const int V3 = Lx * Ly * Lz;
+  const int s3 = b3 * NT + (int)threadIdx.x;
+  double red = 0.0;
+  if (b3 == 0 && (tc + 1) * T >= Lt) {
+    // padding sites of the last tile are kept at zero (written by the last chunk's first block)
+    for (long sp = V + threadIdx.x; sp < Vpad; sp += NT) {
+      C* op = out + sp_base((int)sp);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
+    }
+  }
+  if (s3 < V3) {
+    const int x = s3 % Lx;
+    const int y = (s3 / Lx) % Ly;
+    const int z = s3 / (Lx * Ly);
+    const int sy = Lx, sz = Lx * Ly;
+    const int fx = x == Lx - 1 ? 1 - Lx : 1, bx = x == 0 ? Lx - 1 : -1;
+    const int fy = y == Ly - 1 ? (1 - Ly) * sy : sy, by = y == 0 ? (Ly - 1) * sy : -sy;
+    const int fz = z == Lz - 1 ? (1 - Lz) * sz : sz, bz = z == 0 ? (Lz - 1) * sz : -sz;
+    constexpr int SF = (WHICH == 1) ? 1 : -1;  // forward projector 1 + SF g_mu, backward 1 - SF g_mu
+    const int t0 = tc * T;
+    const int t1 = t0 + T < Lt ? t0 + T : Lt;
+    const R sc = scale ? (R)scale[rhs] : (R)1;
+    const R mk = (R)(-kappa);
+    // carried state: centre spinor of the current slice and the backward-t hop into it
+    C cen[12], gb[6];
+    {
+      const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+      const int sprev = tp * V3 + s3;
+      C p[12], h[6], u[9];
+      const C* pp = in + sp_base(sprev);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+      const C* up = U + lk_base(sprev, 3);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+      project<3, -SF>(p, h);
+      mul_half<true>(u, h, gb);
+      const C* cp = in + sp_base(t0 * V3 + s3);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) cen[c] = cp[c * kTile];
+    }
+#pragma unroll 1
+    for (int t = t0; t < t1; ++t) {
+      const int site = t * V3 + s3;
+      C acc[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = CT<R>::make(0, 0);
+#pragma unroll 1
+      for (int mu = 0; mu < 3; ++mu) {
+        const int df = mu == 0 ? fx : mu == 1 ? fy : fz;
+        const int db = mu == 0 ? bx : mu == 1 ? by : bz;
+        hop<SF, false>(U, in, mu, site + df, site, acc);
+        hop<-SF, true>(U, in, mu, site + db, site + db, acc);
+      }
+      // forward t: psi(t+1) is the next centre; U_t(t) also forms the next backward hop.
+      // The hops are accumulated in k_wilson's order (x+, x-, y+, y-, z+, z-, t+, t-) with
+      // the same arithmetic, so both kernels give the same result.
+      const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
+      C nx[12], u[9];
+      {
+        const C* pp = in + sp_base(snext);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) nx[c] = pp[c * kTile];
+        const C* up = U + lk_base(site, 3);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+        C h[6], g[6];
+        project<3, SF>(nx, h);
+        mul_half<false>(u, h, g);
+        reconstruct<3, SF>(acc, g);
+        // backward t: the hop carried from the previous slice
+        reconstruct<3, -SF>(acc, gb);
+        project<3, -SF>(cen, h);
+        mul_half<true>(u, h, gb);
+      }
+      C* op = out + sp_base(site);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const C p = cen[c];
+        C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
+        if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
+        op[c * kTile] = r;
+        if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
+        if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) cen[c] = nx[c];
+    }
+  }
+  if (RED != 0) {
+    __shared__ double lds[NT / 64];
+    const double s = block_sum<NT>(red, lds);
+    if (threadIdx.x == 0) part[(long)rhs * nbs + sb] = s;
+  }
+}
+
+// Multi-rhs time-marching form: a block is 64 consecutive (x, y, z) sites (one wave per
+// rhs) of one time chunk for RB right-hand sides.  At each time slice the block stages
+// the seven links its sites use from that slice (U_x, U_y, U_z at x, at x - mu for the
+// backward hops, and U_t at x) in LDS once, and all RB waves read them from there, so a
+// link leaves L2 once per RB right-hand sides instead of once per right-hand side.  The
+// t hops are carried along t as in k_wilson_tm; the arithmetic and its order are the
+// same as in k_wilson.  Logical block = (site block, rhs group).
+template <class R, int WHICH, int RED, int RB>
+__global__ void __launch_bounds__(64 * RB)
+k_wilson_tml(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
+             typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+             int Lt, long V, long Vpad, int T, int nb3, int nbs, int ngroups, int order,
+             const double* __restrict__ scale, const int* __restrict__ active, double* __restrict__ part) {
+  using C = typename CT<R>::type;
+  constexpr int kSlots = 7, kL = kSlots * 9 * 64;
+  __shared__ C lu[kL];
+  const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int grp = order == 1 ? lb / nbs : lb % ngroups;
+  const int sb = order == 1 ? lb % nbs : lb / ngroups;
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  const int rhs = grp * RB + w;
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int r = grp * RB + q;
+    any |= r < nrhs && (!active || active[r]);
+  }
+  if (!any) return;  // uniform over the block
+  const bool on = rhs < nrhs && (!active || active[rhs]);
+  const int b3 = sb % nb3, tc = sb / nb3;
+  const int V3 = Lx * Ly * Lz;
+  const int s3 = b3 * 64 + lane;
+  const bool valid = s3 < V3;
+  if (on) {
+    in += rhs * fstride;
+    out += rhs * fstride;
+  }
+  if (on && b3 == 0 && (tc + 1) * T >= Lt) {
+    for (long sp = V + lane; sp < Vpad; sp += 64) {
+      C* op = out + sp_base((int)sp);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
+    }
+  }
+  int x = 0, y = 0, z = 0;
+  if (valid) {
+    x = s3 % Lx;
+    y = (s3 / Lx) % Ly;
+    z = s3 / (Lx * Ly);
+  }
+  const int sy = Lx, sz = Lx * Ly;
+  const int fx = x == Lx - 1 ? 1 - Lx : 1, bx = x == 0 ? Lx - 1 : -1;
+  const int fy = y == Ly - 1 ? (1 - Ly) * sy : sy, by = y == 0 ? (Ly - 1) * sy : -sy;
+  const int fz = z == Lz - 1 ? (1 - Lz) * sz : sz, bz = z == 0 ? (Lz - 1) * sz : -sz;
+  constexpr int SF = (WHICH == 1) ? 1 : -1;
+  const int t0 = tc * T;
+  const int t1 = t0 + T < Lt ? t0 + T : Lt;
+  const R sc = (on && scale) ? (R)scale[rhs] : (R)1;
+  const R mk = (R)(-kappa);
+  const bool work = on && valid;
+  double red = 0.0;
+  C cen[12], gb[6];
+  if (work) {
+    const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+    const int sprev = tp * V3 + s3;
+    C p[12], h[6], u[9];
+    const C* pp = in + sp_base(sprev);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+    const C* up = U + lk_base(sprev, 3);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+    project<3, -SF>(p, h);
+    mul_half<true>(u, h, gb);
+    const C* cp = in + sp_base(t0 * V3 + s3);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) cen[c] = cp[c * kTile];
+  }
+#pragma unroll 1
+  for (int t = t0; t < t1; ++t) {
+    const int site = t * V3 + s3;
+    __syncthreads();  // the previous slice's links are no longer read
+    if (valid) {
+      // slot k: 0-2 U_mu(x), 3-5 U_mu(x - mu) for mu = x, y, z, 6 U_t(x); this thread loads
+      // components of its own lane's site
+      for (int q = w; q < kSlots * 9; q += RB) {
+        const int slot = q / 9, e = q % 9;
+        const int mu = slot < 3 ? slot : slot < 6 ? slot - 3 : 3;
+        const int ls = slot < 3 || slot == 6 ? site : site + (mu == 0 ? bx : mu == 1 ? by : bz);
+        lu[(slot * 9 + e) * 64 + lane] = U[lk_base(ls, mu) + e * kTile];
+      }
+    }
+    __syncthreads();
+    if (work) {
+      C acc[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = CT<R>::make(0, 0);
+#pragma unroll 1
+      for (int mu = 0; mu < 3; ++mu) {
+        const int df = mu == 0 ? fx : mu == 1 ? fy : fz;
+        const int db = mu == 0 ? bx : mu == 1 ? by : bz;
+        hop_at<SF, false>(lu + (mu * 9) * 64 + lane, 64, in, mu, site + df, acc);
+        hop_at<-SF, true>(lu + ((3 + mu) * 9) * 64 + lane, 64, in, mu, site + db, acc);
+      }
+      const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
+      C nx[12], u[9];
+      {
+        const C* pp = in + sp_base(snext);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) nx[c] = pp[c * kTile];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lu[(6 * 9 + e) * 64 + lane];
+        C h[6], g[6];
+        project<3, SF>(nx, h);
+        mul_half<false>(u, h, g);
+        reconstruct<3, SF>(acc, g);
+        reconstruct<3, -SF>(acc, gb);
+        project<3, -SF>(cen, h);
+        mul_half<true>(u, h, gb);
+      }
+      C* op = out + sp_base(site);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const C p = cen[c];
+        C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
+        if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
+        op[c * kTile] = r;
+        if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
+        if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) cen[c] = nx[c];
+    }
+  }
+  if (RED != 0) {
+    red = wave_sum(red);
+    if (lane == 0 && on) part[(long)rhs * nbs + sb] = red;
+  }
+}
+
+// Launch-shape variants.  0-3: k_wilson with (threads per block, occupancy hint)
+// {(256,2), (128,2), (512,1), (256,1)}; 4-6: k_wilson_tm, 256 threads per block, time
+// chunks of T = 4, 8, 16 slices; 7-10: k_wilson_tml with 64 sites per block and
+// (rhs per block, T) = (4, 8), (4, 16), (8, 8), (2, 8).
+static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64};
+static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8};
+static constexpr int kVariantRB[kWilsonVariants] = {0, 0, 0, 0, 0, 0, 0, 4, 4, 8, 2};
+
+static int tm_nb3(const Lattice& lat, int v) {
+  return (lat.L[0] * lat.L[1] * lat.L[2] + kVariantNT[v] - 1) / kVariantNT[v];
+}
+static int tm_chunks(const Lattice& lat, int v) { return (lat.L[3] + kVariantT[v] - 1) / kVariantT[v]; }
+
+template <class R, int WHICH, int RED, int NT>
+static void launch_tm(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
+                      cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+                      double* part, int nbs, int v) {
+  const int* L = lat.L;
+  hipLaunchKernelGGL((k_wilson_tm<R, WHICH, RED, NT>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
+                     kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
+                     order, scale, active, part);
+}
 
 template <class R, int WHICH, int RED, int NT, int OCC>
 static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
@@ -219,6 +511,17 @@ static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, do
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, nbs, order, scale, active, part);
 }
 
+template <class R, int WHICH, int RED, int RB>
+static void launch_tml(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
+                       cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+                       double* part, int nbs, int v) {
+  const int* L = lat.L;
+  const int ngroups = (nrhs + RB - 1) / RB;
+  hipLaunchKernelGGL((k_wilson_tml<R, WHICH, RED, RB>), dim3(nbs * ngroups), dim3(64 * RB), 0, s, U, in, out,
+                     fstride, nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v],
+                     tm_nb3(lat, v), nbs, ngroups, order, scale, active, part);
+}
+
 template <class R, int WHICH, int RED>
 static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa,
                            const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int order,
@@ -227,16 +530,34 @@ static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const
     case 1: launch_one<R, WHICH, RED, 128, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
     case 2: launch_one<R, WHICH, RED, 512, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
     case 3: launch_one<R, WHICH, RED, 256, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    case 4: case 5: case 6:
+      launch_tm<R, WHICH, RED, 256>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      break;
+    case 7: case 8:
+      launch_tml<R, WHICH, RED, 4>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      break;
+    case 9:
+      launch_tml<R, WHICH, RED, 8>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      break;
+    case 10:
+      launch_tml<R, WHICH, RED, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      break;
     default: launch_one<R, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
   }
 }
 
 int wilson_nbs(const Lattice& lat, const WilsonCfg& cfg) {
-  const int nt = kVariantNT[cfg.variant % kWilsonVariants];
+  const int v = cfg.variant % kWilsonVariants;
+  if (kVariantT[v] > 0) return tm_nb3(lat, v) * tm_chunks(lat, v);
+  const int nt = kVariantNT[v];
   return (int)((lat.V + nt - 1) / nt);
 }
 
-int wilson_max_nbs(const Lattice& lat) { return (int)((lat.V + 127) / 128); }
+int wilson_max_nbs(const Lattice& lat) {
+  int m = 0;
+  for (int v = 0; v < kWilsonVariants; ++v) m = std::max(m, wilson_nbs(lat, WilsonCfg{v, 0}));
+  return m;
+}
 
 template <class R>
 int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,

@@ -74,6 +74,7 @@ def _load():
         "dl_solve_next": (I, [P, P, I, P, P, I, D, C.POINTER(dl_next_opts), C.POINTER(dl_stats)]),
         "dl_eig_create": (I, [P, I, P, I, C.POINTER(P)]),
         "dl_bench_wilson": (I, [P, I, I, I, I, C.POINTER(D), C.POINTER(D)]),
+        "dl_apply_batched": (I, [P, I, I, I, P, P, I]),
         "dl_tune_wilson": (I, [P, I, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
         "dl_eig_info": (I, [P, C.POINTER(I), P, P]),
         "dl_eig_vectors": (I, [P, P, I]),
@@ -103,7 +104,7 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_solve_next", "dl_eig_create", "dl_eig_info", "dl_eig_vectors", "dl_eig_destroy",
             "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson",
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
-            "dl_net_apply", "dl_net_loss_grad", "dl_net_train")
+            "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched")
 
 
 def _check(rc):
@@ -247,6 +248,15 @@ class Operator:
         pi, mem = _ptr(psi)
         po, _ = _ptr(out)
         _check(lib.dl_apply(self.h, int(which), pi, po, mem))
+        return out
+
+    def apply_batched(self, which: int, prec: int, Psi):
+        """op(psi_j) for each field of Psi ([n][V][4][3]) by the multi-rhs stencil (FP64 or FP32)."""
+        Psi = _c128(Psi)
+        out = _empty_like(Psi)
+        pi, mem = _ptr(Psi)
+        po, _ = _ptr(out)
+        _check(lib.dl_apply_batched(self.h, int(which), int(prec), int(Psi.shape[0]), pi, po, mem))
         return out
 
     def solve_first(self, b, m: int, k: int, tol: float, eig_tol=None, past_conv_factor=None, max_mvp=None,

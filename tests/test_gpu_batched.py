@@ -85,3 +85,27 @@ def test_batched_rejects_bad_options(gpu_ctx, c1_config):
     with pytest.raises(deflan.DeflanError):
         op.solve_next(B, None, 1e-10, storage=deflan.DL_BF16, batched=1)
     op.close()
+
+
+@pytest.mark.parametrize("variant", [0, 5, 7, 9])
+def test_batched_solver_in_each_stencil_family(gpu_ctx, c1_config, variant, monkeypatch):
+    """The batched FP32 D-MinRes with the stencil forced to one launch shape of each family
+    (per site, time-marching, marching with LDS links for 4 and 8 rhs): active masks, fused
+    reductions and scaling of every family reach tol and the dense solution."""
+    from paper_0901_3163_amd import deflan
+    dims, U, kappa = c1_config["dims"], c1_config["links"], c1_config["kappa"]
+    monkeypatch.setenv("DEFLAN_WILSON_VARIANT", f"{variant},0")
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_G5M)
+    b1 = gaussian_spinor(dims, 100)
+    _, eig, _ = op.solve_first(b1, 60, 20, 1e-10)
+    B = np.stack([gaussian_spinor(dims, 120 + i) for i in range(5)] + [point_source(dims, 9, 1, 0)])
+    X, sts, rc = op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1)
+    assert rc == deflan.DL_OK
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    M = dirac.dense(ora.M, ora.n)
+    for i in range(len(B)):
+        r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+        assert sts[i]["relres"] <= 1e-10 and r <= 1.0001e-10
+        assert _rel(X[i], np.linalg.solve(M, B[i].ravel())) < 1e-6
+    eig.close()
+    op.close()

@@ -127,3 +127,50 @@ def test_tsk_project_and_combine(gpu_ctx, n, nv):
     G = rng.standard_normal((nv, 13))
     Y = deflan.dl_tsk_combine(gpu_ctx, V, G)
     assert _rel(Y, G.T @ V) < 1e-13
+
+
+N_VARIANTS = 11  # stencil launch shapes: 0-3 one thread per site, 4-6 time-marching, 7-10 marching with LDS links
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 16), (16, 16, 16, 32)])
+def test_multi_rhs_apply_every_variant(gpu_ctx, dims, monkeypatch):
+    """The multi-rhs stencil in every launch shape and block order, FP64 and FP32, on 3 fields.
+
+    FP64 agrees with the oracle to 1e-13 (max-norm relative).  FP32 (input and links rounded)
+    agrees to 2e-6: each output sums 8 hops of 2 x 3 complex products, about 100 FP32
+    roundings of O(1) terms, so |error| <~ 100 u max|out| = 6e-6, typically far less.  All
+    launch shapes of one precision give bitwise the same numbers (the same operations in
+    the same order), so time-marching and per-site forms are interchangeable for the tuner.
+    The (3, 5, 7, 6) lattice has 105 sites per time slice (not a multiple of the block) and 6
+    slices (not a multiple of the time chunk); (16, 16, 16, 32) is the benchmark lattice.
+    """
+    from paper_0901_3163_amd import deflan
+    U = su3_links(dims, seed=21)
+    kappa = 0.1371
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_G5M)
+    Psi = np.stack([gaussian_spinor(dims, 30 + i) for i in range(3)])
+    names = {0: "M", 1: "Mdag", 2: "g5M"}
+    big = np.prod(dims) > 100000
+    for which, name in names.items():
+        if big and which == 1:
+            continue
+        ref = np.stack([getattr(ora, name)(p.ravel()).reshape(p.shape) for p in Psi])
+        for prec, tol in ((deflan.DL_FP64, 1e-13), (deflan.DL_FP32, 2e-6)):
+            first = None
+            for v in range(N_VARIANTS):
+                for o in range(3):
+                    if big and o != 0:
+                        continue
+                    monkeypatch.setenv("DEFLAN_WILSON_VARIANT", f"{v},{o}")
+                    got = op.apply_batched(which, prec, Psi)
+                    assert _rel(got, ref) < tol, (dims, name, prec, v, o, _rel(got, ref))
+                    if first is None:
+                        first = got
+                    else:
+                        assert np.array_equal(got, first), (dims, name, prec, v, o)
+    monkeypatch.delenv("DEFLAN_WILSON_VARIANT")
+    # one field alone through the tuned shape equals the batch's first field
+    one = op.apply_batched(2, deflan.DL_FP64, Psi[:1])
+    assert _rel(one[0], ora.g5M(Psi[0].ravel()).reshape(Psi[0].shape)) < 1e-13
+    op.close()

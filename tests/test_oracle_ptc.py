@@ -8,7 +8,7 @@ gauge covariance and to phase and scale equivariance.
 import numpy as np
 import pytest
 
-from lattice_inputs import gaussian_spinor, su3_links, volume
+from lattice_inputs import gaussian_spinor, point_source, su3_links, volume
 from oracle import dirac, ptc
 
 DIMS = (4, 2, 3, 4)
@@ -153,3 +153,20 @@ def test_gradient_matches_central_differences(layer):
     fd = (loss(w + eps * d) - loss(w - eps * d)) / (2 * eps)
     an = np.sum(np.real(G) * np.real(d) + np.imag(G) * np.imag(d))
     assert abs(fd - an) <= 1e-7 * max(abs(fd), 1e-3 * L)
+
+
+def test_input_scale_is_the_rms_over_the_support():
+    V = volume(DIMS)
+    b = gaussian_spinor(DIMS, 30)
+    assert abs(ptc.input_scale(b) - np.sqrt(np.sum(np.abs(b) ** 2) / V)) < 1e-14 * ptc.input_scale(b)
+    p = 2.5 * point_source(DIMS, 7, 1, 2)
+    assert ptc.input_scale(p) == 2.5
+    q = np.zeros_like(b)
+    q[3] = b[3]
+    q[10] = b[10]
+    assert abs(ptc.input_scale(q) ** 2 - (np.sum(np.abs(b[3]) ** 2) + np.sum(np.abs(b[10]) ** 2)) / 2) < 1e-13
+    assert ptc.input_scale(np.zeros_like(b)) == 0.0
+    # a point source reaches the network as a unit delta: its guess is O(1) at the source
+    U = su3_links(DIMS, 31)
+    y = ptc.forward(U, ptc.init_weights(32, scale=1.0), point_source(DIMS, 0, 0, 0), DIMS)
+    assert 1e-2 < np.linalg.norm(y[0]) < 1e2
