@@ -98,7 +98,11 @@ typedef struct {
   int    storage;           /* DL_FP64 (default): plain FP64 D-CG / D-MinRes.
                                DL_FP32 / DL_BF16: low-precision Krylov storage and Dslash,
                                FP32 arithmetic, FP64 reliable updates and FP64 true residual. */
-  int    reliable_every;    /* iterations between FP64 reliable updates (default 50) */
+  int    reliable_every;    /* batched path: the FP32 inner solve restarts from the FP64 residual
+                               b - M x64, with a new projection over the eigenvectors, after each
+                               1e-4 reduction; within such a cycle D-CG also makes a reliable update
+                               every reliable_every iterations (x64 += e, r = b - M x64 in FP64,
+                               search direction kept).  0 = default 50, < 0 = no reliable updates */
   int    batched;           /* 0: one rhs after another; 1: all rhs advance together through
                                the multi-rhs kernels (links read once per site for all rhs) */
   int    x0_given;          /* 1: X holds initial guesses on entry (default 0: x0 = 0) */
@@ -107,6 +111,9 @@ typedef struct {
                                x0 = net(b), then the Galerkin projection; per rhs the library keeps
                                whichever of that and the projection-only start has the smaller
                                true residual ||b - M x0|| (costs one extra projection per rhs) */
+  int    graph;             /* batched path: 1 = replay each block of 8 inner iterations as a
+                               captured HIP graph (fewer launches for small lattices); ignored
+                               while kernel timing (dl_timing) is on.  Default 0. */
 } dl_next_opts;
 
 /* Per-solve statistics. */
@@ -201,6 +208,26 @@ int  dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double*
  * call the library tunes on first use (DEFLAN_AUTOTUNE=0: default shape).
  * variant / order / best_us (may be NULL) receive the choice and its time. */
 int  dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* order, double* best_us);
+
+/* One operator's share of a multi-lattice batch. */
+typedef struct {
+  dl_op*        op;         /* operator (all items: the same context and the same kind) */
+  const dl_eig* eig;        /* eigenvectors of op for the Galerkin projection, or NULL */
+  int           nrhs;       /* right-hand sides of this item (0: the item is skipped) */
+  const double* B;          /* [nrhs][V][4][3] complex128 right-hand sides */
+  double*       X;          /* [nrhs][V][4][3] complex128 solutions (initial guesses if x0_given) */
+  double        tol;        /* relative true-residual target of this item's rhs */
+} dl_batch_item;
+
+/* Later right-hand sides of several operators (lattices of different sizes) solved
+ * together by the batched mixed-precision path (D-CG or D-MinRes as in dl_solve_next,
+ * Section 2): every stage is one launch over all lattices and rhs (a work list), with
+ * per-rhs scalars and convergence masks.  opts NULL: DL_FP32 storage, batched; a non-NULL
+ * opts must ask for DL_FP32 and batched = 1, and no network.  stats (may be NULL) gets
+ * one entry per rhs in item order.  All pointers of all items are host (DL_HOST) or all
+ * device (DL_DEVICE).  Returns DL_NOT_CONVERGED if any rhs missed its tol. */
+int  dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int mem,
+                         const dl_next_opts* opts, dl_stats* stats);
 
 /* out_j = op(in_j) for nrhs fields ([nrhs][V][4][3] complex128), op = M, M^dag or gamma5 M
  * (which = DL_APPLY_M, DL_APPLY_MDAG, DL_APPLY_G5M), by the multi-rhs stencil of the batched

@@ -13,7 +13,13 @@
 // residual estimate has dropped by `inner_drop`, re-projecting over the
 // eigenvectors at every restart.  The inner MinRes / CG runs on the
 // correction e with A e = gamma5 r64 (MinRes) or M e = r64 (CG on the normal
-// equations), and x64 += e closes each cycle.
+// equations), and x64 += e closes each cycle.  The batched CG instead keeps its
+// search direction across FP64 reliable updates (x64 += e, r = b - M x64).
+//
+// A batch may hold several operators (lattices of different sizes): field j of the
+// batch then starts at offs[j] and has length lens[j] (Seg), the stencil runs as one
+// work-list launch over all lattices (wilson_multi), and every other stage is one
+// launch over (block, rhs) pairs whatever lattice the rhs belongs to.
 #include "engine.hpp"
 #include "ptc.hpp"
 #include "cplx.hpp"
@@ -25,6 +31,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 
 namespace dl {
 
@@ -33,6 +40,16 @@ enum {
   B_ALPHA = 0, B_BETA, B_BNEXT, B_COLD, B_SOLD, B_C, B_S, B_ETA, B_TAU, B_DELTA, B_EPS, B_GAMMA,
   B_INV, B_NRM, B_FLAG, B_SS, B_QQ, B_RR, B_CGA, B_CGB, B_NCUR, B_NPREV, NS
 };
+
+// Field layout of a batch: rhs r starts at off[r] and has len[r] complex elements (device
+// tables); off == nullptr means uniform fields of length n at stride n.
+struct Seg {
+  const long* off;
+  const long* len;
+  long n;
+};
+__device__ __forceinline__ long seg_off(const Seg& g, int r) { return g.off ? g.off[r] : (long)r * g.n; }
+__device__ __forceinline__ long seg_len(const Seg& g, int r) { return g.off ? g.len[r] : g.n; }
 
 static int bgrid(long n) {
   long nb = (n + kBlock - 1) / kBlock;
@@ -48,12 +65,12 @@ __device__ __forceinline__ double b_fin_sum(const double* part, int np, double* 
 // ---- FP64 <-> FP32 and residual kernels (grid: (G, nrhs)) -----------------------
 // r = b - y (FP64), partial ||r||^2 column-major [rhs][G]
 __global__ void __launch_bounds__(kBlock)
-k_b_resid(long n, const double2* b, const double2* y, double2* r, const int* __restrict__ active,
+k_b_resid(Seg g, const double2* b, const double2* y, double2* r, const int* __restrict__ active,
           double* __restrict__ part) {
   const int rhs = blockIdx.y;
   double acc = 0.0;
   if (!active || active[rhs]) {
-    const long off = (long)rhs * n;
+    const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
       const double2 v = c_sub(b[off + i], y[off + i]);
       r[off + i] = v;
@@ -82,12 +99,12 @@ __global__ void __launch_bounds__(kBlock) k_b_fin_store(const double* part, int 
 
 // MinRes inner start: v = gamma5 r64 * inv (FP32), vp = d1 = d2 = e = 0; state reset.
 __global__ void __launch_bounds__(kBlock)
-k_b_minres_start(long n, const double2* r64, float2* v, float2* vp, float2* d1, float2* d2, float2* e, double* st,
+k_b_minres_start(Seg g, const double2* r64, float2* v, float2* vp, float2* d1, float2* d2, float2* e, double* st,
                  double* invs, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const double inv = st[rhs * NS + B_INV];
-  const long off = (long)rhs * n;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
     const int c = (int)((i >> 6) % kSpin);
     const double2 x = r64[off + i];
@@ -126,14 +143,14 @@ __global__ void __launch_bounds__(kBlock) k_b_fin_alpha(const double* part, int 
 // Wilson epilogue applied 1/n_j).  un = w - (alpha/n_j) u_j - (beta_j/n_{j-1}) u_{j-1},
 // written over u_{j-1}; partial ||un||^2.
 __global__ void __launch_bounds__(kBlock)
-k_b_lanczos3(long n, const double* st, const float2* u, float2* up, const float2* w, const int* __restrict__ active,
+k_b_lanczos3(Seg g, const double* st, const float2* u, float2* up, const float2* w, const int* __restrict__ active,
              double* __restrict__ part) {
   const int rhs = blockIdx.y;
   double acc = 0.0;
   if (!active || active[rhs]) {
     const double* S = st + rhs * NS;
     const float a = (float)(S[B_ALPHA] / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
-    const long off = (long)rhs * n;
+    const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
       float2 t = c_axpy(-a, u[off + i], w[off + i]);
       t = c_axpy(-b, up[off + i], t);
@@ -193,7 +210,7 @@ k_b_fin_rot(const double* part, int np, double* st, double* invs, const int* act
 
 // d_new = (u_j / n_j - delta d1 - eps d2)/gamma -> dn ; e += tau d_new   (n_j = B_NPREV after the rotation)
 __global__ void __launch_bounds__(kBlock)
-k_b_minres_update(long n, const double* st, const float2* u, const float2* d1, const float2* d2, float2* dn,
+k_b_minres_update(Seg g, const double* st, const float2* u, const float2* d1, const float2* d2, float2* dn,
                   float2* e, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
@@ -201,7 +218,7 @@ k_b_minres_update(long n, const double* st, const float2* u, const float2* d1, c
   const float delta = (float)S[B_DELTA], eps = (float)S[B_EPS], ig = (float)(1.0 / S[B_GAMMA]);
   const float tau = (float)S[B_TAU];
   const float iu = (float)(1.0 / S[B_NPREV]);
-  const long off = (long)rhs * n;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
     float2 d = c_axpy(-delta, d1[off + i], c_scale(u[off + i], iu));
     d = c_axpy(-eps, d2[off + i], d);
@@ -213,10 +230,10 @@ k_b_minres_update(long n, const double* st, const float2* u, const float2* d1, c
 
 // x64 += e (FP32 correction)
 __global__ void __launch_bounds__(kBlock)
-k_b_accum(long n, double2* x, const float2* e, const int* __restrict__ active) {
+k_b_accum(Seg g, double2* x, const float2* e, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
-  const long off = (long)rhs * n;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
     const float2 d = e[off + i];
     x[off + i] = make_double2(x[off + i].x + (double)d.x, x[off + i].y + (double)d.y);
@@ -224,10 +241,10 @@ k_b_accum(long n, double2* x, const float2* e, const int* __restrict__ active) {
 }
 
 // gamma5 on FP64 fields (batched)
-__global__ void __launch_bounds__(kBlock) k_b_gamma5(long n, const double2* in, double2* out, const int* active) {
+__global__ void __launch_bounds__(kBlock) k_b_gamma5(Seg g, const double2* in, double2* out, const int* active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
-  const long off = (long)rhs * n;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
     const int c = (int)((i >> 6) % kSpin);
     const double2 v = in[off + i];
@@ -238,10 +255,10 @@ __global__ void __launch_bounds__(kBlock) k_b_gamma5(long n, const double2* in, 
 // ---- CG on the normal equations (CGLS), FP32 inner -----------------------------------
 // start: r32 = r64 (FP32), e = 0 ; s and p are formed by the caller (s = M^dag r32, p = s).
 __global__ void __launch_bounds__(kBlock)
-k_b_cg_start(long n, const double2* r64, float2* r32, float2* e, double* st, const int* __restrict__ active) {
+k_b_cg_start(Seg g, const double2* r64, float2* r32, float2* e, double* st, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
-  const long off = (long)rhs * n;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
     const double2 x = r64[off + i];
     r32[off + i] = make_float2((float)x.x, (float)x.y);
@@ -265,13 +282,13 @@ __global__ void __launch_bounds__(kBlock) k_b_cg_alpha(const double* part, int n
 
 // e += alpha p ; r -= alpha q ; partial ||r||^2
 __global__ void __launch_bounds__(kBlock)
-k_b_cg_xr(long n, const double* st, const float2* p, const float2* q, float2* e, float2* r,
+k_b_cg_xr(Seg g, const double* st, const float2* p, const float2* q, float2* e, float2* r,
           const int* __restrict__ active, double* __restrict__ part) {
   const int rhs = blockIdx.y;
   double acc = 0.0;
   if (!active || active[rhs]) {
     const float a = (float)st[rhs * NS + B_CGA];
-    const long off = (long)rhs * n;
+    const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
       e[off + i] = c_axpy(a, p[off + i], e[off + i]);
       const float2 v = c_axpy(-a, q[off + i], r[off + i]);
@@ -304,19 +321,36 @@ k_b_cg_beta(const double* ps, int nps, const double* pr, int npr, double* st, co
 
 // p = s + beta p
 __global__ void __launch_bounds__(kBlock)
-k_b_cg_xpay(long n, const double* st, const float2* s, float2* p, const int* __restrict__ active) {
+k_b_cg_xpay(Seg g, const double* st, const float2* s, float2* p, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const float b = (float)st[rhs * NS + B_CGB];
-  const long off = (long)rhs * n;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
     p[off + i] = c_axpy(b, p[off + i], s[off + i]);
 }
 
-__global__ void k_b_copy_f32(long n, const float2* a, float2* b, const int* active) {
+// partial ||a||^2 of FP32 fields, column-major [rhs][G]
+__global__ void __launch_bounds__(kBlock)
+k_b_norm2_f32(Seg g, const float2* a, const int* __restrict__ active, double* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  double acc = 0.0;
+  if (!active || active[rhs]) {
+    const long off = seg_off(g, rhs), n = seg_len(g, rhs);
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+      const float2 v = a[off + i];
+      acc = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, acc));
+    }
+  }
+  __shared__ double lds[kBlock / 64];
+  const double s = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) part[(long)rhs * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_b_copy_f32(Seg g, const float2* a, float2* b, const int* active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
-  const long off = (long)rhs * n;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     b[off + i] = a[off + i];
 }
@@ -327,21 +361,64 @@ static double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-struct Batch {
+// One operator of a batch and its right-hand sides [r0, r0 + nr).
+struct BItem {
   dl_op* op;
+  const dl_eig* eig;
+  int r0, nr;
+  double tol;
+};
+
+struct Batch {
+  std::vector<BItem> items;
+  dl_ctx* ctx;
   int nr;
-  long n;
   hipStream_t s;
+  std::vector<long> h_off, h_len;
+  DBuf<long> d_off, d_len;
+  long total = 0, nmax = 0;
+  Seg seg{};
   DBuf<double> st, part, part2;
   DBuf<int> active;
   DBuf<double> invs;  // per-rhs 1/n_j, the Wilson epilogue scale of the unnormalised Lanczos vector
   std::vector<int> h_active;
   std::vector<double> h_st;
+  std::vector<int> item_of;  // rhs -> item
   int G;
-  Batch(dl_op* o, int nrhs) : op(o), nr(nrhs), n(o->lat.nc), s(o->ctx->stream) {
+  // multi-lattice stencil work lists (FP32 and FP64 links)
+  DBuf<WilsonItem> wl32, wl64;
+  int ml_blocks = 0, ml_pstride = 0;
+
+  explicit Batch(const std::vector<BItem>& its) : items(its), ctx(its[0].op->ctx), s(its[0].op->ctx->stream) {
+    nr = 0;
+    for (const auto& it : items) nr += it.nr;
+    item_of.resize(nr);
+    for (size_t i = 0; i < items.size(); ++i) {
+      const BItem& it = items[i];
+      for (int r = 0; r < it.nr; ++r) {
+        item_of[it.r0 + r] = (int)i;
+        h_off.push_back(total);
+        h_len.push_back(it.op->lat.nc);
+        total += it.op->lat.nc;
+      }
+      nmax = std::max(nmax, it.op->lat.nc);
+    }
+    if (single()) {
+      seg = Seg{nullptr, nullptr, nmax};
+    } else {
+      d_off.alloc(nr);
+      d_len.alloc(nr);
+      DL_HIP(hipMemcpyAsync(d_off.get(), h_off.data(), nr * sizeof(long), hipMemcpyHostToDevice, s));
+      DL_HIP(hipMemcpyAsync(d_len.get(), h_len.data(), nr * sizeof(long), hipMemcpyHostToDevice, s));
+      seg = Seg{d_off.get(), d_len.get(), nmax};
+      build_worklists();
+    }
     st.alloc((size_t)nr * NS);
-    G = bgrid(n);
-    const size_t np = (size_t)nr * std::max(G, wilson_max_nbs(op->lat));
+    G = bgrid(nmax);
+    int pw = G;
+    for (const auto& it : items) pw = std::max(pw, wilson_max_nbs(it.op->lat));
+    pw = std::max(pw, ml_pstride);
+    const size_t np = (size_t)nr * pw;
     part.alloc(np);
     part2.alloc(np);
     active.alloc(nr);
@@ -350,7 +427,10 @@ struct Batch {
     h_st.resize((size_t)nr * NS);
     static_assert(NS % 2 == 0, "state rows are cleared as double2");
     zero(s, (long)nr * NS / 2, reinterpret_cast<double2*>(st.get()));
+    DL_HIP(hipStreamSynchronize(s));
   }
+  bool single() const { return items.size() == 1; }
+  void build_worklists();
   void push_active() {
     DL_HIP(hipMemcpyAsync(active.get(), h_active.data(), nr * sizeof(int), hipMemcpyHostToDevice, s));
     DL_HIP(hipStreamSynchronize(s));
@@ -365,6 +445,16 @@ struct Batch {
     for (int v : h_active) a += v;
     return a;
   }
+  // algorithmic stencil bytes of the active rhs: links once per site and lattice, spinors per rhs
+  double wilson_bytes(double link_b, double spinor_b) const {
+    double b = 0.0;
+    for (const auto& it : items) {
+      int na = 0;
+      for (int r = 0; r < it.nr; ++r) na += h_active[it.r0 + r];
+      if (na) b += (double)it.op->lat.V * (link_b + spinor_b * na);
+    }
+    return b;
+  }
 };
 
 __global__ void k_f64_to_f32(long n, const double2* a, float2* b) {
@@ -373,8 +463,6 @@ __global__ void k_f64_to_f32(long n, const double2* a, float2* b) {
 }
 
 // FP32 copy of the links, made on first use and kept with the operator.
-const float2* op_links32_public(dl_op* op);
-static const float2* op_links32(dl_op* op) { return op_links32_public(op); }
 const float2* op_links32_public(dl_op* op) {
   if (!op->U32.get()) {
     op->U32.alloc(op->lat.nl);
@@ -385,89 +473,187 @@ const float2* op_links32_public(dl_op* op) {
   return op->U32.get();
 }
 
-static int wilson32(dl_op* op, int which, const float2* in, float2* out, int nr, int nact, int red, double* part,
-                    const int* active, const double* scale = nullptr) {
-  const WilsonCfg cfg = wilson_cfg(op, DL_FP32, nr);
-  // algorithmic bytes: links once per site (288 B FP32) + input and output spinor per active rhs (192 B)
-  TimeScope ts(op->ctx, T_WILSON, (double)op->lat.V * (288.0 + 192.0 * nact));
-  return wilson_batched<float>(op->ctx->stream, op->lat, op_links32(op), op->kappa, which, in, out, op->lat.nc, nr,
-                               red, scale, active, part, cfg);
+void Batch::build_worklists() {
+  std::vector<WilsonItem> w32, w64;
+  int block0 = 0;
+  for (const auto& it : items) {
+    const Lattice& lat = it.op->lat;
+    WilsonItem w{};
+    w.kappa = it.op->kappa;
+    for (int d = 0; d < 4; ++d) w.L[d] = lat.L[d];
+    w.V = lat.V;
+    w.Vpad = lat.ntiles * kTile;
+    w.rhs0 = it.r0;
+    w.nrhs = it.nr;
+    w.nbs = (int)((lat.V + 255) / 256);
+    w.block0 = block0;
+    block0 += w.nbs * w.nrhs;
+    ml_pstride = std::max(ml_pstride, w.nbs);
+    w.U = op_links32_public(it.op);
+    w32.push_back(w);
+    w.U = it.op->U.get();
+    w64.push_back(w);
+  }
+  if (ml_pstride > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
+  ml_blocks = block0;
+  wl32.alloc(w32.size());
+  wl64.alloc(w64.size());
+  DL_HIP(hipMemcpyAsync(wl32.get(), w32.data(), w32.size() * sizeof(WilsonItem), hipMemcpyHostToDevice, s));
+  DL_HIP(hipMemcpyAsync(wl64.get(), w64.data(), w64.size() * sizeof(WilsonItem), hipMemcpyHostToDevice, s));
+  DL_HIP(hipStreamSynchronize(s));
 }
 
-static void wilson64b(dl_op* op, int which, const double2* in, double2* out, int nr, int nact, const int* active) {
-  const WilsonCfg cfg = wilson_cfg(op, DL_FP64, nr);
-  TimeScope ts(op->ctx, T_WILSON, (double)op->lat.V * (576.0 + 384.0 * nact));
-  wilson_batched<double>(op->ctx->stream, op->lat, op->U.get(), op->kappa, which, in, out, op->lat.nc, nr, 0,
-                         nullptr, active, nullptr, cfg);
+// FP32 stencil over the whole batch; returns the partial stride per rhs of the fused reduction.
+static int bwilson32(Batch& bt, int which, const float2* in, float2* out, int red, double* part,
+                     const double* scale = nullptr) {
+  TimeScope ts(bt.ctx, T_WILSON, bt.wilson_bytes(288.0, 192.0));
+  if (bt.single()) {
+    dl_op* op = bt.items[0].op;
+    const WilsonCfg cfg = wilson_cfg(op, DL_FP32, bt.nr);
+    const int nbs = wilson_batched<float>(bt.s, op->lat, op_links32_public(op), op->kappa, which, in, out, op->lat.nc,
+                                          bt.nr, red, scale, bt.active.get(), part, cfg);
+    return nbs;
+  }
+  wilson_multi<float>(bt.s, bt.wl32.get(), (int)bt.items.size(), bt.ml_blocks, bt.ml_pstride, which, in, out,
+                      bt.d_off.get(), red, scale, bt.active.get(), part);
+  return red ? bt.ml_pstride : 0;
+}
+
+static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
+  TimeScope ts(bt.ctx, T_WILSON, bt.wilson_bytes(576.0, 384.0));
+  if (bt.single()) {
+    dl_op* op = bt.items[0].op;
+    const WilsonCfg cfg = wilson_cfg(op, DL_FP64, bt.nr);
+    wilson_batched<double>(bt.s, op->lat, op->U.get(), op->kappa, which, in, out, op->lat.nc, bt.nr, 0, nullptr,
+                           bt.active.get(), nullptr, cfg);
+    return;
+  }
+  wilson_multi<double>(bt.s, bt.wl64.get(), (int)bt.items.size(), bt.ml_blocks, bt.ml_pstride, which, in, out,
+                       bt.d_off.get(), 0, nullptr, bt.active.get(), nullptr);
 }
 
 // r64 = b - M x64 for active rhs; refreshes st[B_RR], st[B_NRM], st[B_INV].
 static void true_residual(Batch& bt, const double2* B, const double2* X, double2* R, double2* T) {
-  dl_op* op = bt.op;
-  wilson64b(op, 0, X, T, bt.nr, bt.n_active(), bt.active.get());
-  hipLaunchKernelGGL(k_b_resid, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.n, B, T, R, bt.active.get(),
+  bwilson64(bt, 0, X, T);
+  hipLaunchKernelGGL(k_b_resid, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.seg, B, T, R, bt.active.get(),
                      bt.part.get());
   hipLaunchKernelGGL(k_b_fin_store, dim3(bt.nr), dim3(kBlock), 0, bt.s, bt.part.get(), bt.G, bt.st.get(),
                      (int)B_RR);
   DL_HIP(hipGetLastError());
 }
 
-// Galerkin projection over the eigenvectors for every active rhs: x += Y H^-1 Y^H rA,
-// rA = gamma5 r (G5M) or M^dag r (MDAGM).  T: scratch (nr fields).
-static void project_batch(Batch& bt, const dl_eig* eig, const double2* R, double2* X, double2* T,
-                          DBuf<double2>& cbuf, Scratch& S) {
-  if (!eig || eig->k == 0) return;
-  dl_op* op = bt.op;
-  const int k = eig->k;
-  if (op->kind == DL_G5M)
-    hipLaunchKernelGGL(k_b_gamma5, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.n, R, T, bt.active.get());
+// Galerkin projection over each item's eigenvectors for every active rhs: x += Y H^-1 Y^H rA,
+// rA = gamma5 r (G5M) or M^dag r (MDAGM).  T: scratch (a batch of fields).
+static void project_batch(Batch& bt, const double2* R, double2* X, double2* T, DBuf<double2>& cbuf, Scratch& S) {
+  bool any = false;
+  for (const auto& it : bt.items) any |= it.eig && it.eig->k > 0;
+  if (!any) return;
+  if (bt.items[0].op->kind == DL_G5M)
+    hipLaunchKernelGGL(k_b_gamma5, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.seg, R, T, bt.active.get());
   else
-    wilson64b(op, 1, R, T, bt.nr, bt.n_active(), bt.active.get());
-  for (int r = 0; r < bt.nr; ++r) {
-    if (!bt.h_active[r]) continue;
-    int nb;
-    {
-      TimeScope ts(op->ctx, T_TSK_DOTS);
-      nb = tsk_dots(bt.s, bt.n, k, eig->Y.get(), bt.n, nullptr, T + (long)r * bt.n, S.part.get());
+    bwilson64(bt, 1, R, T);
+  for (const auto& it : bt.items) {
+    if (!it.eig || it.eig->k == 0) continue;
+    dl_op* op = it.op;
+    const int k = it.eig->k;
+    const long n = op->lat.nc;
+    int nact = 0;
+    for (int r = it.r0; r < it.r0 + it.nr; ++r) {
+      if (!bt.h_active[r]) continue;
+      ++nact;
+      int nb;
+      {
+        TimeScope ts(bt.ctx, T_TSK_DOTS);
+        nb = tsk_dots(bt.s, n, k, it.eig->Y.get(), n, nullptr, T + bt.h_off[r], S.part.get());
+      }
+      sum_partials(bt.s, S.part.get(), nb, 2 * k, reinterpret_cast<double*>(cbuf.get() + (long)(r - it.r0) * k));
     }
-    sum_partials(bt.s, S.part.get(), nb, 2 * k, reinterpret_cast<double*>(cbuf.get() + (long)r * k));
-  }
-  {
-    TimeScope ts(op->ctx, T_SMALL);
-    proj_solve(bt.s, k, bt.nr, eig->Zr.get(), eig->lamr.get(), cbuf.get(), cbuf.get() + (long)bt.nr * k);
-  }
-  for (int r = 0; r < bt.nr; ++r) {
-    if (!bt.h_active[r]) continue;
-    TimeScope ts(op->ctx, T_TSK_UPDATE);
-    tsk_update(bt.s, bt.n, k, eig->Y.get(), bt.n, nullptr, cbuf.get() + (long)bt.nr * k + (long)r * k, 1.0,
-               X + (long)r * bt.n);
+    if (!nact) continue;
+    {
+      TimeScope ts(bt.ctx, T_SMALL);
+      proj_solve(bt.s, k, it.nr, it.eig->Zr.get(), it.eig->lamr.get(), cbuf.get(), cbuf.get() + (long)it.nr * k);
+    }
+    for (int r = it.r0; r < it.r0 + it.nr; ++r) {
+      if (!bt.h_active[r]) continue;
+      TimeScope ts(bt.ctx, T_TSK_UPDATE);
+      tsk_update(bt.s, n, k, it.eig->Y.get(), n, nullptr, cbuf.get() + (long)it.nr * k + (long)(r - it.r0) * k, 1.0,
+                 X + bt.h_off[r]);
+    }
   }
 }
 
-int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
-                       const dl_next_opts& o, dl_stats* st) {
+// Instantiated graphs of launch sequences, keyed by a small id; captured from the stream on
+// first use and replayed after.  The captured sequences contain kernel launches only.
+struct GraphCache {
+  hipStream_t s;
+  std::map<int, hipGraphExec_t> exec;
+  std::map<int, hipGraph_t> graph;
+  explicit GraphCache(hipStream_t st) : s(st) {}
+  template <class F>
+  void run(int id, F&& enqueue) {
+    auto it = exec.find(id);
+    if (it == exec.end()) {
+      hipGraph_t gr = nullptr;
+      DL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue();
+      } catch (...) {
+        (void)hipStreamEndCapture(s, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      DL_HIP(hipStreamEndCapture(s, &gr));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        DL_HIP(e);
+      }
+      graph[id] = gr;
+      it = exec.emplace(id, ex).first;
+    }
+    DL_HIP(hipGraphLaunch(it->second, s));
+  }
+  ~GraphCache() {
+    if (!exec.empty()) (void)hipStreamSynchronize(s);
+    for (auto& kv : exec) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : graph) (void)hipGraphDestroy(kv.second);
+  }
+};
+
+// The batched solve over a list of operators.  B, X: all fields of the batch, field r at
+// h_off[r] (tiled FP64).  net: learned initial guess (single operator only).
+static int solve_batch(const std::vector<BItem>& items, const double2* B, double2* X, const dl_next_opts& o,
+                       dl_stats* st) {
   const double t0 = now_s();
-  if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
-    fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
-  Batch bt(op, nrhs);
-  const long n = bt.n;
-  const int nr = nrhs;
+  Batch bt(items);
+  const int nr = bt.nr;
   hipStream_t s = bt.s;
-  const bool mr = op->kind == DL_G5M;
+  if (bt.single()) {
+    // settle the stencil launch shapes (tuning launches kernels) before any graph capture
+    (void)wilson_cfg(items[0].op, DL_FP32, nr);
+    (void)wilson_cfg(items[0].op, DL_FP64, nr);
+  }
+  const bool mr = items[0].op->kind == DL_G5M;
+  int kmax = 1;
+  for (const auto& it : items) kmax = std::max(kmax, it.eig ? it.eig->k : 1);
+  int nrmax = 1;
+  for (const auto& it : items) nrmax = std::max(nrmax, it.nr);
   Scratch S;
   S.sc.alloc(256);
-  S.ensure_part((size_t)2 * std::max(eig ? eig->k : 1, 1) * tsk_nblocks(n) + 64);
-  DBuf<double2> R64((size_t)nr * n), T64((size_t)nr * n);
+  S.ensure_part((size_t)2 * kmax * tsk_nblocks(bt.nmax) + 64);
+  DBuf<double2> R64((size_t)bt.total), T64((size_t)bt.total);
   DBuf<float2> f[6];
-  for (auto& b : f) b.alloc((size_t)nr * n);
-  DBuf<double2> cbuf(2 * (size_t)nr * std::max(eig ? eig->k : 1, 1) + 2);
+  for (auto& b : f) b.alloc((size_t)bt.total);
+  DBuf<double2> cbuf(2 * (size_t)nrmax * kmax + 2);
   std::vector<long> iters(nr, 0), mvp(nr, 0);
-  std::vector<double> bnorm(nr), rel(nr, 1.0);
+  std::vector<double> bnorm(nr), rel(nr, 1.0), tol(nr);
+  for (int r = 0; r < nr; ++r) tol[r] = items[bt.item_of[r]].tol;
   // ||b|| per right-hand side (FP64)
   {
     std::vector<double> h(nr);
     for (int r = 0; r < nr; ++r) {
-      const int nb = norm2_partials(s, n, B + (long)r * n, S.part.get());
+      const int nb = norm2_partials(s, bt.h_len[r], B + bt.h_off[r], S.part.get());
       sum_partials(s, S.part.get(), nb, 1, S.sc.get() + r % 256);
       if (r % 256 == 255 || r == nr - 1) {
         const int cnt = r % 256 + 1;
@@ -480,21 +666,23 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
       bnorm[r] = std::sqrt(h[r]);
     }
   }
+  if (!o.x0_given) zero(s, bt.total, X);
   for (int r = 0; r < nr; ++r) {
     if (bnorm[r] == 0.0) {
       bt.h_active[r] = 0;
-      zero(s, n, X + (long)r * n);
+      zero(s, bt.h_len[r], X + bt.h_off[r]);
       rel[r] = 0.0;
     }
   }
-  if (!o.x0_given) zero(s, (long)nr * n, X);
   bt.push_active();
   // FP64 true residual, projection, FP64 true residual again (X in place, R: its residual)
+  bool any_eig = false;
+  for (const auto& it : items) any_eig |= it.eig && it.eig->k > 0;
   auto start = [&](double2* Xs, double2* Rs) {
     true_residual(bt, B, Xs, Rs, T64.get());
     for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
-    project_batch(bt, eig, Rs, Xs, T64.get(), cbuf, S);
-    if (eig && eig->k > 0) {
+    project_batch(bt, Rs, Xs, T64.get(), cbuf, S);
+    if (any_eig) {
       for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r] * (mr ? 0 : 1);
       true_residual(bt, B, Xs, Rs, T64.get());
       for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
@@ -505,13 +693,15 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
   if (o.net && bt.n_active() > 0) {
     // Learned initial guess: start from net(b) + projection or from the projection alone,
     // whichever has the smaller FP64 true residual.
+    if (!bt.single()) fail(DL_E_INVALID, "the learned initial guess takes one operator per batch");
+    dl_op* op = items[0].op;
     dl_net* net = o.net;
     if (net->ctx != op->ctx) fail(DL_E_INVALID, "network and operator belong to different contexts");
     start(X, R64.get());
     bt.pull_state();
     std::vector<double> rp(nr);
     for (int r = 0; r < nr; ++r) rp[r] = bt.get(r, B_NRM);
-    DBuf<double2> XN((size_t)nr * n), RN((size_t)nr * n);
+    DBuf<double2> XN((size_t)bt.total), RN((size_t)bt.total);
     net_apply(net, op, nr, B, XN.get());
     start(XN.get(), RN.get());
     bt.pull_state();
@@ -519,7 +709,7 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
       if (!bt.h_active[r]) continue;
       if (bt.get(r, B_NRM) < rp[r]) {
         used_net[r] = 1;
-        copy(s, n, XN.get() + (long)r * n, X + (long)r * n);
+        copy(s, bt.h_len[r], XN.get() + bt.h_off[r], X + bt.h_off[r]);
       }
     }
     // residual state of the chosen starts
@@ -534,7 +724,12 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
     }
   }
   const double inner_drop = 1e-4;      // reduction of the inner residual estimate per cycle
-  const int check = 8;
+  const int check = 8;                 // iterations between host checks (even)
+  const Seg g = bt.seg;
+  // Graph replay of the `check`-iteration blocks: off while kernel timing is on (its events
+  // would be captured) and on the legacy null stream (which cannot be captured).
+  const bool use_graph = o.graph != 0 && !bt.ctx->timers.enabled && s != nullptr;
+  GraphCache graphs(s);
   for (int cycle = 0; cycle < 40 && bt.n_active() > 0; ++cycle) {
     if (!(cycle == 0 && started)) start(X, R64.get());
     bt.pull_state();
@@ -542,7 +737,7 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
       if (!bt.h_active[r]) continue;
       rel[r] = bt.get(r, B_NRM) / bnorm[r];
       if (!std::isfinite(rel[r])) fail(DL_E_NONFINITE, "non-finite residual");
-      if (rel[r] <= tol || mvp[r] >= o.max_mvp) bt.h_active[r] = 0;
+      if (rel[r] <= tol[r] || mvp[r] >= o.max_mvp) bt.h_active[r] = 0;
     }
     bt.push_active();
     if (verbose()) {
@@ -557,28 +752,45 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
       std::fflush(stderr);
     }
     if (bt.n_active() == 0) break;
+    // Inner target: a cycle ends after an inner_drop reduction of the residual estimate and the
+    // next one restarts from the FP64 residual with a fresh projection over the eigenvectors.
+    // Running the FP32 recurrence on to tol with reliable updates alone, without re-projection,
+    // took 1.7x the iterations of this scheme on the 4^4 near-critical field: FP32 rounding
+    // feeds the deflated low modes back in and only the projection removes them cheaply.
+    // Within a cycle, CG replaces its residual by the FP64 one every reliable_every iterations
+    // and keeps its search direction (a reliable update).
+    const bool reliable = !mr && o.reliable_every > 0;
     std::vector<double> target(nr);
-    for (int r = 0; r < nr; ++r) target[r] = std::max(inner_drop * bt.get(r, B_NRM), 0.5 * tol * bnorm[r]);
+    for (int r = 0; r < nr; ++r) target[r] = std::max(inner_drop * bt.get(r, B_NRM), 0.5 * tol[r] * bnorm[r]);
     std::vector<int> inner_active = bt.h_active;
     const int G = bt.G;
     if (mr) {
       float2 *u = f[0].get(), *up = f[1].get(), *w = f[2].get(), *d1 = f[3].get(), *d2 = f[4].get(),
              *e = f[5].get();
-      hipLaunchKernelGGL(k_b_minres_start, dim3(G, nr), dim3(kBlock), 0, s, n, R64.get(), u, up, d1, d2, e,
+      hipLaunchKernelGGL(k_b_minres_start, dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), u, up, d1, d2, e,
                          bt.st.get(), bt.invs.get(), bt.active.get());
-      for (int it = 0; it < 100000; ++it) {
-        const int nbs = wilson32(op, 2, u, w, nr, bt.n_active(), 2, bt.part.get(), bt.active.get(), bt.invs.get());
+      // one MinRes iteration; `check` (even) iterations return u, up, d1, d2 to their places,
+      // so a block of them is the same launch sequence every time (replayed as a graph)
+      auto iteration = [&]() {
+        const int nbs = bwilson32(bt, 2, u, w, 2, bt.part.get(), bt.invs.get());
         hipLaunchKernelGGL(k_b_fin_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
                            bt.active.get());
-        hipLaunchKernelGGL(k_b_lanczos3, dim3(G, nr), dim3(kBlock), 0, s, n, bt.st.get(), u, up, w,
+        hipLaunchKernelGGL(k_b_lanczos3, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, up, w,
                            bt.active.get(), bt.part.get());
         hipLaunchKernelGGL(k_b_fin_rot, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), G, bt.st.get(), bt.invs.get(),
                            bt.active.get());
-        hipLaunchKernelGGL(k_b_minres_update, dim3(G, nr), dim3(kBlock), 0, s, n, bt.st.get(), u, d1, d2, d2, e,
+        hipLaunchKernelGGL(k_b_minres_update, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, d1, d2, d2, e,
                            bt.active.get());
         DL_HIP(hipGetLastError());
         std::swap(d1, d2);
         std::swap(u, up);
+      };
+      for (int it = 0; it < 100000; ++it) {
+        if (use_graph) {
+          if (it % check == 0) graphs.run(0, [&] { for (int q = 0; q < check; ++q) iteration(); });
+        } else {
+          iteration();
+        }
         for (int r = 0; r < nr; ++r) {
           iters[r] += bt.h_active[r];
           mvp[r] += bt.h_active[r];
@@ -600,26 +812,55 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
       }
       bt.h_active = inner_active;
       bt.push_active();
-      hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, n, X, e, bt.active.get());
+      hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
     } else {
       float2 *r32 = f[0].get(), *sv = f[1].get(), *p = f[2].get(), *q = f[3].get(), *e = f[4].get();
-      hipLaunchKernelGGL(k_b_cg_start, dim3(G, nr), dim3(kBlock), 0, s, n, R64.get(), r32, e, bt.st.get(),
+      hipLaunchKernelGGL(k_b_cg_start, dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e, bt.st.get(),
                          bt.active.get());
-      const int nbs = wilson32(op, 1, r32, sv, nr, bt.n_active(), 1, bt.part.get(), bt.active.get());
+      const int nbs = bwilson32(bt, 1, r32, sv, 1, bt.part.get());
       hipLaunchKernelGGL(k_b_fin_store, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(), (int)B_SS);
-      hipLaunchKernelGGL(k_b_copy_f32, dim3(G, nr), dim3(kBlock), 0, s, n, sv, p, bt.active.get());
+      hipLaunchKernelGGL(k_b_copy_f32, dim3(G, nr), dim3(kBlock), 0, s, g, sv, p, bt.active.get());
       for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
-      for (int it = 0; it < 100000; ++it) {
-        wilson32(op, 0, p, q, nr, bt.n_active(), 1, bt.part.get(), bt.active.get());
+      // With graphs, reliable updates fall on the last iteration of every `rel_blocks`-th block.
+      const int rel_every = !reliable ? 0
+                            : use_graph ? check * std::max(1, (o.reliable_every + check / 2) / check)
+                                        : o.reliable_every;
+      auto iteration = [&](bool update) {
+        bwilson32(bt, 0, p, q, 1, bt.part.get());
         hipLaunchKernelGGL(k_b_cg_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
                            bt.active.get());
-        hipLaunchKernelGGL(k_b_cg_xr, dim3(G, nr), dim3(kBlock), 0, s, n, bt.st.get(), p, q, e, r32,
+        hipLaunchKernelGGL(k_b_cg_xr, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), p, q, e, r32,
                            bt.active.get(), bt.part2.get());
-        wilson32(op, 1, r32, sv, nr, bt.n_active(), 1, bt.part.get(), bt.active.get());
+        if (update) {
+          // reliable update: x64 += e, r = b - M x64 in FP64, the FP32 residual restarts from it
+          // and the search direction p is kept
+          hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
+          true_residual(bt, B, X, R64.get(), T64.get());
+          hipLaunchKernelGGL(k_b_cg_start, dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e, bt.st.get(),
+                             bt.active.get());
+          hipLaunchKernelGGL(k_b_norm2_f32, dim3(G, nr), dim3(kBlock), 0, s, g, r32, bt.active.get(),
+                             bt.part2.get());
+        }
+        bwilson32(bt, 1, r32, sv, 1, bt.part.get());
         hipLaunchKernelGGL(k_b_cg_beta, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.part2.get(), G,
                            bt.st.get(), bt.active.get());
-        hipLaunchKernelGGL(k_b_cg_xpay, dim3(G, nr), dim3(kBlock), 0, s, n, bt.st.get(), sv, p, bt.active.get());
+        hipLaunchKernelGGL(k_b_cg_xpay, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, bt.active.get());
         DL_HIP(hipGetLastError());
+      };
+      for (int it = 0; it < 100000; ++it) {
+        const bool update = rel_every > 0 && (it + 1) % rel_every == 0;
+        if (use_graph) {
+          if (it % check == 0) {
+            const bool upd_block = rel_every > 0 && (it + check) % rel_every == 0;
+            graphs.run(upd_block ? 2 : 1, [&] {
+              for (int q2 = 0; q2 < check; ++q2) iteration(upd_block && q2 == check - 1);
+            });
+          }
+        } else {
+          iteration(update);
+        }
+        if (update)
+          for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
         for (int r = 0; r < nr; ++r) {
           iters[r] += bt.h_active[r];
           mvp[r] += 2 * bt.h_active[r];
@@ -641,7 +882,7 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
       }
       bt.h_active = inner_active;
       bt.push_active();
-      hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, n, X, e, bt.active.get());
+      hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
     }
     DL_HIP(hipGetLastError());
   }
@@ -657,7 +898,7 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
   for (int r = 0; r < nr; ++r) {
     dl_stats one{};
     one.relres = bnorm[r] == 0.0 ? 0.0 : bt.get(r, B_NRM) / bnorm[r];
-    one.status = one.relres <= tol ? DL_OK : DL_NOT_CONVERGED;
+    one.status = one.relres <= tol[r] ? DL_OK : DL_NOT_CONVERGED;
     one.iters = iters[r];
     one.mvp = mvp[r] + (bnorm[r] == 0.0 ? 0 : 1);
     one.guess = used_net[r];
@@ -666,6 +907,26 @@ int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B,
     if (st) st[r] = one;
   }
   return worst;
+}
+
+int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
+                       const dl_next_opts& o, dl_stats* st) {
+  if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
+    fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
+  return solve_batch({BItem{op, eig, 0, nrhs, tol}}, B, X, o, st);
+}
+
+int solve_next_multi(const std::vector<MultiItem>& items, const double2* B, double2* X, const dl_next_opts& o,
+                     dl_stats* st) {
+  std::vector<BItem> bi;
+  int r0 = 0;
+  for (const auto& m : items) {
+    if (m.eig && (m.eig->fingerprint != m.op->fingerprint || m.eig->kind != m.op->kind))
+      fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
+    bi.push_back(BItem{m.op, m.eig, r0, m.nrhs, m.tol});
+    r0 += m.nrhs;
+  }
+  return solve_batch(bi, B, X, o, st);
 }
 
 }  // namespace dl

@@ -46,21 +46,25 @@ void need(bool ok, const char* msg) {
 
 void use_device(dl_ctx* ctx) { DL_HIP(hipSetDevice(ctx->device)); }
 
-// nfield fields in the caller's layout -> tiled device buffer (pads zeroed).
-DBuf<double2> fields_in(dl_op* op, const double* p, int nfield, int mem) {
+// nfield fields in the caller's layout -> tiled device fields at t (pads zeroed).
+void fields_in_to(dl_op* op, const double* p, int nfield, int mem, double2* t) {
   const Lattice& lat = op->lat;
   hipStream_t s = op->ctx->stream;
-  DBuf<double2> t((size_t)nfield * lat.nc);
-  zero(s, (long)nfield * lat.nc, t.get());
+  zero(s, (long)nfield * lat.nc, t);
   const size_t bytes = (size_t)nfield * lat.V * kSpin * sizeof(double2);
   if (mem == DL_DEVICE) {
-    pack_spinor(s, lat, reinterpret_cast<const double2*>(p), t.get(), nfield);
+    pack_spinor(s, lat, reinterpret_cast<const double2*>(p), t, nfield);
   } else {
     DBuf<double2> stage((size_t)nfield * lat.V * kSpin);
     DL_HIP(hipMemcpyAsync(stage.get(), p, bytes, hipMemcpyHostToDevice, s));
-    pack_spinor(s, lat, stage.get(), t.get(), nfield);
+    pack_spinor(s, lat, stage.get(), t, nfield);
     DL_HIP(hipStreamSynchronize(s));
   }
+}
+
+DBuf<double2> fields_in(dl_op* op, const double* p, int nfield, int mem) {
+  DBuf<double2> t((size_t)nfield * op->lat.nc);
+  fields_in_to(op, p, nfield, mem, t.get());
   return t;
 }
 
@@ -109,11 +113,12 @@ dl_next_opts next_defaults(const dl_next_opts* o) {
   d.max_mvp = 1000000;
   if (o) {
     d.storage = o->storage;
-    if (o->reliable_every > 0) d.reliable_every = o->reliable_every;
+    if (o->reliable_every != 0) d.reliable_every = o->reliable_every;  // < 0: no reliable updates
     d.batched = o->batched;
     d.x0_given = o->x0_given;
     if (o->max_mvp > 0) d.max_mvp = o->max_mvp;
     d.net = o->net;
+    d.graph = o->graph;
   }
   return d;
 }
@@ -388,6 +393,72 @@ int dl_apply_batched(dl_op* op, int which, int prec, int nrhs, const double* in,
     }
     fields_out(op, r.get(), out, nrhs, mem);
     return DL_OK;
+  });
+}
+
+int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int mem, const dl_next_opts* opts,
+                        dl_stats* stats) {
+  return guard([&] {
+    need(ctx != nullptr, "ctx is NULL");
+    need(nitems >= 0, "nitems must be >= 0");
+    if (nitems == 0) return DL_OK;
+    need(items != nullptr, "items is NULL");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    dl_next_opts o = next_defaults(opts);
+    if (!opts) {
+      o.storage = DL_FP32;
+      o.batched = 1;
+    }
+    need(o.storage == DL_FP32 && o.batched, "the multi-lattice batch runs the batched path (DL_FP32, batched = 1)");
+    need(!o.net, "the learned initial guess takes one operator per batch (dl_solve_next)");
+    use_device(ctx);
+    std::vector<MultiItem> mi;
+    std::vector<int> src;  // item index of each batch entry
+    long total = 0;
+    int kind = -1;
+    for (int i = 0; i < nitems; ++i) {
+      const dl_batch_item& it = items[i];
+      need(it.op != nullptr, "item op is NULL");
+      need(it.op->ctx == ctx, "every operator of the batch must belong to ctx");
+      need(it.nrhs >= 0, "item nrhs must be >= 0");
+      need(it.tol > 0 && std::isfinite(it.tol), "item tol must be positive");
+      if (kind < 0) kind = it.op->kind;
+      need(it.op->kind == kind, "every operator of the batch must have the same kind");
+      if (it.eig && (it.eig->fingerprint != it.op->fingerprint || it.eig->kind != it.op->kind))
+        fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
+      if (it.nrhs == 0) continue;
+      need(it.B && it.X, "item B or X is NULL");
+      mi.push_back(MultiItem{it.op, it.eig, it.nrhs, it.tol});
+      src.push_back(i);
+      total += (long)it.nrhs * it.op->lat.nc;
+    }
+    if (mi.empty()) return DL_OK;
+    DBuf<double2> bt((size_t)total), xt((size_t)total);
+    long off = 0;
+    for (size_t j = 0; j < mi.size(); ++j) {
+      const dl_batch_item& it = items[src[j]];
+      fields_in_to(it.op, it.B, it.nrhs, mem, bt.get() + off);
+      if (o.x0_given) fields_in_to(it.op, it.X, it.nrhs, mem, xt.get() + off);
+      off += (long)it.nrhs * it.op->lat.nc;
+    }
+    std::vector<dl_stats> st;
+    long nst = 0;
+    for (const auto& m : mi) nst += m.nrhs;
+    st.resize(nst);
+    const int rc = solve_next_multi(mi, bt.get(), xt.get(), o, st.data());
+    off = 0;
+    long r = 0;
+    for (size_t j = 0; j < mi.size(); ++j) {
+      const dl_batch_item& it = items[src[j]];
+      fields_out(it.op, xt.get() + off, it.X, it.nrhs, mem);
+      off += (long)it.nrhs * it.op->lat.nc;
+    }
+    if (stats) {
+      // stats in item order, nrhs entries per item (items with nrhs = 0 have none)
+      for (size_t j = 0; j < mi.size(); ++j)
+        for (int q = 0; q < mi[j].nrhs; ++q, ++r) stats[r] = st[r];
+    }
+    return rc;
   });
 }
 

@@ -1,6 +1,7 @@
 // Operator, eigenvector-handle and solver declarations of libdeflan.
 #pragma once
 #include <map>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -60,6 +61,15 @@ int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2
                const dl_next_opts& o, dl_stats* st);
 int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
                        const dl_next_opts& o, dl_stats* st);
+// Several operators (lattices) in one batch: item i's fields are contiguous after item i-1's.
+struct MultiItem {
+  dl_op* op;
+  const dl_eig* eig;
+  int nrhs;
+  double tol;
+};
+int solve_next_multi(const std::vector<MultiItem>& items, const double2* B, double2* X, const dl_next_opts& o,
+                     dl_stats* st);
 dl_eig* eig_build(dl_op* op, int k, DBuf<double2>&& Y, long* mvp);
 const float2* op_links32_public(dl_op* op);  // FP32 links of the operator (made on first use)
 

@@ -162,6 +162,22 @@ int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double
                    const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int red, const double* scale,
                    const int* active, double* part, WilsonCfg cfg = WilsonCfg());
 
+// Several lattices in one stencil launch (the multi-lattice batched solver): one item per
+// operator, right-hand sides [rhs0, rhs0 + nrhs) of the batch, nbs = ceil(V / 256) site blocks,
+// blocks [block0, block0 + nbs * nrhs) of the launch.  Field j of the batch starts at offs[j].
+struct WilsonItem {
+  const void* U;   // links of the item's precision (double2 or float2), tiled
+  double kappa;
+  int L[4];
+  long V, Vpad;
+  int rhs0, nrhs, nbs, block0;
+};
+// Partials (red != 0) are column-major [rhs][pstride], pstride >= every item's nbs.
+template <class R>
+void wilson_multi(hipStream_t s, const WilsonItem* d_items, int nitems, int nblocks, int pstride, int which,
+                  const cplx_t<R>* in, cplx_t<R>* out, const long* offs, int red, const double* scale,
+                  const int* active, double* part);
+
 // ---- launchers: BLAS-1 ------------------------------------------------------
 int nblocks_for(long n);  // partial count used by the streaming reductions for length n
 // partial sums

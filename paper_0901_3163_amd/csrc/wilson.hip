@@ -153,20 +153,14 @@ __device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int
 // Launch shape: NT threads per block, OCC the occupancy hint (waves per SIMD the
 // register budget must allow); ORDER 0: rhs fastest, XCD-contiguous blocks; 1: sites
 // fastest, XCD-contiguous; 2: rhs fastest, hardware block order.
-template <class R, int WHICH, int RED, int NT, int OCC>
-__global__ void __launch_bounds__(NT, OCC)
-k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
-         typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
-         int Lt, long V, long Vpad, int nbs, int order, const double* __restrict__ scale,
-         const int* __restrict__ active, double* __restrict__ part) {
+// One site of the stencil for one field (zeroes padding sites); returns the fused
+// reduction term (||out||^2 or Re<in, out>) of the site.
+template <class R, int WHICH, int RED>
+__device__ __forceinline__ double wilson_site(const typename CT<R>::type* __restrict__ U,
+                                              const typename CT<R>::type* __restrict__ in,
+                                              typename CT<R>::type* __restrict__ out, double kappa, int Lx, int Ly,
+                                              int Lz, int Lt, long V, long Vpad, int site, R sc) {
   using C = typename CT<R>::type;
-  const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
-  const int rhs = order == 1 ? lb / nbs : lb % nrhs;
-  const int sb = order == 1 ? lb % nbs : lb / nrhs;
-  if (active && !active[rhs]) return;
-  in += rhs * fstride;
-  out += rhs * fstride;
-  const int site = sb * NT + (int)threadIdx.x;
   double red = 0.0;
   if (site >= V && site < Vpad) {
     // padding sites of the last tile are kept at zero
@@ -198,7 +192,6 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
       hop<SF, false>(U, in, mu, site + df, site, acc);
       hop<-SF, true>(U, in, mu, site + db, site + db, acc);
     }
-    const R sc = scale ? (R)scale[rhs] : (R)1;
     const R mk = (R)(-kappa);
     const C* ip = in + sp_base(site);
     C* op = out + sp_base(site);
@@ -212,12 +205,83 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
       if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
     }
   }
+  return red;
+}
+
+template <class R, int WHICH, int RED, int NT, int OCC>
+__global__ void __launch_bounds__(NT, OCC)
+k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
+         typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+         int Lt, long V, long Vpad, int nbs, int order, const double* __restrict__ scale,
+         const int* __restrict__ active, double* __restrict__ part) {
+  const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int rhs = order == 1 ? lb / nbs : lb % nrhs;
+  const int sb = order == 1 ? lb % nbs : lb / nrhs;
+  if (active && !active[rhs]) return;
+  const int site = sb * NT + (int)threadIdx.x;
+  const R sc = scale ? (R)scale[rhs] : (R)1;
+  const double red = wilson_site<R, WHICH, RED>(U, in + rhs * fstride, out + rhs * fstride, kappa, Lx, Ly, Lz, Lt,
+                                                V, Vpad, site, sc);
   if (RED != 0) {
     __shared__ double lds[NT / 64];
     const double s = block_sum<NT>(red, lds);
     if (threadIdx.x == 0) part[(long)rhs * nbs + sb] = s;
   }
 }
+
+// Several lattices in one launch: a work list of items (lattice, links, kappa, range of
+// right-hand sides).  Logical block b (XCD-contiguous) belongs to the item whose block
+// range [block0, block0 + nbs * nrhs) holds it, and within the item to (site block, rhs)
+// with the rhs fastest, so the blocks that read the same links are consecutive.  Field j
+// starts at offs[j] (complex elements).  Partials: part[rhs * pstride + site block]; the
+// first site block of each rhs zeroes the tail up to pstride, so every rhs reduces over
+// pstride partials.
+template <class R, int WHICH, int RED>
+__global__ void __launch_bounds__(256, 2)
+k_wilson_ml(const WilsonItem* __restrict__ items, int nitems, const typename CT<R>::type* __restrict__ in,
+            typename CT<R>::type* __restrict__ out, const long* __restrict__ offs, int pstride,
+            const double* __restrict__ scale, const int* __restrict__ active, double* __restrict__ part) {
+  using C = typename CT<R>::type;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  int it = 0;
+  while (it + 1 < nitems && b >= items[it + 1].block0) ++it;
+  const WilsonItem w = items[it];
+  const int rl = (b - w.block0) % w.nrhs;
+  const int sb = (b - w.block0) / w.nrhs;
+  const int rhs = w.rhs0 + rl;
+  if (active && !active[rhs]) return;
+  const int site = sb * 256 + (int)threadIdx.x;
+  const R sc = scale ? (R)scale[rhs] : (R)1;
+  const long off = offs[rhs];
+  const double red = wilson_site<R, WHICH, RED>(static_cast<const C*>(w.U), in + off, out + off, w.kappa, w.L[0],
+                                                w.L[1], w.L[2], w.L[3], w.V, w.Vpad, site, sc);
+  if (RED != 0) {
+    __shared__ double lds[256 / 64];
+    const double s = block_sum<256>(red, lds);
+    if (threadIdx.x == 0) part[(long)rhs * pstride + sb] = s;
+    if (sb == 0)
+      for (int q = w.nbs + (int)threadIdx.x; q < pstride; q += 256) part[(long)rhs * pstride + q] = 0.0;
+  }
+}
+
+template <class R>
+void wilson_multi(hipStream_t s, const WilsonItem* d_items, int nitems, int nblocks, int pstride, int which,
+                  const cplx_t<R>* in, cplx_t<R>* out, const long* offs, int red, const double* scale,
+                  const int* active, double* part) {
+#define DL_ML(WH, RD)                                                                                      \
+  hipLaunchKernelGGL((k_wilson_ml<R, WH, RD>), dim3(nblocks), dim3(256), 0, s, d_items, nitems, in, out, offs, \
+                     pstride, scale, active, part)
+  if (which == 0) { if (red == 0) DL_ML(0, 0); else if (red == 1) DL_ML(0, 1); else DL_ML(0, 2); }
+  else if (which == 1) { if (red == 0) DL_ML(1, 0); else if (red == 1) DL_ML(1, 1); else DL_ML(1, 2); }
+  else { if (red == 0) DL_ML(2, 0); else if (red == 1) DL_ML(2, 1); else DL_ML(2, 2); }
+#undef DL_ML
+  DL_HIP(hipGetLastError());
+}
+
+template void wilson_multi<double>(hipStream_t, const WilsonItem*, int, int, int, int, const double2*, double2*,
+                                   const long*, int, const double*, const int*, double*);
+template void wilson_multi<float>(hipStream_t, const WilsonItem*, int, int, int, int, const float2*, float2*,
+                                  const long*, int, const double*, const int*, double*);
 
 // t-marching form of the same operator.  A thread owns one (x, y, z) site and walks
 // T consecutive time slices t0 .. t0+T-1 of it.  The forward-t neighbour psi(t+1)

@@ -39,7 +39,12 @@ class dl_first_opts(C.Structure):
 
 class dl_next_opts(C.Structure):
     _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
-                ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p)]
+                ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p), ("graph", C.c_int)]
+
+
+class dl_batch_item(C.Structure):
+    _fields_ = [("op", C.c_void_p), ("eig", C.c_void_p), ("nrhs", C.c_int), ("B", C.c_void_p), ("X", C.c_void_p),
+                ("tol", C.c_double)]
 
 
 class dl_stats(C.Structure):
@@ -75,6 +80,8 @@ def _load():
         "dl_eig_create": (I, [P, I, P, I, C.POINTER(P)]),
         "dl_bench_wilson": (I, [P, I, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "dl_apply_batched": (I, [P, I, I, I, P, P, I]),
+        "dl_solve_next_multi": (I, [P, I, C.POINTER(dl_batch_item), I, C.POINTER(dl_next_opts),
+                                    C.POINTER(dl_stats)]),
         "dl_tune_wilson": (I, [P, I, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
         "dl_eig_info": (I, [P, C.POINTER(I), P, P]),
         "dl_eig_vectors": (I, [P, P, I]),
@@ -104,7 +111,8 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_solve_next", "dl_eig_create", "dl_eig_info", "dl_eig_vectors", "dl_eig_destroy",
             "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson",
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
-            "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched")
+            "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
+            "dl_solve_next_multi")
 
 
 def _check(rc):
@@ -274,12 +282,12 @@ class Operator:
         return x, eig, dict(st.as_dict(), rc=rc)
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
-                   reliable_every=None, net=None):
+                   reliable_every=None, net=None, graph=False):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
         o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
-                         int(max_mvp or 0), net.h if net is not None else None)
+                         int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0)
         st = (dl_stats * max(nrhs, 1))()
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
@@ -389,6 +397,37 @@ class Net:
 
 def num_weights() -> int:
     return int(lib.dl_net_num_weights())
+
+
+def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s=None, graph=False):
+    """Later right-hand sides of several operators in one batched solve.
+
+    items: sequence of (op, eig or None, B [nrhs][V][4][3], tol); all B numpy (host) or all
+    torch device tensors.  Returns (list of X, list of per-rhs stats dicts per item, rc)."""
+    its = (dl_batch_item * max(len(items), 1))()
+    keep, Xs, mem = [], [], None
+    for i, (op, eig, B, tol) in enumerate(items):
+        B = _c128(B)
+        X = _empty_like(B) if x0s is None else _c128(x0s[i]).copy()
+        pB, m = _ptr(B)
+        pX, _ = _ptr(X)
+        if mem is None:
+            mem = m
+        elif m != mem:
+            raise ValueError("all right-hand sides must live in the same memory (host or device)")
+        its[i] = dl_batch_item(op.h, eig.h if eig is not None else None, int(B.shape[0]), pB, pX, float(tol))
+        keep.append(B)
+        Xs.append(X)
+    o = dl_next_opts(DL_FP32, int(reliable_every or 0), 1, 1 if x0s is not None else 0, int(max_mvp or 0), None,
+                     1 if graph else 0)
+    ntot = sum(int(B.shape[0]) for B in keep)
+    st = (dl_stats * max(ntot, 1))()
+    rc = _check(lib.dl_solve_next_multi(ctx.h, len(items), its, mem if mem is not None else DL_HOST, C.byref(o), st))
+    out, r = [], 0
+    for B in keep:
+        out.append([st[r + j].as_dict() for j in range(int(B.shape[0]))])
+        r += int(B.shape[0])
+    return Xs, out, rc
 
 
 # ---- kernel-level entry points ------------------------------------------------

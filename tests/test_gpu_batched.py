@@ -109,3 +109,29 @@ def test_batched_solver_in_each_stencil_family(gpu_ctx, c1_config, variant, monk
         assert _rel(X[i], np.linalg.solve(M, B[i].ravel())) < 1e-6
     eig.close()
     op.close()
+
+
+def test_batched_cg_reliable_updates(gpu_ctx, c1_config):
+    """Batched D-CG with FP64 reliable updates every 10 or 50 iterations inside each restart
+    cycle (search direction kept) and without them: all reach tol and the same solution, at
+    comparable iteration counts."""
+    from paper_0901_3163_amd import deflan
+    dims, U, kappa = c1_config["dims"], c1_config["links"], c1_config["kappa"]
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_MDAGM)
+    b1 = gaussian_spinor(dims, 100)
+    _, eig, _ = op.solve_first(b1, 60, 20, 1e-10)
+    B = np.stack([gaussian_spinor(dims, 140 + i) for i in range(4)])
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    xd = [np.linalg.solve(dirac.dense(ora.M, ora.n), b.ravel()) for b in B]
+    its = {}
+    for rel in (10, 50, -1):
+        X, sts, rc = op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1, reliable_every=rel)
+        assert rc == deflan.DL_OK, rel
+        for i in range(4):
+            r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+            assert r <= 1.0001e-10, (rel, i, r)
+            assert _rel(X[i], xd[i]) < 1e-6
+        its[rel] = sum(s["iters"] for s in sts)
+    assert its[50] <= 1.25 * its[-1] and its[10] <= 1.5 * its[-1], its
+    eig.close()
+    op.close()
