@@ -286,6 +286,11 @@ int  dl_net_train(dl_net* net, dl_op* op, int n, const double* B, const double* 
  * Then, if `subtract`, w <- w - V c in place.  All pointers DL_HOST or DL_DEVICE. */
 int  dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w,
                     double* c, int subtract, int mem);
+/* Several columns at once (the batched deflation projection): C[r][j] = <V_j, W_r> for nv
+ * vectors V ([nv][n] complex) and nw <= 16 columns W ([nw][n]); C: [nw][nv] complex.  If X
+ * ([nw][n]) is not NULL, then X_r += sum_j C[r][j] V_j.  V streams once for all columns. */
+int  dl_tsk_project_multi(dl_ctx* ctx, long n, int nv, const double* V, int nw, const double* W,
+                          double* C, double* X, int mem);
 /* Y = V G for V ([nv][n] complex) and real G ([nv][ny], row-major); Y: [ny][n]. */
 int  dl_tsk_combine(dl_ctx* ctx, long n, int nv, const double* V, const double* G,
                     int ny, double* Y, int mem);

@@ -552,32 +552,43 @@ static void project_batch(Batch& bt, const double2* R, double2* X, double2* T, D
     hipLaunchKernelGGL(k_b_gamma5, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.seg, R, T, bt.active.get());
   else
     bwilson64(bt, 1, R, T);
+  // c = Y^H rA and x += Y d for up to 16 rhs per launch, so the eigenvectors stream once per
+  // 16 rhs instead of once per rhs (the rhs of one item are contiguous at stride n)
+  constexpr int kCols = 16, kRows = 64;
+  S.ensure_part((size_t)2 * kRows * kCols * tsk_multi_nblocks(bt.nmax) + 64);
   for (const auto& it : bt.items) {
     if (!it.eig || it.eig->k == 0) continue;
     dl_op* op = it.op;
     const int k = it.eig->k;
     const long n = op->lat.nc;
     int nact = 0;
-    for (int r = it.r0; r < it.r0 + it.nr; ++r) {
-      if (!bt.h_active[r]) continue;
-      ++nact;
-      int nb;
-      {
-        TimeScope ts(bt.ctx, T_TSK_DOTS);
-        nb = tsk_dots(bt.s, n, k, it.eig->Y.get(), n, nullptr, T + bt.h_off[r], S.part.get());
-      }
-      sum_partials(bt.s, S.part.get(), nb, 2 * k, reinterpret_cast<double*>(cbuf.get() + (long)(r - it.r0) * k));
-    }
+    for (int r = it.r0; r < it.r0 + it.nr; ++r) nact += bt.h_active[r];
     if (!nact) continue;
+    const double2* Y = it.eig->Y.get();
+    for (int c0 = 0; c0 < it.nr; c0 += kCols) {
+      const int nw = std::min(kCols, it.nr - c0);
+      const int* act = bt.active.get() + it.r0 + c0;
+      for (int j0 = 0; j0 < k; j0 += kRows) {
+        const int nv = std::min(kRows, k - j0);
+        int np;
+        {
+          TimeScope ts(bt.ctx, T_TSK_DOTS);
+          np = tsk_dots_multi(bt.s, n, nv, Y + (long)j0 * n, n, T + bt.h_off[it.r0 + c0], n, nw, act, S.part.get());
+        }
+        for (int r = 0; r < nw; ++r)
+          sum_partials(bt.s, S.part.get() + (size_t)2 * r * nv * np, np, 2 * nv,
+                       reinterpret_cast<double*>(cbuf.get() + (long)(c0 + r) * k + j0));
+      }
+    }
     {
       TimeScope ts(bt.ctx, T_SMALL);
       proj_solve(bt.s, k, it.nr, it.eig->Zr.get(), it.eig->lamr.get(), cbuf.get(), cbuf.get() + (long)it.nr * k);
     }
-    for (int r = it.r0; r < it.r0 + it.nr; ++r) {
-      if (!bt.h_active[r]) continue;
+    for (int c0 = 0; c0 < it.nr; c0 += kCols) {
+      const int nw = std::min(kCols, it.nr - c0);
       TimeScope ts(bt.ctx, T_TSK_UPDATE);
-      tsk_update(bt.s, n, k, it.eig->Y.get(), n, nullptr, cbuf.get() + (long)it.nr * k + (long)(r - it.r0) * k, 1.0,
-                 X + bt.h_off[r]);
+      tsk_update_multi(bt.s, n, k, Y, n, cbuf.get() + (long)it.nr * k + (long)c0 * k, nw,
+                       bt.active.get() + it.r0 + c0, X + bt.h_off[it.r0 + c0], n);
     }
   }
 }

@@ -8,6 +8,7 @@
 #include "small.hpp"
 #include "tsk.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -723,6 +724,60 @@ int dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w, doub
     if (mem == DL_HOST) {
       DL_HIP(hipMemcpyAsync(c, cp, (size_t)nv * sizeof(double2), hipMemcpyDeviceToHost, s));
       if (subtract) DL_HIP(hipMemcpyAsync(w, wp, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, s));
+    }
+    DL_HIP(hipStreamSynchronize(s));
+    return DL_OK;
+  });
+}
+
+int dl_tsk_project_multi(dl_ctx* ctx, long n, int nv, const double* V, int nw, const double* W, double* C, double* X,
+                         int mem) {
+  return guard([&] {
+    need(ctx && V && W && C, "NULL argument");
+    need(n > 0 && nv > 0 && nv <= 512, "need n > 0 and 0 < nv <= 512");
+    need(nw >= 1 && nw <= 16, "need 1 <= nw <= 16");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    use_device(ctx);
+    hipStream_t s = ctx->stream;
+    DBuf<double2> Vd, Wd, Xd, Cd;
+    const double2* vp = reinterpret_cast<const double2*>(V);
+    const double2* wp = reinterpret_cast<const double2*>(W);
+    double2* xp = reinterpret_cast<double2*>(X);
+    double2* cp = reinterpret_cast<double2*>(C);
+    if (mem == DL_HOST) {
+      Vd.alloc((size_t)nv * n);
+      Wd.alloc((size_t)nw * n);
+      Cd.alloc((size_t)nw * nv);
+      DL_HIP(hipMemcpyAsync(Vd.get(), V, (size_t)nv * n * sizeof(double2), hipMemcpyHostToDevice, s));
+      DL_HIP(hipMemcpyAsync(Wd.get(), W, (size_t)nw * n * sizeof(double2), hipMemcpyHostToDevice, s));
+      vp = Vd.get();
+      wp = Wd.get();
+      cp = Cd.get();
+      if (X) {
+        Xd.alloc((size_t)nw * n);
+        DL_HIP(hipMemcpyAsync(Xd.get(), X, (size_t)nw * n * sizeof(double2), hipMemcpyHostToDevice, s));
+        xp = Xd.get();
+      }
+    }
+    constexpr int kRows = 64;
+    DBuf<double> part((size_t)2 * kRows * nw * tsk_multi_nblocks(n));
+    for (int j0 = 0; j0 < nv; j0 += kRows) {
+      const int m = std::min(kRows, nv - j0);
+      int np;
+      {
+        TimeScope ts(ctx, T_TSK_DOTS);
+        np = tsk_dots_multi(s, n, m, vp + (long)j0 * n, n, wp, n, nw, nullptr, part.get());
+      }
+      for (int r = 0; r < nw; ++r)
+        sum_partials(s, part.get() + (size_t)2 * r * m * np, np, 2 * m, reinterpret_cast<double*>(cp + (long)r * nv + j0));
+    }
+    if (X) {
+      TimeScope ts(ctx, T_TSK_UPDATE);
+      tsk_update_multi(s, n, nv, vp, n, cp, nw, nullptr, xp, n);
+    }
+    if (mem == DL_HOST) {
+      DL_HIP(hipMemcpyAsync(C, cp, (size_t)nw * nv * sizeof(double2), hipMemcpyDeviceToHost, s));
+      if (X) DL_HIP(hipMemcpyAsync(X, xp, (size_t)nw * n * sizeof(double2), hipMemcpyDeviceToHost, s));
     }
     DL_HIP(hipStreamSynchronize(s));
     return DL_OK;

@@ -122,6 +122,102 @@ k_tsk_combine(long n, int nv, const double2* __restrict__ base, long ld, const i
   }
 }
 
+// ---- several right-hand sides at once: C = V^H W and X += V D ---------------------------
+// W and X hold nw fields at stride ldw (nw <= NW).  V streams once for all nw columns.
+constexpr int kMEPT = 2;     // rows per thread per pass of the multi-column dots
+constexpr int kMultiNV = 64; // basis vectors per multi-column dots launch
+constexpr int kMultiBlocks = 2048;
+
+// part is column-major [2*nw*nv][gridDim.x]: column (r*nv + j)*2 (+1) holds Re (Im) of this
+// block's share of <V_j, W_r>, so the summed result is c[r*nv + j] (rhs-major).  A block walks
+// its rows kMEPT per thread at a time; each wave adds its wave sums to its own LDS row, and the
+// four rows are added at the end (fixed order).
+template <int NW>
+__global__ void __launch_bounds__(kBlock)
+k_tsk_dots_multi(long n, int nv, const double2* __restrict__ base, long ld, const double2* __restrict__ W, long ldw,
+                 int nw, const int* __restrict__ active, double* __restrict__ part) {
+  __shared__ double2 acc[kBlock / 64][NW][kMultiNV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int t = lane; t < NW * kMultiNV; t += 64) acc[wid][t / kMultiNV][t % kMultiNV] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const long step = (long)gridDim.x * kBlock * kMEPT;
+  for (long i0 = (long)blockIdx.x * kBlock * kMEPT + threadIdx.x; i0 - threadIdx.x < n; i0 += step) {
+    double2 wr[kMEPT][NW];
+#pragma unroll
+    for (int e = 0; e < kMEPT; ++e)
+#pragma unroll
+      for (int r = 0; r < NW; ++r) {
+        const long i = i0 + e * kBlock;
+        const bool on = r < nw && i < n && (!active || active[r]);
+        wr[e][r] = on ? W[(long)r * ldw + i] : make_double2(0.0, 0.0);
+      }
+    for (int j = 0; j < nv; ++j) {
+      const double2* v = base + (long)j * ld;
+      double re[NW], im[NW];
+#pragma unroll
+      for (int r = 0; r < NW; ++r) re[r] = im[r] = 0.0;
+#pragma unroll
+      for (int e = 0; e < kMEPT; ++e) {
+        const long i = i0 + e * kBlock;
+        const double2 x = i < n ? v[i] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+          re[r] = fma(x.x, wr[e][r].x, re[r]);
+          re[r] = fma(x.y, wr[e][r].y, re[r]);
+          im[r] = fma(x.x, wr[e][r].y, im[r]);
+          im[r] = fma(-x.y, wr[e][r].x, im[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NW; ++r) {
+        if (r < nw) {
+          const double a = wave_sum(re[r]), b = wave_sum(im[r]);
+          if (lane == 0) acc[wid][r][j] = make_double2(acc[wid][r][j].x + a, acc[wid][r][j].y + b);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nw * nv; t += kBlock) {
+    const int r = t / nv, j = t % nv;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) {
+      a += acc[q][r][j].x;
+      b += acc[q][r][j].y;
+    }
+    part[(long)(2 * (r * nv + j)) * gridDim.x + blockIdx.x] = a;
+    part[(long)(2 * (r * nv + j) + 1) * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+// X_r += sum_j D[r*ldd + j] V_j for active r < nw (D complex, rhs-major, device memory).
+template <int NW>
+__global__ void __launch_bounds__(kBlock)
+k_tsk_update_multi(long n, int nv, const double2* __restrict__ base, long ld, const double2* __restrict__ D, int ldd,
+                   int nw, const int* __restrict__ active, double2* __restrict__ X, long ldx) {
+  __shared__ double2 ds[kMaxNV / 4][NW];  // nv <= 128
+  for (int t = threadIdx.x; t < nv * NW; t += kBlock) {
+    const int j = t / NW, r = t % NW;
+    ds[j][r] = r < nw ? D[(long)r * ldd + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const long stride = (long)gridDim.x * kBlock;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    double2 acc[NW];
+#pragma unroll
+    for (int r = 0; r < NW; ++r) acc[r] = make_double2(0.0, 0.0);
+    for (int j = 0; j < nv; ++j) {
+      const double2 x = base[(long)j * ld + i];
+#pragma unroll
+      for (int r = 0; r < NW; ++r) acc[r] = c_fma(ds[j][r], x, acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NW; ++r)
+      if (r < nw && (!active || active[r])) X[(long)r * ldx + i] = c_add(X[(long)r * ldx + i], acc[r]);
+  }
+}
+
 static int stream_blocks(long n) {
   long nb = (n + kBlock - 1) / kBlock;
   if (nb > 2048) nb = 2048;
@@ -157,6 +253,53 @@ void tsk_combine(hipStream_t s, long n, int nv, const double2* base, long ld, co
   hipLaunchKernelGGL(k_tsk_combine, grid, dim3(kBlock), 0, s, n, nv, base, ld, slot, G, ldg, ny, obase, old,
                      oslot, accumulate);
   DL_HIP(hipGetLastError());
+}
+
+int tsk_multi_nblocks(long n) {
+  long nb = (n + (long)kBlock * kMEPT - 1) / ((long)kBlock * kMEPT);
+  if (nb < 1) nb = 1;
+  if (nb > kMultiBlocks) nb = kMultiBlocks;
+  return (int)nb;
+}
+
+int tsk_dots_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* W, long ldw, int nw,
+                   const int* active, double* part) {
+  if (nv > kMultiNV) fail(DL_E_INVALID, "too many basis vectors for one multi-column contraction (max 64)");
+  if (nw < 1 || nw > 16) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
+  const int nb = tsk_multi_nblocks(n);
+  if (nv > 0) {
+    if (nw <= 4)
+      hipLaunchKernelGGL((k_tsk_dots_multi<4>), dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, W, ldw, nw, active, part);
+    else if (nw <= 8)
+      hipLaunchKernelGGL((k_tsk_dots_multi<8>), dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, W, ldw, nw, active, part);
+    else
+      hipLaunchKernelGGL((k_tsk_dots_multi<16>), dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, W, ldw, nw, active,
+                         part);
+    DL_HIP(hipGetLastError());
+  }
+  return nb;
+}
+
+void tsk_update_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* D, int nw,
+                      const int* active, double2* X, long ldx) {
+  if (nw < 1 || nw > 16) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
+  const int nb = stream_blocks(n);
+  constexpr int kChunk = kMaxNV / 4;  // basis vectors per launch (LDS holds kChunk x NW coefficients)
+  for (int j0 = 0; j0 < nv; j0 += kChunk) {
+    const int nc = nv - j0 < kChunk ? nv - j0 : kChunk;
+    const double2* b = base + (long)j0 * ld;
+    const double2* d = D + j0;
+    if (nw <= 4)
+      hipLaunchKernelGGL((k_tsk_update_multi<4>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active, X,
+                         ldx);
+    else if (nw <= 8)
+      hipLaunchKernelGGL((k_tsk_update_multi<8>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active, X,
+                         ldx);
+    else
+      hipLaunchKernelGGL((k_tsk_update_multi<16>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active, X,
+                         ldx);
+    DL_HIP(hipGetLastError());
+  }
 }
 
 }  // namespace dl

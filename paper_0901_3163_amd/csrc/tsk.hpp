@@ -17,4 +17,15 @@ void tsk_combine(hipStream_t s, long n, int nv, const double2* base, long ld, co
                  const double* G, int ldg, int ny, double2* obase, long old, const int* oslot,
                  int accumulate);
 
+// Several columns at once (nw <= 16 fields W_r / X_r at stride ldw / ldx; nv <= 64 for the
+// dots): part <- partials of c[r*nv + j] = <V_j, W_r> (sum with
+// sum_partials(part, np, 2*nv*nw, c)), returns np (<= 2048, so part needs 2*nv*nw*2048
+// doubles); columns with active[r] == 0 (active may be NULL) read as zero.
+int tsk_dots_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* W, long ldw, int nw,
+                   const int* active, double* part);
+// X_r += sum_j D[r*nv + j] V_j for r < nw with active[r] != 0 (any nv; 128 vectors per launch).
+void tsk_update_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* D, int nw,
+                      const int* active, double2* X, long ldx);
+int tsk_multi_nblocks(long n);
+
 }  // namespace dl

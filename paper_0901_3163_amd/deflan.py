@@ -88,6 +88,7 @@ def _load():
         "dl_eig_destroy": (None, [P]),
         "dl_tsk_project": (I, [P, L, I, P, P, P, I, I]),
         "dl_tsk_combine": (I, [P, L, I, P, P, I, P, I]),
+        "dl_tsk_project_multi": (I, [P, L, I, P, I, P, P, P, I]),
         "dl_small_eigh": (I, [P, I, P, P, P]),
         "dl_net_num_weights": (I, []),
         "dl_net_create": (I, [P, P, C.POINTER(P)]),
@@ -112,7 +113,7 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson",
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
-            "dl_solve_next_multi")
+            "dl_solve_next_multi", "dl_tsk_project_multi")
 
 
 def _check(rc):
@@ -441,6 +442,19 @@ def dl_tsk_project(ctx: Context, V, w, subtract: bool = False):
     pc, _ = _ptr(c)
     _check(lib.dl_tsk_project(ctx.h, int(V.shape[1]), int(V.shape[0]), pV, pw, pc, 1 if subtract else 0, mem))
     return c, w
+
+
+def dl_tsk_project_multi(ctx: Context, V, W, X=None):
+    """C = V^H W per column ([nw][nv]) and, if X is given, X + V C^T per column."""
+    V, W = _c128(V), _c128(W)
+    C = _empty_like(W, (W.shape[0], V.shape[0]))
+    Xo = None if X is None else (_c128(X).copy() if isinstance(X, np.ndarray) else X.clone())
+    pV, mem = _ptr(V)
+    pW, _ = _ptr(W)
+    pC, _ = _ptr(C)
+    pX = _ptr(Xo)[0] if Xo is not None else None
+    _check(lib.dl_tsk_project_multi(ctx.h, int(V.shape[1]), int(V.shape[0]), pV, int(W.shape[0]), pW, pC, pX, mem))
+    return C, Xo
 
 
 def dl_tsk_combine(ctx: Context, V, G):

@@ -174,3 +174,23 @@ def test_multi_rhs_apply_every_variant(gpu_ctx, dims, monkeypatch):
     one = op.apply_batched(2, deflan.DL_FP64, Psi[:1])
     assert _rel(one[0], ora.g5M(Psi[0].ravel()).reshape(Psi[0].shape)) < 1e-13
     op.close()
+
+
+@pytest.mark.parametrize("n,nv,nw", [(1000, 1, 1), (3072, 61, 12), (100003, 130, 16), (1572864, 60, 12),
+                                     (8000000, 8, 3)])
+def test_tsk_project_multi(gpu_ctx, n, nv, nw):
+    """C = V^H W for several columns at once and X += V C^T, against numpy (FP64, 1e-12).
+
+    Covers one vector and one column, more than 64 basis vectors (two dots launches) and more
+    than 128 (two update launches), the 16^3x32 field length with k = 60 and 12 rhs, and a
+    length whose rows outnumber one pass of the grid (the blocks loop over rows)."""
+    from paper_0901_3163_amd import deflan
+    rng = np.random.default_rng(n + nv)
+    V = rng.standard_normal((nv, n)) + 1j * rng.standard_normal((nv, n))
+    W = rng.standard_normal((nw, n)) + 1j * rng.standard_normal((nw, n))
+    X = rng.standard_normal((nw, n)) + 1j * rng.standard_normal((nw, n))
+    C, Xo = deflan.dl_tsk_project_multi(gpu_ctx, V, W, X)
+    Cr = (V.conj() @ W.T).T  # C[r, j] = sum_i conj(V_j[i]) W_r[i]
+    assert np.max(np.abs(C - Cr)) < 1e-12 * np.max(np.abs(Cr)) * max(1.0, np.sqrt(n) / 100)
+    Xr = X + C @ V
+    assert np.max(np.abs(Xo - Xr)) < 1e-12 * np.max(np.abs(Xr)) * max(1.0, np.sqrt(nv))
