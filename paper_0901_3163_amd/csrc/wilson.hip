@@ -403,6 +403,170 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::ty
   }
 }
 
+// Time-marching form with the slice staged in LDS: a block is NT consecutive (x, y, z)
+// sites of one time chunk of one rhs.  At each slice every thread writes its centre spinor
+// and its forward x and y links to LDS; the x and y neighbours (and the backward x, y links)
+// that fall inside the block's site range are then read from LDS instead of L2 (for a
+// 16 x 16 plane per block that is all of them), the z neighbours and the z, t links come
+// from memory, and the t hops are carried along t as in k_wilson_tm.  Same arithmetic and
+// order as k_wilson.
+template <class R, int WHICH, int RED, int NT, bool LK>
+__global__ void __launch_bounds__(NT)
+k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
+             typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+             int Lt, long V, long Vpad, int T, int nb3, int nbs, int order, const double* __restrict__ scale,
+             const int* __restrict__ active, double* __restrict__ part) {
+  using C = typename CT<R>::type;
+  __shared__ C ps[12 * NT];               // centre spinors of the block's sites, component-major
+  __shared__ C pu[LK ? 2 * 9 * NT : 1];   // forward x and y links of the block's sites (LK)
+  const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int rhs = order == 1 ? lb / nbs : lb % nrhs;
+  const int sb = order == 1 ? lb % nbs : lb / nrhs;
+  if (active && !active[rhs]) return;
+  in += rhs * fstride;
+  out += rhs * fstride;
+  const int b3 = sb % nb3, tc = sb / nb3;
+  const int V3 = Lx * Ly * Lz;
+  const int base3 = b3 * NT;
+  const int tid = (int)threadIdx.x;
+  const int s3 = base3 + tid;
+  const bool valid = s3 < V3;
+  double red = 0.0;
+  if (b3 == 0 && (tc + 1) * T >= Lt) {
+    for (long sp = V + tid; sp < Vpad; sp += NT) {
+      C* op = out + sp_base((int)sp);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
+    }
+  }
+  int x = 0, y = 0, z = 0;
+  if (valid) {
+    x = s3 % Lx;
+    y = (s3 / Lx) % Ly;
+    z = s3 / (Lx * Ly);
+  }
+  const int sy = Lx, sz = Lx * Ly;
+  const int fx = x == Lx - 1 ? 1 - Lx : 1, bx = x == 0 ? Lx - 1 : -1;
+  const int fy = y == Ly - 1 ? (1 - Ly) * sy : sy, by = y == 0 ? (Ly - 1) * sy : -sy;
+  const int fz = z == Lz - 1 ? (1 - Lz) * sz : sz, bz = z == 0 ? (Lz - 1) * sz : -sz;
+  constexpr int SF = (WHICH == 1) ? 1 : -1;
+  const int t0 = tc * T;
+  const int t1 = t0 + T < Lt ? t0 + T : Lt;
+  const R sc = scale ? (R)scale[rhs] : (R)1;
+  const R mk = (R)(-kappa);
+  C cen[12], gb[6];
+  if (valid) {
+    const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+    const int sprev = tp * V3 + s3;
+    C p[12], h[6], u[9];
+    const C* pp = in + sp_base(sprev);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+    const C* up = U + lk_base(sprev, 3);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+    project<3, -SF>(p, h);
+    mul_half<true>(u, h, gb);
+    const C* cp = in + sp_base(t0 * V3 + s3);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) cen[c] = cp[c * kTile];
+  }
+#pragma unroll 1
+  for (int t = t0; t < t1; ++t) {
+    const int site = t * V3 + s3;
+    __syncthreads();  // the previous slice is no longer read from LDS
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) ps[c * NT + tid] = cen[c];
+      if (LK) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+          pu[e * NT + tid] = U[lk_base(site, 0) + e * kTile];
+          pu[(9 + e) * NT + tid] = U[lk_base(site, 1) + e * kTile];
+        }
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      C acc[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = CT<R>::make(0, 0);
+#pragma unroll 1
+      for (int hop2 = 0; hop2 < 6; ++hop2) {
+        const int mu = hop2 >> 1;
+        const bool fwd = (hop2 & 1) == 0;
+        const int d = mu == 0 ? (fwd ? fx : bx) : mu == 1 ? (fwd ? fy : by) : (fwd ? fz : bz);
+        const int nb3 = s3 + d;
+        const unsigned li = (unsigned)(nb3 - base3);
+        const bool near = mu < 2 && li < (unsigned)NT && nb3 < V3;
+        C p[12], h[6], g[6], u[9];
+        if (near) {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) p[c] = ps[c * NT + li];
+        } else {
+          const C* pp = in + sp_base(site + d);
+#pragma unroll
+          for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+        }
+        if (LK && fwd && mu < 2) {
+#pragma unroll
+          for (int e = 0; e < 9; ++e) u[e] = pu[(mu * 9 + e) * NT + tid];
+        } else if (LK && !fwd && near) {
+#pragma unroll
+          for (int e = 0; e < 9; ++e) u[e] = pu[(mu * 9 + e) * NT + li];
+        } else {
+          const C* up = U + lk_base(fwd ? site : site + d, mu);
+#pragma unroll
+          for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+        }
+        if (fwd) {
+          project_mu<SF>(mu, p, h);
+          mul_half<false>(u, h, g);
+          reconstruct_mu<SF>(mu, acc, g);
+        } else {
+          project_mu<-SF>(mu, p, h);
+          mul_half<true>(u, h, g);
+          reconstruct_mu<-SF>(mu, acc, g);
+        }
+      }
+      const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
+      C nx[12], u[9];
+      {
+        const C* pp = in + sp_base(snext);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) nx[c] = pp[c * kTile];
+        const C* up = U + lk_base(site, 3);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+        C h[6], g[6];
+        project<3, SF>(nx, h);
+        mul_half<false>(u, h, g);
+        reconstruct<3, SF>(acc, g);
+        reconstruct<3, -SF>(acc, gb);
+        project<3, -SF>(cen, h);
+        mul_half<true>(u, h, gb);
+      }
+      C* op = out + sp_base(site);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const C p = cen[c];
+        C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
+        if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
+        op[c * kTile] = r;
+        if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
+        if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) cen[c] = nx[c];
+    }
+  }
+  if (RED != 0) {
+    __shared__ double lds[NT / 64];
+    const double s2 = block_sum<NT>(red, lds);
+    if (threadIdx.x == 0) part[(long)rhs * nbs + sb] = s2;
+  }
+}
+
 // Multi-rhs time-marching form: a block is 64 consecutive (x, y, z) sites (one wave per
 // rhs) of one time chunk for RB right-hand sides.  At each time slice the block stages
 // the seven links its sites use from that slice (U_x, U_y, U_z at x, at x - mu for the
@@ -547,9 +711,9 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
 // {(256,2), (128,2), (512,1), (256,1)}; 4-6: k_wilson_tm, 256 threads per block, time
 // chunks of T = 4, 8, 16 slices; 7-10: k_wilson_tml with 64 sites per block and
 // (rhs per block, T) = (4, 8), (4, 16), (8, 8), (2, 8).
-static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64};
-static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8};
-static constexpr int kVariantRB[kWilsonVariants] = {0, 0, 0, 0, 0, 0, 0, 4, 4, 8, 2};
+static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64, 256, 256, 256};
+static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8, 8, 8, 16};
+static constexpr int kVariantRB[kWilsonVariants] = {0, 0, 0, 0, 0, 0, 0, 4, 4, 8, 2, 0, 0, 0};
 
 static int tm_nb3(const Lattice& lat, int v) {
   return (lat.L[0] * lat.L[1] * lat.L[2] + kVariantNT[v] - 1) / kVariantNT[v];
@@ -573,6 +737,16 @@ static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, do
   const int* L = lat.L;
   hipLaunchKernelGGL((k_wilson<R, WHICH, RED, NT, OCC>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, nbs, order, scale, active, part);
+}
+
+template <class R, int WHICH, int RED, int NT, bool LK>
+static void launch_tmp(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
+                       cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+                       double* part, int nbs, int v) {
+  const int* L = lat.L;
+  hipLaunchKernelGGL((k_wilson_tmp<R, WHICH, RED, NT, LK>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride,
+                     nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
+                     order, scale, active, part);
 }
 
 template <class R, int WHICH, int RED, int RB>
@@ -605,6 +779,19 @@ static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const
       break;
     case 10:
       launch_tml<R, WHICH, RED, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      break;
+    case 11:
+      // FP64 spinors and links of a slice together exceed the LDS budget: the FP64 form stages spinors only
+      if constexpr (sizeof(R) == 4)
+        launch_tmp<R, WHICH, RED, 256, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
+                                             nbs, variant);
+      else
+        launch_tmp<R, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
+                                              nbs, variant);
+      break;
+    case 12: case 13:
+      launch_tmp<R, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs,
+                                            variant);
       break;
     default: launch_one<R, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
   }
