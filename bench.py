@@ -219,6 +219,8 @@ def main():
     ap.add_argument("--train-lr", type=float, default=3e-3)
     ap.add_argument("--net-seed", type=int, default=7)
     ap.add_argument("--ablation-steps", type=int, default=1)
+    ap.add_argument("--storage", choices=("fp32", "bf16"), default="fp32",
+                    help="Krylov-vector storage of the timed fast path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded across GPUs.",
@@ -263,8 +265,10 @@ def main():
     if args.train_rhs > 0:
         net, net_info = train_guess(ctx, op, eig, deflan, dims, args)
 
-    def fast(use_net=True):
-        return op.solve_next(B, eig, args.tol, storage=deflan.DL_FP32, batched=1,
+    storage = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.storage]
+
+    def fast(use_net=True, st=None):
+        return op.solve_next(B, eig, args.tol, storage=storage if st is None else st, batched=1,
                              net=net if use_net else None)
 
     def plain():
@@ -289,22 +293,27 @@ def main():
     n_w, ms_w, by_w = ctx.kernel_time("wilson")
     ctx.timing(False)
     value = nrhs * args.steps / dt
-    # ablation: the same mixed-precision batched path without the learned guess
-    mixed = None
+    # ablation: the batched path with each storage, with and without the learned guess
+    ablation = {}
     if net is not None:
-        fast(False)
+        net_info["guess_kept_per_rhs"] = float(np.mean(kept))
+    for name, st_, use_net in (("fp32", deflan.DL_FP32, False), ("bf16", deflan.DL_BF16, False),
+                               ("fp32+guess", deflan.DL_FP32, True), ("bf16+guess", deflan.DL_BF16, True)):
+        if use_net and net is None:
+            continue
+        fast(use_net, st_)
         torch.cuda.synchronize()
         t0 = time.time()
         for s in range(args.ablation_steps):
-            Xm, stm, _ = fast(False)
+            Xm, stm, _ = fast(use_net, st_)
         torch.cuda.synchronize()
         dtm = time.time() - t0
-        mixed = dict(value=round(nrhs * args.ablation_steps / dtm, 3), unit="RHS/s", steps=args.ablation_steps,
-                     all_rhs_converged=bool(all(st["relres"] <= args.tol for st in stm)),
-                     iters_per_rhs=float(np.mean([st["iters"] for st in stm])),
-                     path="batched D-MinRes FP32/FP64 without the learned guess (projection-only start)")
-        net_info["guess_kept_per_rhs"] = float(np.mean(kept))
-        log(f"without the learned guess: {mixed['value']:.2f} RHS/s, iters {mixed['iters_per_rhs']:.1f}")
+        ablation[name] = dict(value=round(nrhs * args.ablation_steps / dtm, 3), unit="RHS/s",
+                              steps=args.ablation_steps,
+                              all_rhs_converged=bool(all(st["relres"] <= args.tol for st in stm)),
+                              iters_per_rhs=float(np.mean([st["iters"] for st in stm])),
+                              max_relres=float(max(st["relres"] for st in stm)))
+        log(f"ablation {name}: {ablation[name]['value']:.2f} RHS/s, iters {ablation[name]['iters_per_rhs']:.1f}")
     achieved = by_w / (ms_w * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(dims),
@@ -327,17 +336,18 @@ def main():
     log(f"fast {value:.2f} RHS/s, plain FP64 {plain_value:.2f} RHS/s")
     result = dict(metric=METRIC, value=round(value, 3), unit="RHS/s", n_gpus=1, steps=args.steps,
                   warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 2), higher_is_better=True,
-                  scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+                  scaling="weak", vs_baseline=None, dtype=("f32+f64" if args.storage == "fp32" else "bf16/f32+f64"),
+                  data="synthetic",
                   config=dict(workload=f"16^3x32 Wilson near-critical (kappa {kappa:.6f}), MinRes-DR({args.m},"
                                        f"{args.k}) on gamma5 M then D-MinRes on 12 point sources, tol "
                                        f"{args.tol:g}", lattice=list(dims), kappa=kappa, nrhs=nrhs,
                               m=args.m, k=args.k,
-                              path=("batched D-MinRes, FP32 Krylov vectors and Wilson apply, FP64 residuals, "
-                                    "projection and solution" + (", learned initial guess (net(b) + projection, "
-                                                                  "kept per rhs when its residual is smaller)"
-                                                                  if net is not None else ""))),
+                              path=(f"batched D-MinRes, {args.storage.upper()} Krylov vectors and Wilson apply "
+                                    "(FP32 arithmetic and links), FP64 residuals, projection and solution"
+                                    + (", learned initial guess (net(b) + projection, kept per rhs when its "
+                                       "residual is smaller)" if net is not None else ""))),
                   all_rhs_converged=bool(all_ok), iters_per_rhs=float(np.mean(iters)),
-                  learned_guess=net_info, mixed_batched_no_guess=mixed,
+                  learned_guess=net_info, ablation_batched=ablation,
                   plain_fp64=dict(value=round(plain_value, 3), unit="RHS/s", steps=args.plain_steps,
                                   all_rhs_converged=bool(ok64),
                                   iters_per_rhs=float(np.mean([st["iters"] for st in st64])),

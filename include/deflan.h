@@ -114,6 +114,9 @@ typedef struct {
   int    graph;             /* batched path: 1 = replay each block of 8 inner iterations as a
                                captured HIP graph (fewer launches for small lattices); ignored
                                while kernel timing (dl_timing) is on.  Default 0. */
+  double inner_drop;        /* batched path: residual reduction that ends an inner cycle (then
+                               FP64 residual, projection, restart); 0 = default: 1e-4 with DL_FP32
+                               storage, 1e-2 with DL_BF16 (whose rounding limits one cycle) */
 } dl_next_opts;
 
 /* Per-solve statistics. */

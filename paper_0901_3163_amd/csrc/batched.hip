@@ -5,7 +5,8 @@
 // Wilson links are read from HBM once per site block for the whole batch and
 // launch latency is paid once per stage instead of once per right-hand side.
 // Right-hand sides that have converged are masked off (their blocks return at
-// once).  Krylov vectors and the Wilson apply are FP32 (FP32 accumulation);
+// once).  Krylov vectors and the Wilson apply are FP32 or BF16 storage with FP32
+// arithmetic (links FP32);
 // the solution x, the residual r = b - M x and the Galerkin projection over
 // the stored eigenvectors (Section 2: "projected ... at the beginning") are
 // FP64.  Accuracy is won back by restarting the FP32 inner solve from the FP64
@@ -32,6 +33,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <type_traits>
 
 namespace dl {
 
@@ -98,9 +100,10 @@ __global__ void __launch_bounds__(kBlock) k_b_fin_store(const double* part, int 
 }
 
 // MinRes inner start: v = gamma5 r64 * inv (FP32), vp = d1 = d2 = e = 0; state reset.
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_minres_start(Seg g, const double2* r64, float2* v, float2* vp, float2* d1, float2* d2, float2* e, double* st,
-                 double* invs, const int* __restrict__ active) {
+k_b_minres_start(Seg g, const double2* r64, SV* v, SV* vp, SV* d1, SV* d2, SV* e, double* st, double* invs,
+                 const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const double inv = st[rhs * NS + B_INV];
@@ -109,12 +112,12 @@ k_b_minres_start(Seg g, const double2* r64, float2* v, float2* vp, float2* d1, f
     const int c = (int)((i >> 6) % kSpin);
     const double2 x = r64[off + i];
     const double sg = c >= 6 ? -inv : inv;
-    v[off + i] = make_float2((float)(x.x * sg), (float)(x.y * sg));
+    sst(v + off + i, make_float2((float)(x.x * sg), (float)(x.y * sg)));
     const float2 z = make_float2(0.f, 0.f);
-    vp[off + i] = z;
-    d1[off + i] = z;
-    d2[off + i] = z;
-    e[off + i] = z;
+    sst(vp + off + i, z);
+    sst(d1 + off + i, z);
+    sst(d2 + off + i, z);
+    sst(e + off + i, z);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double* s = st + rhs * NS;
@@ -142,8 +145,9 @@ __global__ void __launch_bounds__(kBlock) k_b_fin_alpha(const double* part, int 
 // Lanczos vectors are kept unnormalised, u_j = n_j v_j, and w = A v_j (the
 // Wilson epilogue applied 1/n_j).  un = w - (alpha/n_j) u_j - (beta_j/n_{j-1}) u_{j-1},
 // written over u_{j-1}; partial ||un||^2.
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_lanczos3(Seg g, const double* st, const float2* u, float2* up, const float2* w, const int* __restrict__ active,
+k_b_lanczos3(Seg g, const double* st, const SV* u, SV* up, const SV* w, const int* __restrict__ active,
              double* __restrict__ part) {
   const int rhs = blockIdx.y;
   double acc = 0.0;
@@ -152,9 +156,9 @@ k_b_lanczos3(Seg g, const double* st, const float2* u, float2* up, const float2*
     const float a = (float)(S[B_ALPHA] / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
     const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-      float2 t = c_axpy(-a, u[off + i], w[off + i]);
-      t = c_axpy(-b, up[off + i], t);
-      up[off + i] = t;
+      float2 t = c_axpy(-a, sld(u + off + i), sld(w + off + i));
+      t = c_axpy(-b, sld(up + off + i), t);
+      sst(up + off + i, t);
       acc = fma((double)t.x, (double)t.x, fma((double)t.y, (double)t.y, acc));
     }
   }
@@ -209,9 +213,10 @@ k_b_fin_rot(const double* part, int np, double* st, double* invs, const int* act
 }
 
 // d_new = (u_j / n_j - delta d1 - eps d2)/gamma -> dn ; e += tau d_new   (n_j = B_NPREV after the rotation)
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_minres_update(Seg g, const double* st, const float2* u, const float2* d1, const float2* d2, float2* dn,
-                  float2* e, const int* __restrict__ active) {
+k_b_minres_update(Seg g, const double* st, const SV* u, const SV* d1, const SV* d2, SV* dn, SV* e,
+                  const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const double* S = st + rhs * NS;
@@ -220,22 +225,23 @@ k_b_minres_update(Seg g, const double* st, const float2* u, const float2* d1, co
   const float iu = (float)(1.0 / S[B_NPREV]);
   const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-    float2 d = c_axpy(-delta, d1[off + i], c_scale(u[off + i], iu));
-    d = c_axpy(-eps, d2[off + i], d);
+    float2 d = c_axpy(-delta, sld(d1 + off + i), c_scale(sld(u + off + i), iu));
+    d = c_axpy(-eps, sld(d2 + off + i), d);
     d = c_scale(d, ig);
-    dn[off + i] = d;
-    e[off + i] = c_axpy(tau, d, e[off + i]);
+    sst(dn + off + i, d);
+    sst(e + off + i, c_axpy(tau, d, sld(e + off + i)));
   }
 }
 
 // x64 += e (FP32 correction)
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_accum(Seg g, double2* x, const float2* e, const int* __restrict__ active) {
+k_b_accum(Seg g, double2* x, const SV* e, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-    const float2 d = e[off + i];
+    const float2 d = sld(e + off + i);
     x[off + i] = make_double2(x[off + i].x + (double)d.x, x[off + i].y + (double)d.y);
   }
 }
@@ -254,15 +260,16 @@ __global__ void __launch_bounds__(kBlock) k_b_gamma5(Seg g, const double2* in, d
 
 // ---- CG on the normal equations (CGLS), FP32 inner -----------------------------------
 // start: r32 = r64 (FP32), e = 0 ; s and p are formed by the caller (s = M^dag r32, p = s).
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_cg_start(Seg g, const double2* r64, float2* r32, float2* e, double* st, const int* __restrict__ active) {
+k_b_cg_start(Seg g, const double2* r64, SV* r32, SV* e, double* st, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
     const double2 x = r64[off + i];
-    r32[off + i] = make_float2((float)x.x, (float)x.y);
-    e[off + i] = make_float2(0.f, 0.f);
+    sst(r32 + off + i, make_float2((float)x.x, (float)x.y));
+    sst(e + off + i, make_float2(0.f, 0.f));
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) st[rhs * NS + B_FLAG] = 0.0;
 }
@@ -281,18 +288,19 @@ __global__ void __launch_bounds__(kBlock) k_b_cg_alpha(const double* part, int n
 }
 
 // e += alpha p ; r -= alpha q ; partial ||r||^2
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_cg_xr(Seg g, const double* st, const float2* p, const float2* q, float2* e, float2* r,
-          const int* __restrict__ active, double* __restrict__ part) {
+k_b_cg_xr(Seg g, const double* st, const SV* p, const SV* q, SV* e, SV* r, const int* __restrict__ active,
+          double* __restrict__ part) {
   const int rhs = blockIdx.y;
   double acc = 0.0;
   if (!active || active[rhs]) {
     const float a = (float)st[rhs * NS + B_CGA];
     const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-      e[off + i] = c_axpy(a, p[off + i], e[off + i]);
-      const float2 v = c_axpy(-a, q[off + i], r[off + i]);
-      r[off + i] = v;
+      sst(e + off + i, c_axpy(a, sld(p + off + i), sld(e + off + i)));
+      const float2 v = c_axpy(-a, sld(q + off + i), sld(r + off + i));
+      sst(r + off + i, v);
       acc = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, acc));
     }
   }
@@ -320,25 +328,27 @@ k_b_cg_beta(const double* ps, int nps, const double* pr, int npr, double* st, co
 }
 
 // p = s + beta p
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_cg_xpay(Seg g, const double* st, const float2* s, float2* p, const int* __restrict__ active) {
+k_b_cg_xpay(Seg g, const double* st, const SV* s, SV* p, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const float b = (float)st[rhs * NS + B_CGB];
   const long off = seg_off(g, rhs), n = seg_len(g, rhs);
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
-    p[off + i] = c_axpy(b, p[off + i], s[off + i]);
+    sst(p + off + i, c_axpy(b, sld(p + off + i), sld(s + off + i)));
 }
 
-// partial ||a||^2 of FP32 fields, column-major [rhs][G]
+// partial ||a||^2 of low-precision fields, column-major [rhs][G]
+template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_norm2_f32(Seg g, const float2* a, const int* __restrict__ active, double* __restrict__ part) {
+k_b_norm2_f32(Seg g, const SV* a, const int* __restrict__ active, double* __restrict__ part) {
   const int rhs = blockIdx.y;
   double acc = 0.0;
   if (!active || active[rhs]) {
     const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-      const float2 v = a[off + i];
+      const float2 v = sld(a + off + i);
       acc = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, acc));
     }
   }
@@ -347,7 +357,8 @@ k_b_norm2_f32(Seg g, const float2* a, const int* __restrict__ active, double* __
   if (threadIdx.x == 0) part[(long)rhs * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void k_b_copy_f32(Seg g, const float2* a, float2* b, const int* active) {
+template <class SV>
+__global__ void k_b_copy_f32(Seg g, const SV* a, SV* b, const int* active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const long off = seg_off(g, rhs), n = seg_len(g, rhs);
@@ -504,15 +515,18 @@ void Batch::build_worklists() {
 }
 
 // FP32 stencil over the whole batch; returns the partial stride per rhs of the fused reduction.
-static int bwilson32(Batch& bt, int which, const float2* in, float2* out, int red, double* part,
-                     const double* scale = nullptr) {
-  TimeScope ts(bt.ctx, T_WILSON, bt.wilson_bytes(288.0, 192.0));
+// Low-precision stencil over the whole batch (FP32 arithmetic and links; spinors stored as SV:
+// float2 or bf2); returns the partial stride per rhs of the fused reduction.
+template <class SV>
+static int bwilson_lo(Batch& bt, int which, const SV* in, SV* out, int red, double* part,
+                      const double* scale = nullptr) {
+  constexpr int prec = sizeof(SV) == sizeof(float2) ? DL_FP32 : DL_BF16;
+  TimeScope ts(bt.ctx, T_WILSON, bt.wilson_bytes(288.0, 2.0 * kSpin * sizeof(SV)));
   if (bt.single()) {
     dl_op* op = bt.items[0].op;
-    const WilsonCfg cfg = wilson_cfg(op, DL_FP32, bt.nr);
-    const int nbs = wilson_batched<float>(bt.s, op->lat, op_links32_public(op), op->kappa, which, in, out, op->lat.nc,
-                                          bt.nr, red, scale, bt.active.get(), part, cfg);
-    return nbs;
+    const WilsonCfg cfg = wilson_cfg(op, prec, bt.nr);
+    return wilson_batched<float>(bt.s, op->lat, op_links32_public(op), op->kappa, which, in, out, op->lat.nc, bt.nr,
+                                 red, scale, bt.active.get(), part, cfg);
   }
   wilson_multi<float>(bt.s, bt.wl32.get(), (int)bt.items.size(), bt.ml_blocks, bt.ml_pstride, which, in, out,
                       bt.d_off.get(), red, scale, bt.active.get(), part);
@@ -640,9 +654,11 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   Batch bt(items);
   const int nr = bt.nr;
   hipStream_t s = bt.s;
+  // everything a captured block could allocate or tune is settled first: the FP32 links and
+  // the stencil launch shapes (tuning launches kernels and allocates)
+  for (const auto& it : items) (void)op_links32_public(it.op);
   if (bt.single()) {
-    // settle the stencil launch shapes (tuning launches kernels) before any graph capture
-    (void)wilson_cfg(items[0].op, DL_FP32, nr);
+    (void)wilson_cfg(items[0].op, o.storage == DL_BF16 ? DL_BF16 : DL_FP32, nr);
     (void)wilson_cfg(items[0].op, DL_FP64, nr);
   }
   const bool mr = items[0].op->kind == DL_G5M;
@@ -654,8 +670,14 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   S.sc.alloc(256);
   S.ensure_part((size_t)2 * kmax * tsk_nblocks(bt.nmax) + 64);
   DBuf<double2> R64((size_t)bt.total), T64((size_t)bt.total);
+  // low-precision Krylov vectors: FP32 or BF16 storage (FP32 arithmetic either way)
+  const bool bf16 = o.storage == DL_BF16;
   DBuf<float2> f[6];
-  for (auto& b : f) b.alloc((size_t)bt.total);
+  DBuf<bf2> h[6];
+  for (int q = 0; q < 6; ++q) {
+    if (bf16) h[q].alloc((size_t)bt.total);
+    else f[q].alloc((size_t)bt.total);
+  }
   DBuf<double2> cbuf(2 * (size_t)nrmax * kmax + 2);
   std::vector<long> iters(nr, 0), mvp(nr, 0);
   std::vector<double> bnorm(nr), rel(nr, 1.0), tol(nr);
@@ -734,7 +756,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       std::fflush(stderr);
     }
   }
-  const double inner_drop = 1e-4;      // reduction of the inner residual estimate per cycle
+  const double inner_drop = o.inner_drop > 0.0 ? o.inner_drop : 1e-4;  // residual drop that ends a cycle
   const int check = 8;                 // iterations between host checks (even)
   const Seg g = bt.seg;
   // Graph replay of the `check`-iteration blocks: off while kernel timing is on (its events
@@ -775,22 +797,24 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
     for (int r = 0; r < nr; ++r) target[r] = std::max(inner_drop * bt.get(r, B_NRM), 0.5 * tol[r] * bnorm[r]);
     std::vector<int> inner_active = bt.h_active;
     const int G = bt.G;
+    // the inner solve for storage SV (the pointers of the six vector buffers)
+    auto inner = [&](auto* f0, auto* f1, auto* f2, auto* f3, auto* f4, auto* f5) {
+    using SV = std::remove_pointer_t<decltype(f0)>;
     if (mr) {
-      float2 *u = f[0].get(), *up = f[1].get(), *w = f[2].get(), *d1 = f[3].get(), *d2 = f[4].get(),
-             *e = f[5].get();
-      hipLaunchKernelGGL(k_b_minres_start, dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), u, up, d1, d2, e,
+      SV *u = f0, *up = f1, *w = f2, *d1 = f3, *d2 = f4, *e = f5;
+      hipLaunchKernelGGL((k_b_minres_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), u, up, d1, d2, e,
                          bt.st.get(), bt.invs.get(), bt.active.get());
       // one MinRes iteration; `check` (even) iterations return u, up, d1, d2 to their places,
       // so a block of them is the same launch sequence every time (replayed as a graph)
       auto iteration = [&]() {
-        const int nbs = bwilson32(bt, 2, u, w, 2, bt.part.get(), bt.invs.get());
+        const int nbs = bwilson_lo(bt, 2, u, w, 2, bt.part.get(), bt.invs.get());
         hipLaunchKernelGGL(k_b_fin_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
                            bt.active.get());
-        hipLaunchKernelGGL(k_b_lanczos3, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, up, w,
+        hipLaunchKernelGGL((k_b_lanczos3<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, up, w,
                            bt.active.get(), bt.part.get());
         hipLaunchKernelGGL(k_b_fin_rot, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), G, bt.st.get(), bt.invs.get(),
                            bt.active.get());
-        hipLaunchKernelGGL(k_b_minres_update, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, d1, d2, d2, e,
+        hipLaunchKernelGGL((k_b_minres_update<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, d1, d2, d2, e,
                            bt.active.get());
         DL_HIP(hipGetLastError());
         std::swap(d1, d2);
@@ -823,39 +847,40 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       }
       bt.h_active = inner_active;
       bt.push_active();
-      hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
+      hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
     } else {
-      float2 *r32 = f[0].get(), *sv = f[1].get(), *p = f[2].get(), *q = f[3].get(), *e = f[4].get();
-      hipLaunchKernelGGL(k_b_cg_start, dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e, bt.st.get(),
+      SV *r32 = f0, *sv = f1, *p = f2, *q = f3, *e = f4;
+      (void)f5;
+      hipLaunchKernelGGL((k_b_cg_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e, bt.st.get(),
                          bt.active.get());
-      const int nbs = bwilson32(bt, 1, r32, sv, 1, bt.part.get());
+      const int nbs = bwilson_lo(bt, 1, r32, sv, 1, bt.part.get());
       hipLaunchKernelGGL(k_b_fin_store, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(), (int)B_SS);
-      hipLaunchKernelGGL(k_b_copy_f32, dim3(G, nr), dim3(kBlock), 0, s, g, sv, p, bt.active.get());
+      hipLaunchKernelGGL((k_b_copy_f32<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, sv, p, bt.active.get());
       for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
       // With graphs, reliable updates fall on the last iteration of every `rel_blocks`-th block.
       const int rel_every = !reliable ? 0
                             : use_graph ? check * std::max(1, (o.reliable_every + check / 2) / check)
                                         : o.reliable_every;
       auto iteration = [&](bool update) {
-        bwilson32(bt, 0, p, q, 1, bt.part.get());
+        bwilson_lo(bt, 0, p, q, 1, bt.part.get());
         hipLaunchKernelGGL(k_b_cg_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
                            bt.active.get());
-        hipLaunchKernelGGL(k_b_cg_xr, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), p, q, e, r32,
+        hipLaunchKernelGGL((k_b_cg_xr<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), p, q, e, r32,
                            bt.active.get(), bt.part2.get());
         if (update) {
           // reliable update: x64 += e, r = b - M x64 in FP64, the FP32 residual restarts from it
           // and the search direction p is kept
-          hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
+          hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
           true_residual(bt, B, X, R64.get(), T64.get());
-          hipLaunchKernelGGL(k_b_cg_start, dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e, bt.st.get(),
+          hipLaunchKernelGGL((k_b_cg_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e, bt.st.get(),
                              bt.active.get());
-          hipLaunchKernelGGL(k_b_norm2_f32, dim3(G, nr), dim3(kBlock), 0, s, g, r32, bt.active.get(),
+          hipLaunchKernelGGL((k_b_norm2_f32<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, r32, bt.active.get(),
                              bt.part2.get());
         }
-        bwilson32(bt, 1, r32, sv, 1, bt.part.get());
+        bwilson_lo(bt, 1, r32, sv, 1, bt.part.get());
         hipLaunchKernelGGL(k_b_cg_beta, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.part2.get(), G,
                            bt.st.get(), bt.active.get());
-        hipLaunchKernelGGL(k_b_cg_xpay, dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, bt.active.get());
+        hipLaunchKernelGGL((k_b_cg_xpay<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, bt.active.get());
         DL_HIP(hipGetLastError());
       };
       for (int it = 0; it < 100000; ++it) {
@@ -893,8 +918,11 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       }
       bt.h_active = inner_active;
       bt.push_active();
-      hipLaunchKernelGGL(k_b_accum, dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
+      hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
     }
+    };
+    if (bf16) inner(h[0].get(), h[1].get(), h[2].get(), h[3].get(), h[4].get(), h[5].get());
+    else inner(f[0].get(), f[1].get(), f[2].get(), f[3].get(), f[4].get(), f[5].get());
     DL_HIP(hipGetLastError());
   }
   // final FP64 true residuals for every rhs

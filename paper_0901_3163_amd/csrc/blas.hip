@@ -154,6 +154,25 @@ __global__ void k_widen_f64(long n, const float2* __restrict__ a, double2* __res
     b[i] = make_double2(a[i].x, a[i].y);
 }
 
+__global__ void k_round_bf16(long n, const double2* __restrict__ a, bf2* __restrict__ b) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    sst(b + i, make_float2((float)a[i].x, (float)a[i].y));
+}
+__global__ void k_widen_bf16(long n, const bf2* __restrict__ a, double2* __restrict__ b) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float2 v = sld(a + i);
+    b[i] = make_double2(v.x, v.y);
+  }
+}
+void round_bf16(hipStream_t s, long n, const double2* a, bf2* b) {
+  hipLaunchKernelGGL(k_round_bf16, dim3(2048), dim3(256), 0, s, n, a, b);
+  DL_HIP(hipGetLastError());
+}
+void widen_bf16(hipStream_t s, long n, const bf2* a, double2* b) {
+  hipLaunchKernelGGL(k_widen_bf16, dim3(2048), dim3(256), 0, s, n, a, b);
+  DL_HIP(hipGetLastError());
+}
+
 void round_f32(hipStream_t s, long n, const double2* a, float2* b) {
   hipLaunchKernelGGL(k_round_f32, dim3(2048), dim3(256), 0, s, n, a, b);
   DL_HIP(hipGetLastError());

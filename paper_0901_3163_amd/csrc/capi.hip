@@ -112,6 +112,7 @@ dl_next_opts next_defaults(const dl_next_opts* o) {
   d.batched = 0;
   d.x0_given = 0;
   d.max_mvp = 1000000;
+  d.inner_drop = 0.0;  // resolved below by storage
   if (o) {
     d.storage = o->storage;
     if (o->reliable_every != 0) d.reliable_every = o->reliable_every;  // < 0: no reliable updates
@@ -120,7 +121,11 @@ dl_next_opts next_defaults(const dl_next_opts* o) {
     if (o->max_mvp > 0) d.max_mvp = o->max_mvp;
     d.net = o->net;
     d.graph = o->graph;
+    if (o->inner_drop != 0.0) d.inner_drop = o->inner_drop;
   }
+  // per-cycle residual drop of the batched inner solve: BF16 storage limits what one cycle
+  // can reach, so its cycles end earlier
+  if (d.inner_drop == 0.0) d.inner_drop = d.storage == DL_BF16 ? 1e-2 : 1e-4;
   return d;
 }
 
@@ -345,9 +350,11 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
     need(tol > 0 && std::isfinite(tol), "tol must be positive");
     const dl_next_opts o = next_defaults(opts);
-    need(o.storage == DL_FP64 || o.storage == DL_FP32, "storage must be DL_FP64 or DL_FP32");
-    need(!(o.storage == DL_FP32 && !o.batched), "DL_FP32 storage runs through the batched path (batched = 1)");
-    need(!(o.batched && o.storage == DL_FP64), "the batched path stores Krylov vectors in DL_FP32");
+    need(o.storage == DL_FP64 || o.storage == DL_FP32 || o.storage == DL_BF16,
+         "storage must be DL_FP64, DL_FP32 or DL_BF16");
+    need(!(o.storage != DL_FP64 && !o.batched), "DL_FP32 and DL_BF16 storage run through the batched path (batched = 1)");
+    need(!(o.batched && o.storage == DL_FP64), "the batched path stores Krylov vectors in DL_FP32 or DL_BF16");
+    need(o.inner_drop > 0.0 && o.inner_drop < 1.0, "inner_drop must be in (0, 1)");
     need(!o.net || o.batched, "the learned initial guess runs on the batched path (batched = 1)");
     need(!(o.net && o.x0_given), "x0_given and a learned initial guess exclude each other");
     if (o.net) check_net_op(o.net, op);
@@ -368,7 +375,7 @@ int dl_apply_batched(dl_op* op, int which, int prec, int nrhs, const double* in,
   return guard([&] {
     need(op != nullptr, "op is NULL");
     need(which >= 0 && which <= 2, "which must be DL_APPLY_M, DL_APPLY_MDAG or DL_APPLY_G5M");
-    need(prec == DL_FP64 || prec == DL_FP32, "prec must be DL_FP64 or DL_FP32");
+    need(prec == DL_FP64 || prec == DL_FP32 || prec == DL_BF16, "prec must be DL_FP64, DL_FP32 or DL_BF16");
     need(nrhs >= 0, "nrhs must be >= 0");
     if (nrhs == 0) return DL_OK;
     need(in && out, "NULL argument");
@@ -384,12 +391,19 @@ int dl_apply_batched(dl_op* op, int which, int prec, int nrhs, const double* in,
     if (prec == DL_FP64) {
       wilson_batched<double>(s, lat, op->U.get(), op->kappa, which, t.get(), r.get(), lat.nc, nrhs, 0, nullptr,
                              nullptr, nullptr, cfg);
-    } else {
+    } else if (prec == DL_FP32) {
       DBuf<float2> a32(n), b32(n);
       round_f32(s, n, t.get(), a32.get());
       wilson_batched<float>(s, lat, op_links32_public(op), op->kappa, which, a32.get(), b32.get(), lat.nc, nrhs, 0,
                             nullptr, nullptr, nullptr, cfg);
       widen_f64(s, n, b32.get(), r.get());
+      DL_HIP(hipStreamSynchronize(s));
+    } else {
+      DBuf<bf2> a16(n), b16(n);
+      round_bf16(s, n, t.get(), a16.get());
+      wilson_batched<float>(s, lat, op_links32_public(op), op->kappa, which, a16.get(), b16.get(), lat.nc, nrhs, 0,
+                            nullptr, nullptr, nullptr, cfg);
+      widen_bf16(s, n, b16.get(), r.get());
       DL_HIP(hipStreamSynchronize(s));
     }
     fields_out(op, r.get(), out, nrhs, mem);
@@ -409,8 +423,11 @@ int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int
     if (!opts) {
       o.storage = DL_FP32;
       o.batched = 1;
+      o.inner_drop = 1e-4;
     }
-    need(o.storage == DL_FP32 && o.batched, "the multi-lattice batch runs the batched path (DL_FP32, batched = 1)");
+    need((o.storage == DL_FP32 || o.storage == DL_BF16) && o.batched,
+         "the multi-lattice batch runs the batched path (DL_FP32 or DL_BF16, batched = 1)");
+    need(o.inner_drop > 0.0 && o.inner_drop < 1.0, "inner_drop must be in (0, 1)");
     need(!o.net, "the learned initial guess takes one operator per batch (dl_solve_next)");
     use_device(ctx);
     std::vector<MultiItem> mi;
@@ -467,7 +484,7 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
   return guard([&] {
     need(op && avg_ms, "NULL argument");
     need(which >= 0 && which <= 2, "which must be DL_APPLY_M, DL_APPLY_MDAG or DL_APPLY_G5M");
-    need(prec == DL_FP64 || prec == DL_FP32, "prec must be DL_FP64 or DL_FP32");
+    need(prec == DL_FP64 || prec == DL_FP32 || prec == DL_BF16, "prec must be DL_FP64, DL_FP32 or DL_BF16");
     need(nrhs >= 1 && nrhs <= 256 && reps >= 1, "need 1 <= nrhs <= 256 and reps >= 1");
     use_device(op->ctx);
     hipStream_t s = op->ctx->stream;
@@ -491,6 +508,19 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
       DL_HIP(hipEventRecord(b, s));
       DL_HIP(hipEventSynchronize(b));
       bb = (double)lat.V * (576.0 + 384.0 * nrhs);
+    } else if (prec == DL_BF16) {
+      DBuf<bf2> in(n), out(n);
+      zero(s, n / 4, reinterpret_cast<double2*>(in.get()));  // n bf2 = n/4 double2 (nc is a multiple of 4)
+      const float2* U32 = op_links32_public(op);
+      wilson_batched<float>(s, lat, U32, op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr, nullptr,
+                            nullptr, cfg);
+      DL_HIP(hipEventRecord(a, s));
+      for (int i = 0; i < reps; ++i)
+        wilson_batched<float>(s, lat, U32, op->kappa, which, in.get(), out.get(), lat.nc, nrhs, 0, nullptr,
+                              nullptr, nullptr, cfg);
+      DL_HIP(hipEventRecord(b, s));
+      DL_HIP(hipEventSynchronize(b));
+      bb = (double)lat.V * (288.0 + 96.0 * nrhs);
     } else {
       DBuf<float2> in(n), out(n);
       zero(s, n / 2, reinterpret_cast<double2*>(in.get()));  // n float2 = n/2 double2 (nc is even)
@@ -517,7 +547,7 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
 int dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* order, double* best_us) {
   return guard([&] {
     need(op != nullptr, "op is NULL");
-    need(prec == DL_FP64 || prec == DL_FP32, "prec must be DL_FP64 or DL_FP32");
+    need(prec == DL_FP64 || prec == DL_FP32 || prec == DL_BF16, "prec must be DL_FP64, DL_FP32 or DL_BF16");
     need(nrhs >= 1 && nrhs <= 256 && reps >= 1, "need 1 <= nrhs <= 256 and reps >= 1");
     use_device(op->ctx);
     double us = 0.0;

@@ -61,6 +61,27 @@ __device__ __forceinline__ float2 c_axpy(float s, float2 a, float2 acc) {
   return make_float2(fmaf(s, a.x, acc.x), fmaf(s, a.y, acc.y));
 }
 
+// Storage loads and stores: FP32/FP64 as is, BF16 widened to / rounded from FP32.
+__device__ __forceinline__ float2 sld(const float2* p) { return *p; }
+__device__ __forceinline__ double2 sld(const double2* p) { return *p; }
+__device__ __forceinline__ float2 sld(const bf2* p) {
+  const bf2 b = *p;
+  return make_float2(__uint_as_float((unsigned)b.x << 16), __uint_as_float((unsigned)b.y << 16));
+}
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ void sst(float2* p, float2 v) { *p = v; }
+__device__ __forceinline__ void sst(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void sst(bf2* p, float2 v) {
+  bf2 b;
+  b.x = f2bf(v.x);
+  b.y = f2bf(v.y);
+  *p = b;
+}
+
 template <class R> struct CT;
 template <> struct CT<double> {
   using type = double2;

@@ -24,6 +24,11 @@
 
 namespace dl {
 
+// BF16 complex storage: the upper halves of the two FP32 parts (round to nearest even).
+struct __align__(4) bf2 {
+  unsigned short x, y;
+};
+
 // complex element type of a real type: double -> double2, float -> float2
 template <class R>
 using cplx_t = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
@@ -158,9 +163,10 @@ void gamma5_f64(hipStream_t s, const Lattice& lat, const double2* in, double2* o
 // Partials (red != 0) are column-major [nrhs][wilson_nbs(lat)].  Returns wilson_nbs(lat) or 0.
 int wilson_nbs(const Lattice& lat, const WilsonCfg& cfg);
 int wilson_max_nbs(const Lattice& lat);  // partials per rhs of the widest-grid variant
-template <class R>
+// SV: spinor storage (double2 with R = double; float2 or bf2 with R = float); arithmetic in R.
+template <class R, class SV>
 int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,
-                   const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int red, const double* scale,
+                   const SV* in, SV* out, long fstride, int nrhs, int red, const double* scale,
                    const int* active, double* part, WilsonCfg cfg = WilsonCfg());
 
 // Several lattices in one stencil launch (the multi-lattice batched solver): one item per
@@ -174,10 +180,10 @@ struct WilsonItem {
   int rhs0, nrhs, nbs, block0;
 };
 // Partials (red != 0) are column-major [rhs][pstride], pstride >= every item's nbs.
-template <class R>
+template <class R, class SV>
 void wilson_multi(hipStream_t s, const WilsonItem* d_items, int nitems, int nblocks, int pstride, int which,
-                  const cplx_t<R>* in, cplx_t<R>* out, const long* offs, int red, const double* scale,
-                  const int* active, double* part);
+                  const SV* in, SV* out, const long* offs, int red, const double* scale, const int* active,
+                  double* part);
 
 // ---- launchers: BLAS-1 ------------------------------------------------------
 int nblocks_for(long n);  // partial count used by the streaming reductions for length n
@@ -192,5 +198,7 @@ void copy(hipStream_t s, long n, const double2* a, double2* b);
 void zero(hipStream_t s, long n, double2* a);
 void round_f32(hipStream_t s, long n, const double2* a, float2* b);  // b = (float) a
 void widen_f64(hipStream_t s, long n, const float2* a, double2* b);  // b = (double) a
+void round_bf16(hipStream_t s, long n, const double2* a, bf2* b);    // b = bf16(float(a)), nearest even
+void widen_bf16(hipStream_t s, long n, const bf2* a, double2* b);    // b = (double) a
 
 }  // namespace dl

@@ -94,8 +94,8 @@ void append_cache(const std::string& key, const WilsonCfg& c, double us) {
   if (out) out << key << ' ' << c.variant << ' ' << c.order << ' ' << us << '\n';
 }
 
-template <class R>
-double time_cfg(dl_op* op, const cplx_t<R>* U, const cplx_t<R>* in, cplx_t<R>* out, int nrhs, WilsonCfg c, int reps,
+template <class R, class SV>
+double time_cfg(dl_op* op, const cplx_t<R>* U, const SV* in, SV* out, int nrhs, WilsonCfg c, int reps,
                 hipEvent_t a, hipEvent_t b) {
   hipStream_t s = op->ctx->stream;
   wilson_batched<R>(s, op->lat, U, op->kappa, 2, in, out, op->lat.nc, nrhs, 0, nullptr, nullptr, nullptr, c);
@@ -120,7 +120,7 @@ WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) 
   DL_HIP(hipEventCreate(&b));
   WilsonCfg best;
   double best_t = 1e300;
-  DBuf<double2> in, out;  // FP64: n double2 each; FP32 uses the first half as float2
+  DBuf<double2> in, out;  // FP64: n double2 each; FP32 uses the first half as float2, BF16 a quarter
   in.alloc(prec == DL_FP64 ? n : (n + 1) / 2);
   out.alloc(prec == DL_FP64 ? n : (n + 1) / 2);
   zero(op->ctx->stream, (long)in.n, in.get());
@@ -132,12 +132,15 @@ WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) 
       double t;
       if (prec == DL_FP64)
         t = time_cfg<double>(op, op->U.get(), in.get(), out.get(), nrhs, c, reps, a, b);
-      else
+      else if (prec == DL_FP32)
         t = time_cfg<float>(op, op_links32_public(op), reinterpret_cast<float2*>(in.get()),
                             reinterpret_cast<float2*>(out.get()), nrhs, c, reps, a, b);
+      else
+        t = time_cfg<float>(op, op_links32_public(op), reinterpret_cast<bf2*>(in.get()),
+                            reinterpret_cast<bf2*>(out.get()), nrhs, c, reps, a, b);
       if (verbose()) {
         std::fprintf(stderr, "[deflan] tune %s nrhs %d variant %d order %d: %.1f us\n",
-                     prec == DL_FP64 ? "fp64" : "fp32", nrhs, v, o, t);
+                     prec == DL_FP64 ? "fp64" : prec == DL_FP32 ? "fp32" : "bf16", nrhs, v, o, t);
         std::fflush(stderr);
       }
       if (t < best_t) {

@@ -129,12 +129,12 @@ __device__ __forceinline__ void mul_half(const C u[9], const C h[6], C g[6]) {
 // components at up[e * ustride]), project, multiply by U (forward) or U^dag (backward,
 // link taken at the neighbour), rebuild and accumulate.  Every load address depends on
 // mu, so the loads of different directions cannot be hoisted ahead of each other.
-template <int S, bool DAG, class C>
-__device__ __forceinline__ void hop_at(const C* up, int ustride, const C* in, int mu, int nb, C acc[12]) {
+template <int S, bool DAG, class C, class SV>
+__device__ __forceinline__ void hop_at(const C* up, int ustride, const SV* in, int mu, int nb, C acc[12]) {
   C p[12], h[6], g[6], u[9];
-  const C* pp = in + sp_base(nb);
+  const SV* pp = in + sp_base(nb);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+  for (int c = 0; c < 12; ++c) p[c] = sld(pp + c * kTile);
 #pragma unroll
   for (int e = 0; e < 9; ++e) u[e] = up[e * ustride];
   project_mu<S>(mu, p, h);
@@ -142,8 +142,8 @@ __device__ __forceinline__ void hop_at(const C* up, int ustride, const C* in, in
   reconstruct_mu<S>(mu, acc, g);
 }
 
-template <int S, bool DAG, class C>
-__device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int lsite, C acc[12]) {
+template <int S, bool DAG, class C, class SV>
+__device__ __forceinline__ void hop(const C* U, const SV* in, int mu, int nb, int lsite, C acc[12]) {
   hop_at<S, DAG>(U + lk_base(lsite, mu), kTile, in, mu, nb, acc);
 }
 
@@ -155,18 +155,17 @@ __device__ __forceinline__ void hop(const C* U, const C* in, int mu, int nb, int
 // fastest, XCD-contiguous; 2: rhs fastest, hardware block order.
 // One site of the stencil for one field (zeroes padding sites); returns the fused
 // reduction term (||out||^2 or Re<in, out>) of the site.
-template <class R, int WHICH, int RED>
+template <class R, class SV, int WHICH, int RED>
 __device__ __forceinline__ double wilson_site(const typename CT<R>::type* __restrict__ U,
-                                              const typename CT<R>::type* __restrict__ in,
-                                              typename CT<R>::type* __restrict__ out, double kappa, int Lx, int Ly,
+                                              const SV* __restrict__ in, SV* __restrict__ out, double kappa, int Lx, int Ly,
                                               int Lz, int Lt, long V, long Vpad, int site, R sc) {
   using C = typename CT<R>::type;
   double red = 0.0;
   if (site >= V && site < Vpad) {
     // padding sites of the last tile are kept at zero
-    C* op = out + sp_base(site);
+    SV* op = out + sp_base(site);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
+    for (int c = 0; c < 12; ++c) sst(op + c * kTile, CT<R>::make(0, 0));
   }
   if (site < V) {
     const int x = site % Lx;
@@ -193,14 +192,14 @@ __device__ __forceinline__ double wilson_site(const typename CT<R>::type* __rest
       hop<-SF, true>(U, in, mu, site + db, site + db, acc);
     }
     const R mk = (R)(-kappa);
-    const C* ip = in + sp_base(site);
-    C* op = out + sp_base(site);
+    const SV* ip = in + sp_base(site);
+    SV* op = out + sp_base(site);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      const C p = ip[c * kTile];
+      const C p = sld(ip + c * kTile);
       C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
       if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
-      op[c * kTile] = r;
+      sst(op + c * kTile, r);
       if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
       if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
     }
@@ -208,10 +207,10 @@ __device__ __forceinline__ double wilson_site(const typename CT<R>::type* __rest
   return red;
 }
 
-template <class R, int WHICH, int RED, int NT, int OCC>
+template <class R, class SV, int WHICH, int RED, int NT, int OCC>
 __global__ void __launch_bounds__(NT, OCC)
-k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
-         typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+k_wilson(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
+         SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
          int Lt, long V, long Vpad, int nbs, int order, const double* __restrict__ scale,
          const int* __restrict__ active, double* __restrict__ part) {
   const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
@@ -220,7 +219,7 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
   if (active && !active[rhs]) return;
   const int site = sb * NT + (int)threadIdx.x;
   const R sc = scale ? (R)scale[rhs] : (R)1;
-  const double red = wilson_site<R, WHICH, RED>(U, in + rhs * fstride, out + rhs * fstride, kappa, Lx, Ly, Lz, Lt,
+  const double red = wilson_site<R, SV, WHICH, RED>(U, in + rhs * fstride, out + rhs * fstride, kappa, Lx, Ly, Lz, Lt,
                                                 V, Vpad, site, sc);
   if (RED != 0) {
     __shared__ double lds[NT / 64];
@@ -236,10 +235,10 @@ k_wilson(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type*
 // starts at offs[j] (complex elements).  Partials: part[rhs * pstride + site block]; the
 // first site block of each rhs zeroes the tail up to pstride, so every rhs reduces over
 // pstride partials.
-template <class R, int WHICH, int RED>
+template <class R, class SV, int WHICH, int RED>
 __global__ void __launch_bounds__(256, 2)
-k_wilson_ml(const WilsonItem* __restrict__ items, int nitems, const typename CT<R>::type* __restrict__ in,
-            typename CT<R>::type* __restrict__ out, const long* __restrict__ offs, int pstride,
+k_wilson_ml(const WilsonItem* __restrict__ items, int nitems, const SV* __restrict__ in,
+            SV* __restrict__ out, const long* __restrict__ offs, int pstride,
             const double* __restrict__ scale, const int* __restrict__ active, double* __restrict__ part) {
   using C = typename CT<R>::type;
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -253,7 +252,7 @@ k_wilson_ml(const WilsonItem* __restrict__ items, int nitems, const typename CT<
   const int site = sb * 256 + (int)threadIdx.x;
   const R sc = scale ? (R)scale[rhs] : (R)1;
   const long off = offs[rhs];
-  const double red = wilson_site<R, WHICH, RED>(static_cast<const C*>(w.U), in + off, out + off, w.kappa, w.L[0],
+  const double red = wilson_site<R, SV, WHICH, RED>(static_cast<const C*>(w.U), in + off, out + off, w.kappa, w.L[0],
                                                 w.L[1], w.L[2], w.L[3], w.V, w.Vpad, site, sc);
   if (RED != 0) {
     __shared__ double lds[256 / 64];
@@ -264,12 +263,12 @@ k_wilson_ml(const WilsonItem* __restrict__ items, int nitems, const typename CT<
   }
 }
 
-template <class R>
+template <class R, class SV>
 void wilson_multi(hipStream_t s, const WilsonItem* d_items, int nitems, int nblocks, int pstride, int which,
-                  const cplx_t<R>* in, cplx_t<R>* out, const long* offs, int red, const double* scale,
-                  const int* active, double* part) {
-#define DL_ML(WH, RD)                                                                                      \
-  hipLaunchKernelGGL((k_wilson_ml<R, WH, RD>), dim3(nblocks), dim3(256), 0, s, d_items, nitems, in, out, offs, \
+                  const SV* in, SV* out, const long* offs, int red, const double* scale, const int* active,
+                  double* part) {
+#define DL_ML(WH, RD)                                                                                          \
+  hipLaunchKernelGGL((k_wilson_ml<R, SV, WH, RD>), dim3(nblocks), dim3(256), 0, s, d_items, nitems, in, out, offs, \
                      pstride, scale, active, part)
   if (which == 0) { if (red == 0) DL_ML(0, 0); else if (red == 1) DL_ML(0, 1); else DL_ML(0, 2); }
   else if (which == 1) { if (red == 0) DL_ML(1, 0); else if (red == 1) DL_ML(1, 1); else DL_ML(1, 2); }
@@ -278,10 +277,12 @@ void wilson_multi(hipStream_t s, const WilsonItem* d_items, int nitems, int nblo
   DL_HIP(hipGetLastError());
 }
 
-template void wilson_multi<double>(hipStream_t, const WilsonItem*, int, int, int, int, const double2*, double2*,
-                                   const long*, int, const double*, const int*, double*);
-template void wilson_multi<float>(hipStream_t, const WilsonItem*, int, int, int, int, const float2*, float2*,
-                                  const long*, int, const double*, const int*, double*);
+template void wilson_multi<double, double2>(hipStream_t, const WilsonItem*, int, int, int, int, const double2*,
+                                            double2*, const long*, int, const double*, const int*, double*);
+template void wilson_multi<float, float2>(hipStream_t, const WilsonItem*, int, int, int, int, const float2*, float2*,
+                                          const long*, int, const double*, const int*, double*);
+template void wilson_multi<float, bf2>(hipStream_t, const WilsonItem*, int, int, int, int, const bf2*, bf2*,
+                                       const long*, int, const double*, const int*, double*);
 
 // t-marching form of the same operator.  A thread owns one (x, y, z) site and walks
 // T consecutive time slices t0 .. t0+T-1 of it.  The forward-t neighbour psi(t+1)
@@ -292,10 +293,10 @@ template void wilson_multi<float>(hipStream_t, const WilsonItem*, int, int, int,
 // blocks of one XCD walk together, so they come from L2.  A block is NT consecutive
 // (x, y, z) sites of one time chunk of one right-hand side; logical block = (site block,
 // rhs) with the same order options as k_wilson.
-template <class R, int WHICH, int RED, int NT>
+template <class R, class SV, int WHICH, int RED, int NT>
 __global__ void __launch_bounds__(NT)
-k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
-            typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
+            SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
             int Lt, long V, long Vpad, int T, int nb3, int nbs, int order, const double* __restrict__ scale,
             const int* __restrict__ active, double* __restrict__ part) {
   using C = typename CT<R>::type;
@@ -312,9 +313,9 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::ty
   if (b3 == 0 && (tc + 1) * T >= Lt) {
     // padding sites of the last tile are kept at zero (written by the last chunk's first block)
     for (long sp = V + threadIdx.x; sp < Vpad; sp += NT) {
-      C* op = out + sp_base((int)sp);
+      SV* op = out + sp_base((int)sp);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
+      for (int c = 0; c < 12; ++c) sst(op + c * kTile, CT<R>::make(0, 0));
     }
   }
   if (s3 < V3) {
@@ -336,17 +337,17 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::ty
       const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
       const int sprev = tp * V3 + s3;
       C p[12], h[6], u[9];
-      const C* pp = in + sp_base(sprev);
+      const SV* pp = in + sp_base(sprev);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+      for (int c = 0; c < 12; ++c) p[c] = sld(pp + c * kTile);
       const C* up = U + lk_base(sprev, 3);
 #pragma unroll
       for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
       project<3, -SF>(p, h);
       mul_half<true>(u, h, gb);
-      const C* cp = in + sp_base(t0 * V3 + s3);
+      const SV* cp = in + sp_base(t0 * V3 + s3);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) cen[c] = cp[c * kTile];
+      for (int c = 0; c < 12; ++c) cen[c] = sld(cp + c * kTile);
     }
 #pragma unroll 1
     for (int t = t0; t < t1; ++t) {
@@ -367,9 +368,9 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::ty
       const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
       C nx[12], u[9];
       {
-        const C* pp = in + sp_base(snext);
+        const SV* pp = in + sp_base(snext);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) nx[c] = pp[c * kTile];
+        for (int c = 0; c < 12; ++c) nx[c] = sld(pp + c * kTile);
         const C* up = U + lk_base(site, 3);
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
@@ -382,13 +383,13 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::ty
         project<3, -SF>(cen, h);
         mul_half<true>(u, h, gb);
       }
-      C* op = out + sp_base(site);
+      SV* op = out + sp_base(site);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const C p = cen[c];
         C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
         if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
-        op[c * kTile] = r;
+        sst(op + c * kTile, r);
         if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
         if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
       }
@@ -410,10 +411,10 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const typename CT<R>::ty
 // 16 x 16 plane per block that is all of them), the z neighbours and the z, t links come
 // from memory, and the t hops are carried along t as in k_wilson_tm.  Same arithmetic and
 // order as k_wilson.
-template <class R, int WHICH, int RED, int NT, bool LK>
+template <class R, class SV, int WHICH, int RED, int NT, bool LK>
 __global__ void __launch_bounds__(NT)
-k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
-             typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
+             SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
              int Lt, long V, long Vpad, int T, int nb3, int nbs, int order, const double* __restrict__ scale,
              const int* __restrict__ active, double* __restrict__ part) {
   using C = typename CT<R>::type;
@@ -434,9 +435,9 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
   double red = 0.0;
   if (b3 == 0 && (tc + 1) * T >= Lt) {
     for (long sp = V + tid; sp < Vpad; sp += NT) {
-      C* op = out + sp_base((int)sp);
+      SV* op = out + sp_base((int)sp);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
+      for (int c = 0; c < 12; ++c) sst(op + c * kTile, CT<R>::make(0, 0));
     }
   }
   int x = 0, y = 0, z = 0;
@@ -459,17 +460,17 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
     const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
     const int sprev = tp * V3 + s3;
     C p[12], h[6], u[9];
-    const C* pp = in + sp_base(sprev);
+    const SV* pp = in + sp_base(sprev);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+    for (int c = 0; c < 12; ++c) p[c] = sld(pp + c * kTile);
     const C* up = U + lk_base(sprev, 3);
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
     project<3, -SF>(p, h);
     mul_half<true>(u, h, gb);
-    const C* cp = in + sp_base(t0 * V3 + s3);
+    const SV* cp = in + sp_base(t0 * V3 + s3);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) cen[c] = cp[c * kTile];
+    for (int c = 0; c < 12; ++c) cen[c] = sld(cp + c * kTile);
   }
 #pragma unroll 1
   for (int t = t0; t < t1; ++t) {
@@ -504,9 +505,9 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
 #pragma unroll
           for (int c = 0; c < 12; ++c) p[c] = ps[c * NT + li];
         } else {
-          const C* pp = in + sp_base(site + d);
+          const SV* pp = in + sp_base(site + d);
 #pragma unroll
-          for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+          for (int c = 0; c < 12; ++c) p[c] = sld(pp + c * kTile);
         }
         if (LK && fwd && mu < 2) {
 #pragma unroll
@@ -532,9 +533,9 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
       const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
       C nx[12], u[9];
       {
-        const C* pp = in + sp_base(snext);
+        const SV* pp = in + sp_base(snext);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) nx[c] = pp[c * kTile];
+        for (int c = 0; c < 12; ++c) nx[c] = sld(pp + c * kTile);
         const C* up = U + lk_base(site, 3);
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
@@ -546,13 +547,13 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
         project<3, -SF>(cen, h);
         mul_half<true>(u, h, gb);
       }
-      C* op = out + sp_base(site);
+      SV* op = out + sp_base(site);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const C p = cen[c];
         C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
         if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
-        op[c * kTile] = r;
+        sst(op + c * kTile, r);
         if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
         if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
       }
@@ -574,10 +575,10 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
 // link leaves L2 once per RB right-hand sides instead of once per right-hand side.  The
 // t hops are carried along t as in k_wilson_tm; the arithmetic and its order are the
 // same as in k_wilson.  Logical block = (site block, rhs group).
-template <class R, int WHICH, int RED, int RB>
+template <class R, class SV, int WHICH, int RED, int RB>
 __global__ void __launch_bounds__(64 * RB)
-k_wilson_tml(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ in,
-             typename CT<R>::type* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+k_wilson_tml(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
+             SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
              int Lt, long V, long Vpad, int T, int nb3, int nbs, int ngroups, int order,
              const double* __restrict__ scale, const int* __restrict__ active, double* __restrict__ part) {
   using C = typename CT<R>::type;
@@ -606,9 +607,9 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
   }
   if (on && b3 == 0 && (tc + 1) * T >= Lt) {
     for (long sp = V + lane; sp < Vpad; sp += 64) {
-      C* op = out + sp_base((int)sp);
+      SV* op = out + sp_base((int)sp);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) op[c * kTile] = CT<R>::make(0, 0);
+      for (int c = 0; c < 12; ++c) sst(op + c * kTile, CT<R>::make(0, 0));
     }
   }
   int x = 0, y = 0, z = 0;
@@ -633,17 +634,17 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
     const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
     const int sprev = tp * V3 + s3;
     C p[12], h[6], u[9];
-    const C* pp = in + sp_base(sprev);
+    const SV* pp = in + sp_base(sprev);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[c] = pp[c * kTile];
+    for (int c = 0; c < 12; ++c) p[c] = sld(pp + c * kTile);
     const C* up = U + lk_base(sprev, 3);
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
     project<3, -SF>(p, h);
     mul_half<true>(u, h, gb);
-    const C* cp = in + sp_base(t0 * V3 + s3);
+    const SV* cp = in + sp_base(t0 * V3 + s3);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) cen[c] = cp[c * kTile];
+    for (int c = 0; c < 12; ++c) cen[c] = sld(cp + c * kTile);
   }
 #pragma unroll 1
   for (int t = t0; t < t1; ++t) {
@@ -674,9 +675,9 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
       const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
       C nx[12], u[9];
       {
-        const C* pp = in + sp_base(snext);
+        const SV* pp = in + sp_base(snext);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) nx[c] = pp[c * kTile];
+        for (int c = 0; c < 12; ++c) nx[c] = sld(pp + c * kTile);
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = lu[(6 * 9 + e) * 64 + lane];
         C h[6], g[6];
@@ -687,13 +688,13 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const typename CT<R>::t
         project<3, -SF>(cen, h);
         mul_half<true>(u, h, gb);
       }
-      C* op = out + sp_base(site);
+      SV* op = out + sp_base(site);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const C p = cen[c];
         C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
         if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
-        op[c * kTile] = r;
+        sst(op + c * kTile, r);
         if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
         if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
       }
@@ -720,80 +721,80 @@ static int tm_nb3(const Lattice& lat, int v) {
 }
 static int tm_chunks(const Lattice& lat, int v) { return (lat.L[3] + kVariantT[v] - 1) / kVariantT[v]; }
 
-template <class R, int WHICH, int RED, int NT>
-static void launch_tm(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
-                      cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+template <class R, class SV, int WHICH, int RED, int NT>
+static void launch_tm(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const SV* in,
+                      SV* out, long fstride, int nrhs, int order, const double* scale, const int* active,
                       double* part, int nbs, int v) {
   const int* L = lat.L;
-  hipLaunchKernelGGL((k_wilson_tm<R, WHICH, RED, NT>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
+  hipLaunchKernelGGL((k_wilson_tm<R, SV, WHICH, RED, NT>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
                      order, scale, active, part);
 }
 
-template <class R, int WHICH, int RED, int NT, int OCC>
-static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
-                       cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+template <class R, class SV, int WHICH, int RED, int NT, int OCC>
+static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const SV* in,
+                       SV* out, long fstride, int nrhs, int order, const double* scale, const int* active,
                        double* part, int nbs) {
   const int* L = lat.L;
-  hipLaunchKernelGGL((k_wilson<R, WHICH, RED, NT, OCC>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
+  hipLaunchKernelGGL((k_wilson<R, SV, WHICH, RED, NT, OCC>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, nbs, order, scale, active, part);
 }
 
-template <class R, int WHICH, int RED, int NT, bool LK>
-static void launch_tmp(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
-                       cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+template <class R, class SV, int WHICH, int RED, int NT, bool LK>
+static void launch_tmp(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const SV* in,
+                       SV* out, long fstride, int nrhs, int order, const double* scale, const int* active,
                        double* part, int nbs, int v) {
   const int* L = lat.L;
-  hipLaunchKernelGGL((k_wilson_tmp<R, WHICH, RED, NT, LK>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride,
+  hipLaunchKernelGGL((k_wilson_tmp<R, SV, WHICH, RED, NT, LK>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride,
                      nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
                      order, scale, active, part);
 }
 
-template <class R, int WHICH, int RED, int RB>
-static void launch_tml(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const cplx_t<R>* in,
-                       cplx_t<R>* out, long fstride, int nrhs, int order, const double* scale, const int* active,
+template <class R, class SV, int WHICH, int RED, int RB>
+static void launch_tml(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const SV* in,
+                       SV* out, long fstride, int nrhs, int order, const double* scale, const int* active,
                        double* part, int nbs, int v) {
   const int* L = lat.L;
   const int ngroups = (nrhs + RB - 1) / RB;
-  hipLaunchKernelGGL((k_wilson_tml<R, WHICH, RED, RB>), dim3(nbs * ngroups), dim3(64 * RB), 0, s, U, in, out,
+  hipLaunchKernelGGL((k_wilson_tml<R, SV, WHICH, RED, RB>), dim3(nbs * ngroups), dim3(64 * RB), 0, s, U, in, out,
                      fstride, nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v],
                      tm_nb3(lat, v), nbs, ngroups, order, scale, active, part);
 }
 
-template <class R, int WHICH, int RED>
+template <class R, class SV, int WHICH, int RED>
 static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa,
-                           const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int order,
+                           const SV* in, SV* out, long fstride, int nrhs, int order,
                            const double* scale, const int* active, double* part, int nbs) {
   switch (variant) {
-    case 1: launch_one<R, WHICH, RED, 128, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
-    case 2: launch_one<R, WHICH, RED, 512, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
-    case 3: launch_one<R, WHICH, RED, 256, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    case 1: launch_one<R, SV, WHICH, RED, 128, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    case 2: launch_one<R, SV, WHICH, RED, 512, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    case 3: launch_one<R, SV, WHICH, RED, 256, 1>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
     case 4: case 5: case 6:
-      launch_tm<R, WHICH, RED, 256>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      launch_tm<R, SV, WHICH, RED, 256>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
       break;
     case 7: case 8:
-      launch_tml<R, WHICH, RED, 4>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      launch_tml<R, SV, WHICH, RED, 4>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
       break;
     case 9:
-      launch_tml<R, WHICH, RED, 8>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      launch_tml<R, SV, WHICH, RED, 8>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
       break;
     case 10:
-      launch_tml<R, WHICH, RED, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
+      launch_tml<R, SV, WHICH, RED, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs, variant);
       break;
     case 11:
       // FP64 spinors and links of a slice together exceed the LDS budget: the FP64 form stages spinors only
       if constexpr (sizeof(R) == 4)
-        launch_tmp<R, WHICH, RED, 256, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
+        launch_tmp<R, SV, WHICH, RED, 256, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
                                              nbs, variant);
       else
-        launch_tmp<R, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
+        launch_tmp<R, SV, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
                                               nbs, variant);
       break;
     case 12: case 13:
-      launch_tmp<R, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs,
+      launch_tmp<R, SV, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs,
                                             variant);
       break;
-    default: launch_one<R, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
+    default: launch_one<R, SV, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
   }
 }
 
@@ -810,16 +811,16 @@ int wilson_max_nbs(const Lattice& lat) {
   return m;
 }
 
-template <class R>
+template <class R, class SV>
 int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,
-                   const cplx_t<R>* in, cplx_t<R>* out, long fstride, int nrhs, int red, const double* scale,
+                   const SV* in, SV* out, long fstride, int nrhs, int red, const double* scale,
                    const int* active, double* part, WilsonCfg cfg) {
   const int v = cfg.variant % kWilsonVariants;
   const int nbs = wilson_nbs(lat, cfg);
   if (red && nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
   if ((long)nbs * nrhs > 2147483647L) fail(DL_E_INVALID, "grid too large");
   const int o = cfg.order;
-#define DL_W(WH, RD) launch_variant<R, WH, RD>(v, s, lat, U, kappa, in, out, fstride, nrhs, o, scale, active, part, nbs)
+#define DL_W(WH, RD) launch_variant<R, SV, WH, RD>(v, s, lat, U, kappa, in, out, fstride, nrhs, o, scale, active, part, nbs)
   if (which == 0) { if (red == 0) DL_W(0, 0); else if (red == 1) DL_W(0, 1); else DL_W(0, 2); }
   else if (which == 1) { if (red == 0) DL_W(1, 0); else if (red == 1) DL_W(1, 1); else DL_W(1, 2); }
   else { if (red == 0) DL_W(2, 0); else if (red == 1) DL_W(2, 1); else DL_W(2, 2); }
@@ -828,14 +829,16 @@ int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double
   return red ? nbs : 0;
 }
 
-template int wilson_batched<double>(hipStream_t, const Lattice&, const double2*, double, int, const double2*,
-                                    double2*, long, int, int, const double*, const int*, double*, WilsonCfg);
-template int wilson_batched<float>(hipStream_t, const Lattice&, const float2*, double, int, const float2*, float2*,
-                                   long, int, int, const double*, const int*, double*, WilsonCfg);
+template int wilson_batched<double, double2>(hipStream_t, const Lattice&, const double2*, double, int, const double2*,
+                                             double2*, long, int, int, const double*, const int*, double*, WilsonCfg);
+template int wilson_batched<float, float2>(hipStream_t, const Lattice&, const float2*, double, int, const float2*,
+                                           float2*, long, int, int, const double*, const int*, double*, WilsonCfg);
+template int wilson_batched<float, bf2>(hipStream_t, const Lattice&, const float2*, double, int, const bf2*, bf2*,
+                                        long, int, int, const double*, const int*, double*, WilsonCfg);
 
 int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,
                const double2* in, double2* out, int red, double* part, WilsonCfg cfg) {
-  return wilson_batched<double>(s, lat, U, kappa, which, in, out, lat.nc, 1, red, nullptr, nullptr, part, cfg);
+  return wilson_batched<double, double2>(s, lat, U, kappa, which, in, out, lat.nc, 1, red, nullptr, nullptr, part, cfg);
 }
 
 __global__ void k_gamma5_f64(const double2* __restrict__ in, double2* __restrict__ out, long nc) {

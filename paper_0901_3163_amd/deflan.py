@@ -39,7 +39,8 @@ class dl_first_opts(C.Structure):
 
 class dl_next_opts(C.Structure):
     _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
-                ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p), ("graph", C.c_int)]
+                ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p), ("graph", C.c_int),
+                ("inner_drop", C.c_double)]
 
 
 class dl_batch_item(C.Structure):
@@ -283,12 +284,13 @@ class Operator:
         return x, eig, dict(st.as_dict(), rc=rc)
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
-                   reliable_every=None, net=None, graph=False):
+                   reliable_every=None, net=None, graph=False, inner_drop=None):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
         o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
-                         int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0)
+                         int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0,
+                         float(inner_drop or 0.0))
         st = (dl_stats * max(nrhs, 1))()
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
@@ -400,7 +402,8 @@ def num_weights() -> int:
     return int(lib.dl_net_num_weights())
 
 
-def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s=None, graph=False):
+def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s=None, graph=False,
+                     storage=DL_FP32, inner_drop=None):
     """Later right-hand sides of several operators in one batched solve.
 
     items: sequence of (op, eig or None, B [nrhs][V][4][3], tol); all B numpy (host) or all
@@ -419,8 +422,8 @@ def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s
         its[i] = dl_batch_item(op.h, eig.h if eig is not None else None, int(B.shape[0]), pB, pX, float(tol))
         keep.append(B)
         Xs.append(X)
-    o = dl_next_opts(DL_FP32, int(reliable_every or 0), 1, 1 if x0s is not None else 0, int(max_mvp or 0), None,
-                     1 if graph else 0)
+    o = dl_next_opts(int(storage), int(reliable_every or 0), 1, 1 if x0s is not None else 0, int(max_mvp or 0), None,
+                     1 if graph else 0, float(inner_drop or 0.0))
     ntot = sum(int(B.shape[0]) for B in keep)
     st = (dl_stats * max(ntot, 1))()
     rc = _check(lib.dl_solve_next_multi(ctx.h, len(items), its, mem if mem is not None else DL_HOST, C.byref(o), st))

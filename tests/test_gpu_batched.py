@@ -83,7 +83,35 @@ def test_batched_rejects_bad_options(gpu_ctx, c1_config):
     with pytest.raises(deflan.DeflanError):
         op.solve_next(B, None, 1e-10, storage=deflan.DL_FP32, batched=0)
     with pytest.raises(deflan.DeflanError):
-        op.solve_next(B, None, 1e-10, storage=deflan.DL_BF16, batched=1)
+        op.solve_next(B, None, 1e-10, storage=deflan.DL_BF16, batched=0)
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(B, None, 1e-10, storage=deflan.DL_FP32, batched=1, inner_drop=2.0)
+    op.close()
+
+
+@pytest.mark.parametrize("kind", ["g5m", "mdagm"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_bf16_storage(gpu_ctx, c1_config, kind, graph):
+    """BF16 Krylov vectors and stencil input/output (FP32 arithmetic and links, FP64 residuals,
+    projection and solution): every rhs reaches tol 1e-10 (1e-11 is the M^dag M floor, not
+    asked here) and the dense solution, with and without graph replay."""
+    from paper_0901_3163_amd import deflan
+    dims, U, kappa = c1_config["dims"], c1_config["links"], c1_config["kappa"]
+    k = deflan.DL_G5M if kind == "g5m" else deflan.DL_MDAGM
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, k)
+    _, eig, _ = op.solve_first(gaussian_spinor(dims, 100), 60, 20, 1e-10)
+    B = np.stack([gaussian_spinor(dims, 160 + i) for i in range(3)] + [point_source(dims, 4, 3, 1),
+                                                                        np.zeros_like(gaussian_spinor(dims, 1))])
+    X, sts, rc = op.solve_next(B, eig, 1e-10, storage=deflan.DL_BF16, batched=1, graph=graph)
+    assert rc == deflan.DL_OK
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    M = dirac.dense(ora.M, ora.n)
+    for i in range(4):
+        r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+        assert sts[i]["relres"] <= 1e-10 and r <= 1.0001e-10, (i, r)
+        assert _rel(X[i], np.linalg.solve(M, B[i].ravel())) < 1e-6
+    assert np.all(X[4] == 0)
+    eig.close()
     op.close()
 
 
