@@ -6,19 +6,19 @@ U = exp(0.5 i X), seed 0; kappa from the oracle's kappa search, min|lambda(gamma
 for a Gaussian first right-hand side (seed 200), and the training of the
 learned-guess network on 24 point sources at other sites of the same field.
 One timed step: D-MinRes for the 12 spin-colour point sources e_{site 0, spin s,
-colour c} on the fast path (FP32 Krylov vectors and Wilson apply for all 12
-together, FP64 true residuals, projection and solution, learned initial guess),
-every one verified by its FP64 true residual <= 1e-10.  Inputs and outputs stay
-in HBM (torch complex128 device tensors passed as device pointers).  The same
-solve without the learned guess and the plain FP64 one-rhs-at-a-time D-MinRes
-are timed after it as the ablation.
+colour c} on the fast path (Krylov vectors and stencil spinors in BF16 -- or FP32
+with --storage fp32 -- FP32 arithmetic and links, all 12 rhs together, FP64 true
+residuals, projection and solution, learned initial guess), every one verified by
+its FP64 true residual <= 1e-10.  Inputs and outputs stay in HBM (torch complex128
+device tensors passed as device pointers).  The ablation (each storage with and
+without the guess) and the plain FP64 one-rhs-at-a-time D-MinRes are timed after it.
 
-value = 12 * steps / timed seconds (RHS/s).  roofline: the batched FP32 Wilson
-stencil, its average launch duration taken with HIP events on the library's
-stream around every launch inside the timed region, algorithmic bytes per launch
-= 288 B/site (links once) + 192 B/site per active rhs (input and output spinor).
-cpu_baseline: the oracle's D-MinRes on the host cores for a bounded sample of the
-same workload.
+value = 12 * steps / timed seconds (RHS/s).  roofline: the batched stencil, its
+average launch duration taken with HIP events on the library's stream around every
+launch inside the timed region, algorithmic bytes per launch = 288 B/site (FP32
+links once) + 96 (BF16) or 192 (FP32) B/site per active rhs (input and output
+spinor).  cpu_baseline: the oracle's D-MinRes on the host cores for a bounded
+sample of the same workload.  --multi: the uneven multi-lattice batch instead.
 """
 from __future__ import annotations
 
@@ -60,9 +60,9 @@ def wilson_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(dims):
+def traffic_from_profiles(dims, storage):
     """HBM bytes per Wilson launch from the committed rocprofv3 counter summary, if current."""
-    p = os.path.join(ROOT, "profiles", "wilson_f32_nrhs12_16x16x16x32_traffic.json")
+    p = os.path.join(ROOT, "profiles", f"wilson_{storage}_nrhs12_16x16x16x32_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -173,9 +173,82 @@ def train_guess(ctx, op, eig, deflan, dims, args):
     return net, info
 
 
+def multi_lattice(args):
+    """Uneven lattices in one batched solve: 16 Gaussian rhs on each of 8^4, 12^4, 16^3x32 and
+    20^3x40 (64 in all), D-CG on M^dag M with k = 40, 60, 80, 100 eigenvectors from Lan-DR(k + 40, k)
+    (setup, untimed).  Timed: one dl_solve_next_multi over all 64 rhs (with and without graph
+    replay), the same rhs as four per-lattice batched calls, and plain FP64 D-CG on 2 rhs per
+    lattice (per-rhs time, scaled to 16 rhs).  Prints one JSON line."""
+    import torch
+    from lattice_inputs import gaussian_spinor, su3_links
+    from paper_0901_3163_amd import deflan
+    os.environ.setdefault("DEFLAN_VERBOSE", "1")
+    # FP32 storage: with BF16 vectors the normal-equations CG needs about 4x the iterations
+    # (cycles limited to a 1e-2 drop each restart its recurrence), so D-CG batches run FP32
+    storage = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.multi_storage]
+    kappa, tol = 0.145, args.tol
+    lats = [((8, 8, 8, 8), 40), ((12, 12, 12, 12), 60), ((16, 16, 16, 32), 80), ((20, 20, 20, 40), 100)]
+    ctx = deflan.Context(0)
+    items, setup = [], {}
+    seed = 400
+    for j, (dims, k) in enumerate(lats):
+        U = torch.from_numpy(su3_links(dims, 10 + j)).cuda()
+        op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_MDAGM)
+        del U
+        t0 = time.time()
+        b1 = torch.from_numpy(gaussian_spinor(dims, 300 + j)).cuda()
+        _, eig, st1 = op.solve_first(b1, k + 40, k, tol)
+        torch.cuda.synchronize()
+        name = "x".join(map(str, dims))
+        setup[name] = dict(k=k, first_rhs_mvp=st1["mvp"], first_rhs_seconds=round(time.time() - t0, 2))
+        log(f"multi: {name} Lan-DR({k + 40},{k}) done, {st1['mvp']} MVPs")
+        B = torch.from_numpy(np.stack([gaussian_spinor(dims, seed + i) for i in range(16)])).cuda()
+        seed += 16
+        items.append((op, eig, B, tol))
+    nrhs = 16 * len(lats)
+    out = {}
+    for graph in (False, True):
+        deflan.solve_next_multi(ctx, items, storage=storage, graph=graph)  # warm-up (tuning, graphs)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        Xs, sts, rc = deflan.solve_next_multi(ctx, items, storage=storage, graph=graph)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        ok = rc == 0 and all(s["relres"] <= tol for ss in sts for s in ss)
+        out["one_launch_per_stage" + ("_graph" if graph else "")] = dict(
+            value=round(nrhs / dt, 3), unit="RHS/s", seconds=round(dt, 3), all_rhs_converged=bool(ok),
+            iters_per_rhs=float(np.mean([s["iters"] for ss in sts for s in ss])))
+        log(f"multi: one batch over all lattices (graph {graph}): {nrhs / dt:.2f} RHS/s")
+    t0 = time.time()
+    ok = True
+    for op, eig, B, _ in items:
+        X, st, rc = op.solve_next(B, eig, tol, storage=storage, batched=1)
+        ok &= rc == 0
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    out["per_lattice_batches"] = dict(value=round(nrhs / dt, 3), unit="RHS/s", seconds=round(dt, 3),
+                                      all_rhs_converged=bool(ok))
+    log(f"multi: four per-lattice batches: {nrhs / dt:.2f} RHS/s")
+    t_plain = 0.0
+    for op, eig, B, _ in items:
+        t0 = time.time()
+        X, st, rc = op.solve_next(B[:2], eig, tol)
+        torch.cuda.synchronize()
+        t_plain += (time.time() - t0) * 8  # 2 of 16 rhs
+    out["plain_fp64_per_rhs"] = dict(value=round(nrhs / t_plain, 3), unit="RHS/s",
+                                     sample="2 rhs per lattice, time scaled to 16")
+    res = dict(workload="uneven lattices 8^4, 12^4, 16^3x32, 20^3x40, 16 Gaussian rhs each, D-CG on M^dag M, "
+                        f"kappa {kappa}, tol {tol:g}, {args.multi_storage} storage", setup=setup, **out)
+    for op, eig, B, _ in items:
+        eig.close()
+        op.close()
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def kernel_only(args):
-    """The dominant kernel alone, for rocprofv3 counter runs: the FP32 gamma5 M stencil on the
-    16^3x32 lattice for 12 right-hand sides at once (reps launches), then a device copy of
+    """The dominant kernel alone, for rocprofv3 counter runs: the gamma5 M stencil (--storage
+    spinors) on the 16^3x32 lattice for 12 right-hand sides at once (reps launches), then a device copy of
     1 GiB (reps launches) whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
     import torch
     from paper_0901_3163_amd import deflan
@@ -183,8 +256,9 @@ def kernel_only(args):
     dims = tuple(e["dims"])
     ctx = deflan.Context(0)
     op = deflan.Operator(ctx, dims, torch.from_numpy(tiled_links(dims)).cuda(), e["kappa"], deflan.DL_G5M)
-    ms, by = op.bench_wilson(deflan.DL_APPLY_G5M, deflan.DL_FP32, 12, args.reps)
-    log(f"wilson fp32 nrhs12: {ms * 1e3:.1f} us/launch, algorithmic {by / 1e6:.1f} MB/launch")
+    prec = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.storage]
+    ms, by = op.bench_wilson(deflan.DL_APPLY_G5M, prec, 12, args.reps)
+    log(f"wilson {args.storage} nrhs12: {ms * 1e3:.1f} us/launch, algorithmic {by / 1e6:.1f} MB/launch")
     x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
     y = torch.empty_like(x)
     x.fill_(1.0)
@@ -192,7 +266,8 @@ def kernel_only(args):
         y.copy_(x)
     torch.cuda.synchronize()
     log("copy: 1 GiB read + 1 GiB written per launch")
-    print(json.dumps(dict(kernel="k_wilson<float,2,0>", dims=list(dims), nrhs=12, reps=args.reps,
+    print(json.dumps(dict(kernel=f"Wilson stencil gamma5 M, {args.storage} spinors", dims=list(dims), nrhs=12,
+                          reps=args.reps,
                           avg_us=round(ms * 1e3, 2), algorithmic_bytes=by, copy_bytes=1 << 30,
                           source_hash=wilson_source_hash())))
     op.close()
@@ -219,8 +294,10 @@ def main():
     ap.add_argument("--train-lr", type=float, default=3e-3)
     ap.add_argument("--net-seed", type=int, default=7)
     ap.add_argument("--ablation-steps", type=int, default=1)
-    ap.add_argument("--storage", choices=("fp32", "bf16"), default="fp32",
+    ap.add_argument("--storage", choices=("fp32", "bf16"), default="bf16",
                     help="Krylov-vector storage of the timed fast path")
+    ap.add_argument("--multi", action="store_true", help="the uneven multi-lattice batch instead (own JSON line)")
+    ap.add_argument("--multi-storage", choices=("fp32", "bf16"), default="fp32")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded across GPUs.",
@@ -229,6 +306,8 @@ def main():
 
     if args.kernel_only:
         return kernel_only(args)
+    if args.multi:
+        return multi_lattice(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -315,13 +394,15 @@ def main():
                               max_relres=float(max(st["relres"] for st in stm)))
         log(f"ablation {name}: {ablation[name]['value']:.2f} RHS/s, iters {ablation[name]['iters_per_rhs']:.1f}")
     achieved = by_w / (ms_w * 1e-3) / 1e9
+    sp_b = 96 if args.storage == "bf16" else 192
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(dims),
-                    kernel="k_wilson<float, gamma5 M> (FP32, batched over right-hand sides)", launches=n_w,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(dims, args.storage),
+                    kernel=(f"Wilson stencil, gamma5 M, {args.storage.upper()} spinors, FP32 links and arithmetic, "
+                            "batched over right-hand sides (tuned launch shape)"), launches=n_w,
                     avg_us=round(ms_w / max(n_w, 1) * 1e3, 2), bytes_per_launch=round(by_w / max(n_w, 1)),
-                    note=("algorithmic bytes per launch: links once (288 B/site FP32) + input and output "
-                          "spinor per active rhs (192 B/site); the 16^3x32 working set fits the 256 MB "
-                          "Infinity Cache, see dslash_sweep for HBM-resident sizes"))
+                    note=(f"algorithmic bytes per launch: links once (288 B/site FP32) + input and output "
+                          f"spinor per active rhs ({sp_b} B/site); the 16^3x32 working set is about the size of "
+                          "the 256 MB Infinity Cache, see dslash_sweep for HBM-resident sizes"))
     # plain FP64 D-MinRes, one rhs after another: the baseline the fast path is compared with
     log("plain FP64 baseline")
     X64, st64, _ = plain()

@@ -65,7 +65,7 @@ __device__ __forceinline__ double b_fin_sum(const double* part, int np, double* 
 }
 
 // ---- FP64 <-> FP32 and residual kernels (grid: (G, nrhs)) -----------------------
-// r = b - y (FP64), partial ||r||^2 column-major [rhs][G]
+// r = b - y (FP64; y == nullptr: r = b), partial ||r||^2 column-major [rhs][G]
 __global__ void __launch_bounds__(kBlock)
 k_b_resid(Seg g, const double2* b, const double2* y, double2* r, const int* __restrict__ active,
           double* __restrict__ part) {
@@ -74,7 +74,7 @@ k_b_resid(Seg g, const double2* b, const double2* y, double2* r, const int* __re
   if (!active || active[rhs]) {
     const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-      const double2 v = c_sub(b[off + i], y[off + i]);
+      const double2 v = y ? c_sub(b[off + i], y[off + i]) : b[off + i];
       r[off + i] = v;
       acc = fma(v.x, v.x, fma(v.y, v.y, acc));
     }
@@ -450,6 +450,10 @@ struct Batch {
     DL_HIP(hipMemcpyAsync(h_st.data(), st.get(), h_st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     DL_HIP(hipStreamSynchronize(s));
   }
+  void push_state() {
+    DL_HIP(hipMemcpyAsync(st.get(), h_st.data(), h_st.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    DL_HIP(hipStreamSynchronize(s));
+  }
   double get(int r, int f) const { return h_st[(size_t)r * NS + f]; }
   int n_active() const {
     int a = 0;
@@ -546,11 +550,13 @@ static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
                        bt.d_off.get(), 0, nullptr, bt.active.get(), nullptr);
 }
 
-// r64 = b - M x64 for active rhs; refreshes st[B_RR], st[B_NRM], st[B_INV].
-static void true_residual(Batch& bt, const double2* B, const double2* X, double2* R, double2* T) {
-  bwilson64(bt, 0, X, T);
-  hipLaunchKernelGGL(k_b_resid, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.seg, B, T, R, bt.active.get(),
-                     bt.part.get());
+// r64 = b - M x64 for active rhs (x_zero: x64 = 0, r64 = b without the stencil); refreshes
+// st[B_RR], st[B_NRM], st[B_INV].
+static void true_residual(Batch& bt, const double2* B, const double2* X, double2* R, double2* T,
+                          bool x_zero = false) {
+  if (!x_zero) bwilson64(bt, 0, X, T);
+  hipLaunchKernelGGL(k_b_resid, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.seg, B, x_zero ? nullptr : T, R,
+                     bt.active.get(), bt.part.get());
   hipLaunchKernelGGL(k_b_fin_store, dim3(bt.nr), dim3(kBlock), 0, bt.s, bt.part.get(), bt.G, bt.st.get(),
                      (int)B_RR);
   DL_HIP(hipGetLastError());
@@ -711,9 +717,10 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   // FP64 true residual, projection, FP64 true residual again (X in place, R: its residual)
   bool any_eig = false;
   for (const auto& it : items) any_eig |= it.eig && it.eig->k > 0;
-  auto start = [&](double2* Xs, double2* Rs) {
-    true_residual(bt, B, Xs, Rs, T64.get());
-    for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
+  auto start = [&](double2* Xs, double2* Rs, bool x_zero) {
+    true_residual(bt, B, Xs, Rs, T64.get(), x_zero);
+    if (!x_zero)
+      for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
     project_batch(bt, Rs, Xs, T64.get(), cbuf, S);
     if (any_eig) {
       for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r] * (mr ? 0 : 1);
@@ -730,24 +737,28 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
     dl_op* op = items[0].op;
     dl_net* net = o.net;
     if (net->ctx != op->ctx) fail(DL_E_INVALID, "network and operator belong to different contexts");
-    start(X, R64.get());
+    start(X, R64.get(), !o.x0_given);
     bt.pull_state();
     std::vector<double> rp(nr);
     for (int r = 0; r < nr; ++r) rp[r] = bt.get(r, B_NRM);
     DBuf<double2> XN((size_t)bt.total), RN((size_t)bt.total);
     net_apply(net, op, nr, B, XN.get());
-    start(XN.get(), RN.get());
+    start(XN.get(), RN.get(), false);
     bt.pull_state();
+    // keep the better start per rhs, with its residual and residual state
     for (int r = 0; r < nr; ++r) {
       if (!bt.h_active[r]) continue;
       if (bt.get(r, B_NRM) < rp[r]) {
         used_net[r] = 1;
         copy(s, bt.h_len[r], XN.get() + bt.h_off[r], X + bt.h_off[r]);
+        copy(s, bt.h_len[r], RN.get() + bt.h_off[r], R64.get() + bt.h_off[r]);
+      } else {
+        bt.h_st[(size_t)r * NS + B_NRM] = rp[r];
+        bt.h_st[(size_t)r * NS + B_RR] = rp[r] * rp[r];
+        bt.h_st[(size_t)r * NS + B_INV] = rp[r] > 0.0 ? 1.0 / rp[r] : 0.0;
       }
     }
-    // residual state of the chosen starts
-    true_residual(bt, B, X, R64.get(), T64.get());
-    for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
+    bt.push_state();
     started = true;
     if (verbose()) {
       int cnt = 0;
@@ -764,7 +775,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   const bool use_graph = o.graph != 0 && !bt.ctx->timers.enabled && s != nullptr;
   GraphCache graphs(s);
   for (int cycle = 0; cycle < 40 && bt.n_active() > 0; ++cycle) {
-    if (!(cycle == 0 && started)) start(X, R64.get());
+    if (!(cycle == 0 && started)) start(X, R64.get(), cycle == 0 && !o.x0_given);
     bt.pull_state();
     for (int r = 0; r < nr; ++r) {
       if (!bt.h_active[r]) continue;
