@@ -145,10 +145,10 @@ void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, d
 // occupancy hint) among {(256,2), (128,2), (512,1), (256,1)}; 4-6 = one thread per (x,y,z)
 // site marching through time chunks of 4, 8, 16 slices; 7-10 = the marching form with 64
 // sites per block, links staged in LDS and shared by (rhs per block, T) = (4, 8), (4, 16),
-// (8, 8), (2, 8); 11-13 = the marching form with each slice's spinors staged in LDS (11: with
-// the x, y links too, FP32 only; T = 8, 8, 16); order = block order (0: rhs fastest, XCD-contiguous; 1: sites
+// (8, 8), (2, 8); 11-14 = the marching form with each slice's spinors staged in LDS (11: with
+// the x, y links too, FP32 only; T = 8, 8, 16, 8; 14 loads the next slice ahead); order = block order (0: rhs fastest, XCD-contiguous; 1: sites
 // fastest, XCD-contiguous; 2: rhs fastest, hardware order).  Chosen by the autotuner.
-constexpr int kWilsonVariants = 14;
+constexpr int kWilsonVariants = 15;
 constexpr int kWilsonOrders = 3;
 struct WilsonCfg {
   int variant = 0;

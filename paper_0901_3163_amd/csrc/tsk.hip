@@ -124,70 +124,93 @@ k_tsk_combine(long n, int nv, const double2* __restrict__ base, long ld, const i
 
 // ---- several right-hand sides at once: C = V^H W and X += V D ---------------------------
 // W and X hold nw fields at stride ldw (nw <= NW).  V streams once for all nw columns.
-constexpr int kMEPT = 2;     // rows per thread per pass of the multi-column dots
-constexpr int kMultiNV = 64; // basis vectors per multi-column dots launch
+constexpr int kMultiNV = 64; // basis vectors per multi-column dots call
 constexpr int kMultiBlocks = 2048;
 
-// part is column-major [2*nw*nv][gridDim.x]: column (r*nv + j)*2 (+1) holds Re (Im) of this
-// block's share of <V_j, W_r>, so the summed result is c[r*nv + j] (rhs-major).  A block walks
-// its rows kMEPT per thread at a time; each wave adds its wave sums to its own LDS row, and the
-// four rows are added at the end (fixed order).
-template <int NW>
+// C = V^H W as a tiled product: a block stages a 64-row tile of 32 basis vectors and of up
+// to 16 columns in LDS (coalesced 1 KiB runs), then each thread accumulates a 4 x 4 block of
+// (vector, column) products over 8 of the tile's rows; the 8 row groups are added in LDS at
+// the end (fixed order).  Vectors [j0, j0 + nj) of nv, columns r < nw.  part is column-major
+// [2*nw*nv][gridDim.x]: column (r*nv + j)*2 (+1) holds Re (Im) of the block's share of
+// <V_j, W_r>, so the summed result is c[r*nv + j] (rhs-major).
+constexpr int kTR = 64, kTJ = 32, kTW = 16;
 __global__ void __launch_bounds__(kBlock)
-k_tsk_dots_multi(long n, int nv, const double2* __restrict__ base, long ld, const double2* __restrict__ W, long ldw,
-                 int nw, const int* __restrict__ active, double* __restrict__ part) {
-  __shared__ double2 acc[kBlock / 64][NW][kMultiNV];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int t = lane; t < NW * kMultiNV; t += 64) acc[wid][t / kMultiNV][t % kMultiNV] = make_double2(0.0, 0.0);
-  __syncthreads();
-  const long step = (long)gridDim.x * kBlock * kMEPT;
-  for (long i0 = (long)blockIdx.x * kBlock * kMEPT + threadIdx.x; i0 - threadIdx.x < n; i0 += step) {
-    double2 wr[kMEPT][NW];
+k_tsk_dots_multi(long n, int nv, int j0, int nj, const double2* __restrict__ base, long ld,
+                 const double2* __restrict__ W, long ldw, int nw, const int* __restrict__ active,
+                 double* __restrict__ part) {
+  // one buffer: the V tile (kTJ rows of kTR + 1), the W tile after it, and later the reduction
+  __shared__ double2 sm[(kTJ + kTW) * (kTR + 1)];
+  double2 (*vt)[kTR + 1] = reinterpret_cast<double2 (*)[kTR + 1]>(sm);
+  double2 (*wt)[kTR + 1] = reinterpret_cast<double2 (*)[kTR + 1]>(sm + kTJ * (kTR + 1));
+  const int tid = threadIdx.x;
+  const int mt = tid & 31, rg = tid >> 5;   // micro tile (8 j-groups x 4 r-groups), row group 0..7
+  const int jq = (mt & 7) * 4, rq = (mt >> 3) * 4;
+  double2 acc[4][4];
 #pragma unroll
-    for (int e = 0; e < kMEPT; ++e)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int r = 0; r < NW; ++r) {
-        const long i = i0 + e * kBlock;
-        const bool on = r < nw && i < n && (!active || active[r]);
-        wr[e][r] = on ? W[(long)r * ldw + i] : make_double2(0.0, 0.0);
-      }
-    for (int j = 0; j < nv; ++j) {
-      const double2* v = base + (long)j * ld;
-      double re[NW], im[NW];
+    for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+  const long ntiles = (n + kTR - 1) / kTR;
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long r0 = tile * kTR;
+    __syncthreads();
+    for (int e = tid; e < kTJ * kTR; e += kBlock) {
+      const int j = e / kTR, row = e % kTR;
+      const long i = r0 + row;
+      vt[j][row] = (j < nj && i < n) ? base[(long)(j0 + j) * ld + i] : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < kTW * kTR; e += kBlock) {
+      const int r = e / kTR, row = e % kTR;
+      const long i = r0 + row;
+      const bool on = r < nw && i < n && (!active || active[r]);
+      wt[r][row] = on ? W[(long)r * ldw + i] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int row = rg; row < kTR; row += 8) {
+      double2 v[4], w[4];
 #pragma unroll
-      for (int r = 0; r < NW; ++r) re[r] = im[r] = 0.0;
+      for (int a = 0; a < 4; ++a) v[a] = vt[jq + a][row];
 #pragma unroll
-      for (int e = 0; e < kMEPT; ++e) {
-        const long i = i0 + e * kBlock;
-        const double2 x = i < n ? v[i] : make_double2(0.0, 0.0);
+      for (int b = 0; b < 4; ++b) w[b] = wt[rq + b][row];
 #pragma unroll
-        for (int r = 0; r < NW; ++r) {
-          re[r] = fma(x.x, wr[e][r].x, re[r]);
-          re[r] = fma(x.y, wr[e][r].y, re[r]);
-          im[r] = fma(x.x, wr[e][r].y, im[r]);
-          im[r] = fma(-x.y, wr[e][r].x, im[r]);
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          // conj(v) * w
+          acc[a][b].x = fma(v[a].x, w[b].x, acc[a][b].x);
+          acc[a][b].x = fma(v[a].y, w[b].y, acc[a][b].x);
+          acc[a][b].y = fma(v[a].x, w[b].y, acc[a][b].y);
+          acc[a][b].y = fma(-v[a].y, w[b].x, acc[a][b].y);
         }
-      }
-#pragma unroll
-      for (int r = 0; r < NW; ++r) {
-        if (r < nw) {
-          const double a = wave_sum(re[r]), b = wave_sum(im[r]);
-          if (lane == 0) acc[wid][r][j] = make_double2(acc[wid][r][j].x + a, acc[wid][r][j].y + b);
-        }
-      }
     }
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nw * nv; t += kBlock) {
-    const int r = t / nv, j = t % nv;
-    double a = 0.0, b = 0.0;
+  // add the 8 row groups in two halves of 16 vectors: each row group writes its sums for the
+  // half to red[g][256], then 256 threads add the 8 groups (fixed order)
+  double2* red = sm;
+  static_assert((kTJ + kTW) * (kTR + 1) >= 8 * 256, "reduction buffer");
+  for (int half = 0; half < 2; ++half) {
+    __syncthreads();
+    if ((jq >> 4) == half) {
 #pragma unroll
-    for (int q = 0; q < kBlock / 64; ++q) {
-      a += acc[q][r][j].x;
-      b += acc[q][r][j].y;
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) red[rg * 256 + (jq - 16 * half + a) * 16 + rq + b] = acc[a][b];
     }
-    part[(long)(2 * (r * nv + j)) * gridDim.x + blockIdx.x] = a;
-    part[(long)(2 * (r * nv + j) + 1) * gridDim.x + blockIdx.x] = b;
+    __syncthreads();
+    const int t = tid;  // 256 (j, r) sums of this half
+    const int j = 16 * half + t / 16, r = t % 16;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      re += red[g * 256 + t].x;
+      im += red[g * 256 + t].y;
+    }
+    if (j < nj && r < nw) {
+      const long col = 2L * (r * nv + j0 + j);
+      part[col * gridDim.x + blockIdx.x] = re;
+      part[(col + 1) * gridDim.x + blockIdx.x] = im;
+    }
   }
 }
 
@@ -256,7 +279,7 @@ void tsk_combine(hipStream_t s, long n, int nv, const double2* base, long ld, co
 }
 
 int tsk_multi_nblocks(long n) {
-  long nb = (n + (long)kBlock * kMEPT - 1) / ((long)kBlock * kMEPT);
+  long nb = (n + kTR - 1) / kTR;
   if (nb < 1) nb = 1;
   if (nb > kMultiBlocks) nb = kMultiBlocks;
   return (int)nb;
@@ -265,16 +288,12 @@ int tsk_multi_nblocks(long n) {
 int tsk_dots_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* W, long ldw, int nw,
                    const int* active, double* part) {
   if (nv > kMultiNV) fail(DL_E_INVALID, "too many basis vectors for one multi-column contraction (max 64)");
-  if (nw < 1 || nw > 16) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
+  if (nw < 1 || nw > kTW) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
   const int nb = tsk_multi_nblocks(n);
-  if (nv > 0) {
-    if (nw <= 4)
-      hipLaunchKernelGGL((k_tsk_dots_multi<4>), dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, W, ldw, nw, active, part);
-    else if (nw <= 8)
-      hipLaunchKernelGGL((k_tsk_dots_multi<8>), dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, W, ldw, nw, active, part);
-    else
-      hipLaunchKernelGGL((k_tsk_dots_multi<16>), dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, W, ldw, nw, active,
-                         part);
+  for (int j0 = 0; j0 < nv; j0 += kTJ) {
+    const int nj = nv - j0 < kTJ ? nv - j0 : kTJ;
+    hipLaunchKernelGGL(k_tsk_dots_multi, dim3(nb), dim3(kBlock), 0, s, n, nv, j0, nj, base, ld, W, ldw, nw, active,
+                       part);
     DL_HIP(hipGetLastError());
   }
   return nb;

@@ -411,7 +411,7 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
 // 16 x 16 plane per block that is all of them), the z neighbours and the z, t links come
 // from memory, and the t hops are carried along t as in k_wilson_tm.  Same arithmetic and
 // order as k_wilson.
-template <class R, class SV, int WHICH, int RED, int NT, bool LK>
+template <class R, class SV, int WHICH, int RED, int NT, bool LK, bool PF>
 __global__ void __launch_bounds__(NT)
 k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
              SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
@@ -492,6 +492,14 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
       C acc[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = CT<R>::make(0, 0);
+      // PF: the next slice's spinor is loaded before the spatial hops, so its latency overlaps them
+      const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
+      C nx[12];
+      if (PF) {
+        const SV* pn = in + sp_base(snext);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) nx[c] = sld(pn + c * kTile);
+      }
 #pragma unroll 1
       for (int hop2 = 0; hop2 < 6; ++hop2) {
         const int mu = hop2 >> 1;
@@ -530,12 +538,13 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
           reconstruct_mu<-SF>(mu, acc, g);
         }
       }
-      const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
-      C nx[12], u[9];
+      C u[9];
       {
-        const SV* pp = in + sp_base(snext);
+        if (!PF) {
+          const SV* pp = in + sp_base(snext);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) nx[c] = sld(pp + c * kTile);
+          for (int c = 0; c < 12; ++c) nx[c] = sld(pp + c * kTile);
+        }
         const C* up = U + lk_base(site, 3);
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
@@ -712,9 +721,9 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
 // {(256,2), (128,2), (512,1), (256,1)}; 4-6: k_wilson_tm, 256 threads per block, time
 // chunks of T = 4, 8, 16 slices; 7-10: k_wilson_tml with 64 sites per block and
 // (rhs per block, T) = (4, 8), (4, 16), (8, 8), (2, 8).
-static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64, 256, 256, 256};
-static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8, 8, 8, 16};
-static constexpr int kVariantRB[kWilsonVariants] = {0, 0, 0, 0, 0, 0, 0, 4, 4, 8, 2, 0, 0, 0};
+static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64, 256, 256, 256, 256};
+static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8, 8, 8, 16, 8};
+static constexpr int kVariantRB[kWilsonVariants] = {0, 0, 0, 0, 0, 0, 0, 4, 4, 8, 2, 0, 0, 0, 0};
 
 static int tm_nb3(const Lattice& lat, int v) {
   return (lat.L[0] * lat.L[1] * lat.L[2] + kVariantNT[v] - 1) / kVariantNT[v];
@@ -740,12 +749,13 @@ static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, do
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, nbs, order, scale, active, part);
 }
 
-template <class R, class SV, int WHICH, int RED, int NT, bool LK>
+template <class R, class SV, int WHICH, int RED, int NT, bool LK, bool PF>
 static void launch_tmp(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const SV* in,
                        SV* out, long fstride, int nrhs, int order, const double* scale, const int* active,
                        double* part, int nbs, int v) {
   const int* L = lat.L;
-  hipLaunchKernelGGL((k_wilson_tmp<R, SV, WHICH, RED, NT, LK>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride,
+  hipLaunchKernelGGL((k_wilson_tmp<R, SV, WHICH, RED, NT, LK, PF>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out,
+                     fstride,
                      nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
                      order, scale, active, part);
 }
@@ -784,15 +794,19 @@ static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const
     case 11:
       // FP64 spinors and links of a slice together exceed the LDS budget: the FP64 form stages spinors only
       if constexpr (sizeof(R) == 4)
-        launch_tmp<R, SV, WHICH, RED, 256, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
-                                             nbs, variant);
+        launch_tmp<R, SV, WHICH, RED, 256, true, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale,
+                                                        active, part, nbs, variant);
       else
-        launch_tmp<R, SV, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part,
-                                              nbs, variant);
+        launch_tmp<R, SV, WHICH, RED, 256, false, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale,
+                                                         active, part, nbs, variant);
       break;
     case 12: case 13:
-      launch_tmp<R, SV, WHICH, RED, 256, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs,
-                                            variant);
+      launch_tmp<R, SV, WHICH, RED, 256, false, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active,
+                                                       part, nbs, variant);
+      break;
+    case 14:
+      launch_tmp<R, SV, WHICH, RED, 256, false, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active,
+                                                      part, nbs, variant);
       break;
     default: launch_one<R, SV, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
   }
