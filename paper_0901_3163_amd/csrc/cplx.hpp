@@ -68,6 +68,11 @@ __device__ __forceinline__ float2 sld(const bf2* p) {
   const bf2 b = *p;
   return make_float2(__uint_as_float((unsigned)b.x << 16), __uint_as_float((unsigned)b.y << 16));
 }
+__device__ __forceinline__ float2 sldv(float2 v) { return v; }
+__device__ __forceinline__ double2 sldv(double2 v) { return v; }
+__device__ __forceinline__ float2 sldv(bf2 b) {
+  return make_float2(__uint_as_float((unsigned)b.x << 16), __uint_as_float((unsigned)b.y << 16));
+}
 __device__ __forceinline__ unsigned short f2bf(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);

@@ -146,7 +146,7 @@ void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, d
 // site marching through time chunks of 4, 8, 16 slices; 7-10 = the marching form with 64
 // sites per block, links staged in LDS and shared by (rhs per block, T) = (4, 8), (4, 16),
 // (8, 8), (2, 8); 11-14 = the marching form with each slice's spinors staged in LDS (11: with
-// the x, y links too, FP32 only; T = 8, 8, 16, 8; 14 loads the next slice ahead); order = block order (0: rhs fastest, XCD-contiguous; 1: sites
+// the x, y links too, FP32 only; T = 8, 8, 16, 8; 14 issues each hop's loads one hop ahead); order = block order (0: rhs fastest, XCD-contiguous; 1: sites
 // fastest, XCD-contiguous; 2: rhs fastest, hardware order).  Chosen by the autotuner.
 constexpr int kWilsonVariants = 15;
 constexpr int kWilsonOrders = 3;

@@ -43,7 +43,7 @@ bool autotune_enabled() {
 }
 
 std::string arch_name(int device) {
-  static std::map<int, std::string> names;  // guarded by g_mu's callers or first use
+  static std::map<int, std::string> names;  // callers hold g_mu
   auto it = names.find(device);
   if (it != names.end()) return it->second;
   hipDeviceProp_t p;
@@ -169,11 +169,11 @@ WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs) {
   const int okey = prec * 100000 + nrhs;
   auto oc = op->wcfg.find(okey);
   if (oc != op->wcfg.end()) return oc->second;
-  const std::string key = make_key(arch_name(op->ctx->device), op->lat, prec, nrhs);
   WilsonCfg c;
   bool found = false;
   {
     std::lock_guard<std::mutex> g(g_mu);
+    const std::string key = make_key(arch_name(op->ctx->device), op->lat, prec, nrhs);
     load_cache();
     auto it = g_table.find(key);
     if (it != g_table.end()) {

@@ -404,6 +404,61 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
   }
 }
 
+// Helpers of the slice-staged form: where hop h's neighbour comes from, and the loads of its
+// spinor (raw storage values) and link, returned by value so they stay in registers.
+struct HopSrc {
+  bool near;    // the neighbour lies in the block's LDS slice
+  unsigned li;  // its LDS index
+  int d;        // site offset of the neighbour
+};
+template <class SV>
+struct SpRaw {
+  SV e[12];
+};
+template <class C>
+struct Lk {
+  C e[9];
+};
+template <int NT>
+__device__ __forceinline__ HopSrc hop_src(int hh, int d, int s3, int base3, int V3) {
+  const int mu = hh >> 1;
+  const int nb3 = s3 + d;
+  HopSrc r;
+  r.d = d;
+  r.li = (unsigned)(nb3 - base3);
+  r.near = mu < 2 && r.li < (unsigned)NT && nb3 < V3;
+  return r;
+}
+template <class SV>
+__device__ __forceinline__ SpRaw<SV> fetch_sp(const SV* __restrict__ in, int site) {
+  SpRaw<SV> r;
+  const SV* pp = in + sp_base(site);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) r.e[c] = pp[c * kTile];
+  return r;
+}
+// link of hop hh: forward hops use U_mu(x), backward hops U_mu(x - mu); with LK the x and y
+// links of the block's sites come from LDS (pu: [2][9][NT])
+template <bool LK, int NT, class C>
+__device__ __forceinline__ Lk<C> fetch_link(const C* __restrict__ U, const C* pu, int hh, const HopSrc& src, int site,
+                                            int tid) {
+  const int mu = hh >> 1;
+  const bool fwd = (hh & 1) == 0;
+  Lk<C> r;
+  if (LK && fwd && mu < 2) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) r.e[e] = pu[(mu * 9 + e) * NT + tid];
+  } else if (LK && !fwd && src.near) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) r.e[e] = pu[(mu * 9 + e) * NT + src.li];
+  } else {
+    const C* up = U + lk_base(fwd ? site : site + src.d, mu);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) r.e[e] = up[e * kTile];
+  }
+  return r;
+}
+
 // Time-marching form with the slice staged in LDS: a block is NT consecutive (x, y, z)
 // sites of one time chunk of one rhs.  At each slice every thread writes its centre spinor
 // and its forward x and y links to LDS; the x and y neighbours (and the backward x, y links)
@@ -492,42 +547,53 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
       C acc[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = CT<R>::make(0, 0);
-      // PF: the next slice's spinor is loaded before the spatial hops, so its latency overlaps them
       const int snext = (t == Lt - 1 ? 0 : t + 1) * V3 + s3;
       C nx[12];
+      // Hop h (0..5: x+, x-, y+, y-, z+, z-) reads the neighbour's spinor from LDS (near) or
+      // memory, and its link.  PF: the memory loads of hop h + 1 are issued before hop h is
+      // computed, so two hops' loads are in flight at once.
+      auto hop_d = [=](int hh) {
+        return hh == 0 ? fx : hh == 1 ? bx : hh == 2 ? fy : hh == 3 ? by : hh == 4 ? fz : bz;
+      };
+      HopSrc nsrc{};
+      SpRaw<SV> nraw{};
+      Lk<C> nu{};
       if (PF) {
-        const SV* pn = in + sp_base(snext);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) nx[c] = sld(pn + c * kTile);
+        nsrc = hop_src<NT>(0, hop_d(0), s3, base3, V3);
+        if (!nsrc.near) nraw = fetch_sp(in, site + nsrc.d);
+        nu = fetch_link<LK, NT>(U, pu, 0, nsrc, site, tid);
       }
 #pragma unroll 1
       for (int hop2 = 0; hop2 < 6; ++hop2) {
         const int mu = hop2 >> 1;
         const bool fwd = (hop2 & 1) == 0;
-        const int d = mu == 0 ? (fwd ? fx : bx) : mu == 1 ? (fwd ? fy : by) : (fwd ? fz : bz);
-        const int nb3 = s3 + d;
-        const unsigned li = (unsigned)(nb3 - base3);
-        const bool near = mu < 2 && li < (unsigned)NT && nb3 < V3;
         C p[12], h[6], g[6], u[9];
-        if (near) {
-#pragma unroll
-          for (int c = 0; c < 12; ++c) p[c] = ps[c * NT + li];
+        HopSrc src;
+        SpRaw<SV> raw;
+        Lk<C> lk;
+        if (PF) {
+          src = nsrc;
+          raw = nraw;
+          lk = nu;
+          if (hop2 < 5) {
+            nsrc = hop_src<NT>(hop2 + 1, hop_d(hop2 + 1), s3, base3, V3);
+            if (!nsrc.near) nraw = fetch_sp(in, site + nsrc.d);
+            nu = fetch_link<LK, NT>(U, pu, hop2 + 1, nsrc, site, tid);
+          }
         } else {
-          const SV* pp = in + sp_base(site + d);
-#pragma unroll
-          for (int c = 0; c < 12; ++c) p[c] = sld(pp + c * kTile);
+          src = hop_src<NT>(hop2, hop_d(hop2), s3, base3, V3);
+          if (!src.near) raw = fetch_sp(in, site + src.d);
+          lk = fetch_link<LK, NT>(U, pu, hop2, src, site, tid);
         }
-        if (LK && fwd && mu < 2) {
+        if (src.near) {
 #pragma unroll
-          for (int e = 0; e < 9; ++e) u[e] = pu[(mu * 9 + e) * NT + tid];
-        } else if (LK && !fwd && near) {
-#pragma unroll
-          for (int e = 0; e < 9; ++e) u[e] = pu[(mu * 9 + e) * NT + li];
+          for (int c = 0; c < 12; ++c) p[c] = ps[c * NT + src.li];
         } else {
-          const C* up = U + lk_base(fwd ? site : site + d, mu);
 #pragma unroll
-          for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+          for (int c = 0; c < 12; ++c) p[c] = sldv(raw.e[c]);
         }
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lk.e[e];
         if (fwd) {
           project_mu<SF>(mu, p, h);
           mul_half<false>(u, h, g);
@@ -540,7 +606,7 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
       }
       C u[9];
       {
-        if (!PF) {
+        {
           const SV* pp = in + sp_base(snext);
 #pragma unroll
           for (int c = 0; c < 12; ++c) nx[c] = sld(pp + c * kTile);
