@@ -17,6 +17,8 @@ kappa     -- the kappa search that fixes the near-critical mass of the
              synthetic lattice workloads.
 ptc       -- the gauge-covariant parallel-transport convolution network used
              for the learned initial guess (forward and hand-written backward).
+lowp      -- binary32 and bfloat16 rounding, the contraction of rounded fields and
+             the Galerkin projection over a rounded eigenvector basis.
 
 All arithmetic is complex128/float64 with inner product <u, v> = sum conj(u) v.
 """
