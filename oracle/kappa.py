@@ -172,6 +172,8 @@ def main(argv=None):
         res["4x4x4x4"] = search_small((4, 4, 4, 4), 1e-3)
     if "large" in argv:
         res["16x16x16x32"] = search_large((16, 16, 16, 32), 1e-4, log=lambda m: print(m, flush=True))
+    if "precision" in argv:
+        res["24x24x24x48"] = search_large((24, 24, 24, 48), 1e-3, log=lambda m: print(m, flush=True))
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
     print(json.dumps(res, indent=1))

@@ -361,7 +361,8 @@ def test_landr_on_lattice_vs_dense(c1):
                                   residual=lambda x: np.linalg.norm(b - op.M(x)) / np.linalg.norm(b),
                                   apv=2, mvp0=1, max_mvp=20000)
     xd = np.linalg.solve(M, b)
-    assert info["relres"] <= 1e-11
+    # at that floor the last digit depends on the BLAS summation order (thread count)
+    assert info["relres"] <= 2e-11
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-8
     ev = np.linalg.eigvalsh(M.conj().T @ M)[:20]
     assert np.max(np.abs(np.sort(eig["vals"]) - ev) / ev) < 1e-8
