@@ -173,6 +173,125 @@ def train_guess(ctx, op, eig, deflan, dims, args):
     return net, info
 
 
+def projection_sweep(ctx, deflan, shapes, reps):
+    """The deflation contraction C = V^H W (k eigenvectors against 12 columns) on device fields:
+    FP64 (LDS tiles, vector FMAs) and FP32 / BF16 storage on the matrix cores.  Kernel time from
+    HIP events around the contraction launches only; algorithmic bytes = every basis vector and
+    every column read once; useful flops = 8 k * 12 * n (complex multiply-add)."""
+    import torch
+    out = {}
+    nw = 12
+    for dims, k in shapes:
+        n = 12 * int(np.prod(dims))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        V = torch.randn(k, n, dtype=torch.complex128, device="cuda", generator=g)
+        W = torch.randn(nw, n, dtype=torch.complex128, device="cuda", generator=g)
+        for name, prec, bpc in (("fp64", None, 16), ("fp32", deflan.DL_FP32, 8), ("bf16", deflan.DL_BF16, 4)):
+            def call():
+                if prec is None:
+                    return deflan.dl_tsk_project_multi(ctx, V, W)
+                return deflan.dl_tsk_project_lowp(ctx, prec, V, W)
+            call()
+            torch.cuda.synchronize()
+            ctx.timing(True)
+            for _ in range(reps):
+                call()
+            nl, ms, _ = ctx.kernel_time("tsk_dots")
+            ctx.timing(False)
+            t = ms / reps * 1e-3
+            by = (k + nw) * n * bpc
+            gbs = by / t / 1e9
+            key = f"{'x'.join(map(str, dims))}/k{k}/{name}"
+            out[key] = dict(k=k, nrhs=nw, launches_per_call=nl / reps, us_per_call=round(t * 1e6, 1),
+                            GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                            useful_TFLOPs=round(8.0 * k * nw * n / t / 1e12, 2),
+                            engine="matrix cores (MFMA)" if prec is not None else "vector FMA")
+            log(f"projection {key}: {t * 1e6:.1f} us, {gbs:.0f} GB/s")
+        del V, W
+        torch.cuda.empty_cache()
+    return out
+
+
+def precision_study(args):
+    """The precision ablation on the 24^3x48 near-critical lattice (min|lambda(gamma5 M)| ~ 1e-3):
+    FP64 Lan-DR(200,100) on M^dag M for a Gaussian first rhs (seed 299), the eigenvectors
+    lowered to FP32 and BF16, then D-CG for 12 Gaussian rhs (seeds 300-311) on the batched path
+    with FP32 or BF16 Krylov storage (FP32 arithmetic, reliable updates every 50 iterations,
+    FP64 restarts) and the projection over FP64 or FP32 eigenvectors.  Each
+    case: RHS/s, iterations, the library's FP64 true residual and the relative error against
+    the plain FP64 D-CG solutions of the same rhs on the GPU (the parity-checked FP64 path).
+    Prints one JSON line."""
+    import torch
+    from lattice_inputs import gaussian_spinor, su3_links
+    from paper_0901_3163_amd import deflan
+    os.environ.setdefault("DEFLAN_VERBOSE", "1")
+    try:
+        e = kappa_for("24x24x24x48")
+    except KeyError:
+        sys.exit("no kappa stored for 24x24x24x48: run `python -m oracle.kappa precision`")
+    dims, kappa, tol = tuple(e["dims"]), e["kappa"], args.tol
+    ctx = deflan.Context(0)
+    U = torch.from_numpy(su3_links(dims, e["seed"], e["eps"])).cuda()
+    op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_MDAGM)
+    del U
+    log(f"precision study 24^3x48 kappa {kappa:.7f}: Lan-DR({args.prec_m},{args.prec_k})")
+    t0 = time.time()
+    _, eig, st1 = op.solve_first(torch.from_numpy(gaussian_spinor(dims, 299)).cuda(), args.prec_m, args.prec_k, tol)
+    torch.cuda.synchronize()
+    t_first = time.time() - t0
+    log(f"first rhs: {st1['mvp']} MVPs, {t_first:.1f}s, relres {st1['relres']:.2e}")
+    t0 = time.time()
+    lower_mvp = eig.lower(deflan.DL_FP32)
+    torch.cuda.synchronize()
+    t_lower = time.time() - t0
+    B = torch.from_numpy(np.stack([gaussian_spinor(dims, 300 + i) for i in range(12)])).cuda()
+    nrhs = B.shape[0]
+    t0 = time.time()
+    X64, st64, _ = op.solve_next(B, eig, tol)
+    torch.cuda.synchronize()
+    t64 = time.time() - t0
+    log(f"plain FP64 D-CG: {nrhs / t64:.2f} RHS/s, iters {np.mean([s['iters'] for s in st64]):.0f}")
+    nx = torch.linalg.vector_norm(X64.reshape(nrhs, -1), dim=1)
+    cases = {}
+    for sname, scode in (("fp32", deflan.DL_FP32), ("bf16", deflan.DL_BF16)):
+        op.solve_next(B[:2], eig, tol, storage=scode, batched=1)  # launch-shape tuning for this storage
+        # (the BF16 contraction serves the gamma5 M form only: on M^dag M its error reaches the
+        # residual amplified by 1/sigma_min(M))
+        for ename, ecode in (("fp64", deflan.DL_FP64), ("fp32", deflan.DL_FP32)):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            X, sts, rc = op.solve_next(B, eig, tol, storage=scode, batched=1, reliable_every=50, eig_storage=ecode)
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+            err = torch.linalg.vector_norm((X - X64).reshape(nrhs, -1), dim=1) / nx
+            key = f"storage_{sname}/eig_{ename}"
+            cases[key] = dict(value=round(nrhs / dt, 3), unit="RHS/s", seconds=round(dt, 3),
+                              iters_per_rhs=float(np.mean([s["iters"] for s in sts])),
+                              max_relres=float(max(s["relres"] for s in sts)),
+                              all_rhs_converged=bool(rc == 0 and all(s["relres"] <= tol for s in sts)),
+                              max_rel_error_vs_fp64_path=float(err.max()))
+            log(f"{key}: {nrhs / dt:.2f} RHS/s, iters {cases[key]['iters_per_rhs']:.0f}, "
+                f"err {cases[key]['max_rel_error_vs_fp64_path']:.1e}")
+    n = 12 * int(np.prod(dims))
+    res = dict(workload=(f"24^3x48 Wilson near-critical (kappa {kappa:.6f}), Lan-DR({args.prec_m},{args.prec_k}) "
+                         f"on M^dag M, then D-CG on 12 Gaussian rhs, tol {tol:g}"),
+               first_rhs=dict(mvp=st1["mvp"], mvp_lin=st1["mvp_lin"], seconds=round(t_first, 2),
+                              relres=st1["relres"], stop_rule=st1["stop_rule"]),
+               lowering=dict(mvp=lower_mvp, seconds=round(t_lower, 2)),
+               eigenvector_bytes=dict(fp64=args.prec_k * n * 16, fp32=args.prec_k * n * 8),
+               plain_fp64=dict(value=round(nrhs / t64, 3), unit="RHS/s",
+                               iters_per_rhs=float(np.mean([s["iters"] for s in st64])),
+                               max_relres=float(max(s["relres"] for s in st64))),
+               cases=cases,
+               error_reference="plain FP64 D-CG on the GPU (one rhs at a time), the path the parity tests check "
+                               "against the oracle")
+    eig.close()
+    op.close()
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def multi_lattice(args):
     """Uneven lattices in one batched solve: 16 Gaussian rhs on each of 8^4, 12^4, 16^3x32 and
     20^3x40 (64 in all), D-CG on M^dag M with k = 40, 60, 80, 100 eigenvectors from Lan-DR(k + 40, k)
@@ -274,6 +393,37 @@ def kernel_only(args):
     ctx.close()
 
 
+def projection_only(args):
+    """The deflation contraction alone, for rocprofv3 counter runs: C = V^H W for k = 60
+    eigenvectors and 12 columns of the 16^3x32 field length, reps calls each in FP64, FP32 and
+    BF16 storage (the FP32 / BF16 calls round V and W on the device first)."""
+    import torch
+    from paper_0901_3163_amd import deflan
+    ctx = deflan.Context(0)
+    dims, k, nw = (16, 16, 16, 32), 60, 12
+    n = 12 * int(np.prod(dims))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    V = torch.randn(k, n, dtype=torch.complex128, device="cuda", generator=g)
+    W = torch.randn(nw, n, dtype=torch.complex128, device="cuda", generator=g)
+    res = {}
+    for name, prec, bpc in (("fp64", None, 16), ("fp32", deflan.DL_FP32, 8), ("bf16", deflan.DL_BF16, 4)):
+        ctx.timing(True)
+        for _ in range(args.reps):
+            if prec is None:
+                deflan.dl_tsk_project_multi(ctx, V, W)
+            else:
+                deflan.dl_tsk_project_lowp(ctx, prec, V, W)
+        nl, ms, _ = ctx.kernel_time("tsk_dots")
+        ctx.timing(False)
+        res[name] = dict(launches=nl, avg_us_per_call=round(ms / args.reps * 1e3, 1),
+                         algorithmic_bytes_per_call=(k + nw) * n * bpc)
+        log(f"projection {name}: {ms / args.reps * 1e3:.1f} us per call ({nl // args.reps} launches)")
+    print(json.dumps(dict(kernel="deflation contraction C = V^H W", dims=list(dims), k=k, nrhs=nw, reps=args.reps,
+                          **res)))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,8 +446,16 @@ def main():
     ap.add_argument("--ablation-steps", type=int, default=1)
     ap.add_argument("--storage", choices=("fp32", "bf16"), default="bf16",
                     help="Krylov-vector storage of the timed fast path")
+    ap.add_argument("--eig-storage", choices=("fp64", "fp32", "bf16"), default="bf16",
+                    help="eigenvectors the projection of the timed fast path reads")
     ap.add_argument("--multi", action="store_true", help="the uneven multi-lattice batch instead (own JSON line)")
     ap.add_argument("--multi-storage", choices=("fp32", "bf16"), default="fp32")
+    ap.add_argument("--precision", action="store_true",
+                    help="the 24^3x48 precision study instead (own JSON line)")
+    ap.add_argument("--prec-m", type=int, default=200)
+    ap.add_argument("--prec-k", type=int, default=100)
+    ap.add_argument("--no-proj-sweep", action="store_true", help="skip the deflation-contraction sweep")
+    ap.add_argument("--proj-only", action="store_true", help="run only the deflation contraction (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded across GPUs.",
@@ -308,6 +466,10 @@ def main():
         return kernel_only(args)
     if args.multi:
         return multi_lattice(args)
+    if args.precision:
+        return precision_study(args)
+    if args.proj_only:
+        return projection_only(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -345,10 +507,18 @@ def main():
         net, net_info = train_guess(ctx, op, eig, deflan, dims, args)
 
     storage = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.storage]
+    eig_storage = {"fp64": deflan.DL_FP64, "fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.eig_storage]
+    # lowered eigenvector copies (setup: k MVPs for the FP32 basis's Gram matrix); a BF16
+    # handle serves FP32 as well
+    t0 = time.time()
+    lower_mvp = eig.lower(deflan.DL_BF16)
+    torch.cuda.synchronize()
+    lowering = dict(mvp=lower_mvp, seconds=round(time.time() - t0, 2))
 
-    def fast(use_net=True, st=None):
+    def fast(use_net=True, st=None, eig_st=None):
         return op.solve_next(B, eig, args.tol, storage=storage if st is None else st, batched=1,
-                             net=net if use_net else None)
+                             net=net if use_net else None,
+                             eig_storage=eig_storage if eig_st is None else eig_st)
 
     def plain():
         return op.solve_next(B, eig, args.tol)
@@ -376,15 +546,20 @@ def main():
     ablation = {}
     if net is not None:
         net_info["guess_kept_per_rhs"] = float(np.mean(kept))
-    for name, st_, use_net in (("fp32", deflan.DL_FP32, False), ("bf16", deflan.DL_BF16, False),
-                               ("fp32+guess", deflan.DL_FP32, True), ("bf16+guess", deflan.DL_BF16, True)):
+    E64, E32, E16 = deflan.DL_FP64, deflan.DL_FP32, deflan.DL_BF16
+    for name, st_, use_net, est in (("fp32", deflan.DL_FP32, False, E64), ("bf16", deflan.DL_BF16, False, E64),
+                                    ("fp32+guess", deflan.DL_FP32, True, E64),
+                                    ("bf16+guess", deflan.DL_BF16, True, E64),
+                                    ("fp32+eig_fp32", deflan.DL_FP32, False, E32),
+                                    ("bf16+eig_bf16", deflan.DL_BF16, False, E16),
+                                    ("bf16+eig_bf16+guess", deflan.DL_BF16, True, E16)):
         if use_net and net is None:
             continue
-        fast(use_net, st_)
+        fast(use_net, st_, est)
         torch.cuda.synchronize()
         t0 = time.time()
         for s in range(args.ablation_steps):
-            Xm, stm, _ = fast(use_net, st_)
+            Xm, stm, _ = fast(use_net, st_, est)
         torch.cuda.synchronize()
         dtm = time.time() - t0
         ablation[name] = dict(value=round(nrhs * args.ablation_steps / dtm, 3), unit="RHS/s",
@@ -424,7 +599,11 @@ def main():
                                        f"{args.tol:g}", lattice=list(dims), kappa=kappa, nrhs=nrhs,
                               m=args.m, k=args.k,
                               path=(f"batched D-MinRes, {args.storage.upper()} Krylov vectors and Wilson apply "
-                                    "(FP32 arithmetic and links), FP64 residuals, projection and solution"
+                                    "(FP32 arithmetic and links), FP64 residuals and solution, projection over "
+                                    + {"fp64": "FP64 eigenvectors",
+                                       "fp32": "FP32 eigenvectors (matrix-core contraction)",
+                                       "bf16": "BF16-contracted, FP32-corrected eigenvectors (matrix cores)"}[
+                                           args.eig_storage]
                                     + (", learned initial guess (net(b) + projection, kept per rhs when its "
                                        "residual is smaller)" if net is not None else ""))),
                   all_rhs_converged=bool(all_ok), iters_per_rhs=float(np.mean(iters)),
@@ -434,12 +613,15 @@ def main():
                                   iters_per_rhs=float(np.mean([st["iters"] for st in st64])),
                                   path="D-MinRes FP64, one rhs after another"),
                   speedup_vs_plain_fp64=round(value / plain_value, 3),
+                  eigenvector_lowering=lowering,
                   first_rhs=dict(mvp=st1["mvp"], mvp_lin=st1["mvp_lin"], seconds=round(t_first, 2),
                                  relres=st1["relres"], stop_rule=st1["stop_rule"],
                                  mvp_overhead=round(st1["mvp"] / max(st1["mvp_lin"], 1), 3)),
                   roofline=roofline)
     if not args.no_sweep:
         result["dslash_sweep"] = dslash_sweep(ctx, deflan, [(24, 24, 24, 48), (32, 32, 32, 64)], reps=20)
+    if not args.no_proj_sweep:
+        result["projection_sweep"] = projection_sweep(ctx, deflan, [(dims, args.k), ((24, 24, 24, 48), 100)], reps=5)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(dims, kappa, result["plain_fp64"]["iters_per_rhs"], args.k)

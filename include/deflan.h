@@ -117,6 +117,17 @@ typedef struct {
   double inner_drop;        /* batched path: residual reduction that ends an inner cycle (then
                                FP64 residual, projection, restart); 0 = default: 1e-4 with DL_FP32
                                storage, 1e-2 with DL_BF16 (whose rounding limits one cycle) */
+  int    eig_storage;       /* batched path: eigenvectors the Galerkin projection reads.  DL_FP64
+                               (0, default): the handle's FP64 basis.  DL_FP32 / DL_BF16: the
+                               lowered copies made by dl_eig_lower (DL_E_INVALID if missing):
+                               c = Y^H r on the matrix cores against the FP32 / BF16 rounding of
+                               Y and r, then x += Y32 H32^-1 c in FP64 over the FP32 rounding Y32
+                               (H32 = Y32^H A Y32).  The BF16 contraction leaves about
+                               1.6e-3 ||r|| / sqrt(n) in each deflated mode (n complex elements per
+                               field), so it suits cycles whose inner_drop is well above
+                               1.6e-3 sqrt(k / n): BF16 storage, or FP32 storage on large lattices.
+                               DL_BF16 is for the gamma5 M form only (DL_E_INVALID with M^dag M,
+                               where the residual sees that error amplified by 1/sigma_min(M)). */
 } dl_next_opts;
 
 /* Per-solve statistics. */
@@ -247,6 +258,18 @@ int  dl_eig_create(dl_op* op, int k, const double* V, int mem, dl_eig** out);
 int  dl_eig_info(const dl_eig* eig, int* k, double* evals, double* resid);
 /* Copy the k eigenvectors out ([k][V][4][3] complex128). */
 int  dl_eig_vectors(const dl_eig* eig, double* V, int mem);
+/* Lowered copies of the eigenvectors for the batched projection (Section 2's Galerkin
+ * projection over a rounded basis; dl_next_opts.eig_storage selects them).  prec DL_FP32:
+ * Y32 = fp32(Y) and H32 = Y32^H A Y32 (k MVPs in FP64 on the widened Y32) -- Y32 is the
+ * projection basis.  DL_BF16: also Y16 = bf16(Y), read (with a BF16 rounding of the
+ * residual) by the contraction c = Y^H r, 4 bytes per complex instead of 8; the correction
+ * stays on Y32, since a basis rounded to BF16 no longer spans the near-null modes of a
+ * near-critical A to the accuracy deflation needs (eps_bf16^2 ||A|| exceeds the smallest
+ * eigenvalues).  A handle lowered to DL_BF16 serves eig_storage DL_FP32 as well; lowering it
+ * to DL_FP32 releases Y16.  DL_FP64 releases the copies.  The FP64 basis is kept (dl_eig_vectors and
+ * the FP64 paths still use it).  eig must belong to op (DL_E_MISMATCH).  *mvp (may be NULL)
+ * receives the MVPs used. */
+int  dl_eig_lower(dl_op* op, dl_eig* eig, int prec, long* mvp);
 void dl_eig_destroy(dl_eig* eig);
 
 /* ---- learned initial guess ---------------------------------------------------
@@ -294,6 +317,14 @@ int  dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w,
  * ([nw][n]) is not NULL, then X_r += sum_j C[r][j] V_j.  V streams once for all columns. */
 int  dl_tsk_project_multi(dl_ctx* ctx, long n, int nv, const double* V, int nw, const double* W,
                           double* C, double* X, int mem);
+/* The matrix-core contraction of dl_next_opts.eig_storage: C[r][j] = <q(V_j), q(W_r)> for
+ * nv <= 512 vectors V ([nv][n] complex128) and nw <= 16 columns W ([nw][n]), q = rounding to
+ * prec (DL_FP32 or DL_BF16, nearest even; BF16 via FP32) done on the device; FP32 matrix-core
+ * products and block sums, FP64 partial sums; C: [nw][nv] complex128.  If X ([nw][n]) is not
+ * NULL, X_r += sum_j C[r][j] fp32(V_j) in FP64 (the update basis of the lowered projection).
+ * All pointers DL_HOST or DL_DEVICE. */
+int  dl_tsk_project_lowp(dl_ctx* ctx, int prec, long n, int nv, const double* V, int nw,
+                         const double* W, double* C, double* X, int mem);
 /* Y = V G for V ([nv][n] complex) and real G ([nv][ny], row-major); Y: [ny][n]. */
 int  dl_tsk_combine(dl_ctx* ctx, long n, int nv, const double* V, const double* G,
                     int ny, double* Y, int mem);

@@ -399,6 +399,11 @@ struct Batch {
   // multi-lattice stencil work lists (FP32 and FP64 links)
   DBuf<WilsonItem> wl32, wl64;
   int ml_blocks = 0, ml_pstride = 0;
+  // projection over lowered eigenvectors (eig_prec DL_FP32 / DL_BF16): rA rounded for the
+  // matrix-core contraction
+  int eig_prec = DL_FP64;
+  DBuf<float2> ra32;
+  DBuf<bf2> ra16;
 
   explicit Batch(const std::vector<BItem>& its) : items(its), ctx(its[0].op->ctx), s(its[0].op->ctx->stream) {
     nr = 0;
@@ -562,6 +567,64 @@ static void true_residual(Batch& bt, const double2* B, const double2* X, double2
   DL_HIP(hipGetLastError());
 }
 
+// The projection over lowered eigenvectors: rA (FP64, in T) is rounded to the contraction's
+// storage, c = Yc^H rA on the matrix cores (Yc = Y16 for BF16, Y32 for FP32; FP32 accumulation,
+// FP64 partials), d = H32^-1 c in FP64, and x += Y32 d in FP64 arithmetic.  The Galerkin basis
+// is Y32 with its own Gram matrix, so the correction is the exact projection onto span(Y32);
+// the contraction's rounding only perturbs c, by about eps * ||rA|| / sqrt(n) per entry.
+static void project_batch_lowp(Batch& bt, double2* X, const double2* T, DBuf<double2>& cbuf, Scratch& S) {
+  constexpr int kCols = 16, kRows = 128;
+  const bool b16 = bt.eig_prec == DL_BF16;
+  if (b16) {
+    if (bt.ra16.n < (size_t)bt.total) bt.ra16.alloc(bt.total);
+    round_bf16(bt.s, bt.total, T, bt.ra16.get());
+  } else {
+    if (bt.ra32.n < (size_t)bt.total) bt.ra32.alloc(bt.total);
+    round_f32(bt.s, bt.total, T, bt.ra32.get());
+  }
+  S.ensure_part((size_t)2 * kRows * kCols * tsk_lowp_nblocks(bt.nmax, bt.eig_prec) + 64);
+  for (const auto& it : bt.items) {
+    if (!it.eig || it.eig->k == 0) continue;
+    const dl_eig* e = it.eig;
+    if (e->lo_prec == DL_FP64 || (b16 && e->lo_prec != DL_BF16))
+      fail(DL_E_INVALID, "eigenvector handle not lowered to the requested storage");
+    const int k = e->k;
+    const long n = it.op->lat.nc;
+    int nact = 0;
+    for (int r = it.r0; r < it.r0 + it.nr; ++r) nact += bt.h_active[r];
+    if (!nact) continue;
+    for (int c0 = 0; c0 < it.nr; c0 += kCols) {
+      const int nw = std::min(kCols, it.nr - c0);
+      const int* act = bt.active.get() + it.r0 + c0;
+      const long off = bt.h_off[it.r0 + c0];
+      for (int j0 = 0; j0 < k; j0 += kRows) {
+        const int nv = std::min(kRows, k - j0);
+        int np;
+        {
+          TimeScope ts(bt.ctx, T_TSK_DOTS);
+          np = b16 ? tsk_dots_lowp(bt.s, n, nv, e->Y16.get() + (long)j0 * n, n, bt.ra16.get() + off, n, nw, act,
+                                   S.part.get())
+                   : tsk_dots_lowp(bt.s, n, nv, e->Y32.get() + (long)j0 * n, n, bt.ra32.get() + off, n, nw, act,
+                                   S.part.get());
+        }
+        for (int r = 0; r < nw; ++r)
+          sum_partials(bt.s, S.part.get() + (size_t)2 * r * nv * np, np, 2 * nv,
+                       reinterpret_cast<double*>(cbuf.get() + (long)(c0 + r) * k + j0));
+      }
+    }
+    {
+      TimeScope ts(bt.ctx, T_SMALL);
+      proj_solve(bt.s, k, it.nr, e->Zr32.get(), e->lamr32.get(), cbuf.get(), cbuf.get() + (long)it.nr * k);
+    }
+    for (int c0 = 0; c0 < it.nr; c0 += kCols) {
+      const int nw = std::min(kCols, it.nr - c0);
+      TimeScope ts(bt.ctx, T_TSK_UPDATE);
+      tsk_update_multi32(bt.s, n, k, e->Y32.get(), n, cbuf.get() + (long)it.nr * k + (long)c0 * k, nw,
+                         bt.active.get() + it.r0 + c0, X + bt.h_off[it.r0 + c0], n);
+    }
+  }
+}
+
 // Galerkin projection over each item's eigenvectors for every active rhs: x += Y H^-1 Y^H rA,
 // rA = gamma5 r (G5M) or M^dag r (MDAGM).  T: scratch (a batch of fields).
 static void project_batch(Batch& bt, const double2* R, double2* X, double2* T, DBuf<double2>& cbuf, Scratch& S) {
@@ -575,6 +638,10 @@ static void project_batch(Batch& bt, const double2* R, double2* X, double2* T, D
   // c = Y^H rA and x += Y d for up to 16 rhs per launch, so the eigenvectors stream once per
   // 16 rhs instead of once per rhs (the rhs of one item are contiguous at stride n)
   constexpr int kCols = 16, kRows = 64;
+  if (bt.eig_prec != DL_FP64) {
+    project_batch_lowp(bt, X, T, cbuf, S);
+    return;
+  }
   S.ensure_part((size_t)2 * kRows * kCols * tsk_multi_nblocks(bt.nmax) + 64);
   for (const auto& it : bt.items) {
     if (!it.eig || it.eig->k == 0) continue;
@@ -660,6 +727,18 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   Batch bt(items);
   const int nr = bt.nr;
   hipStream_t s = bt.s;
+  bt.eig_prec = o.eig_storage;
+  // On M^dag M the coefficients are divided by lambda(M^dag M) = sigma^2 while the M-residual
+  // multiplies them back by sigma only, so the contraction's error reaches the residual
+  // amplified by 1/sigma_min(M); BF16 is too coarse for that near criticality.
+  if (bt.eig_prec == DL_BF16 && items[0].op->kind == DL_MDAGM)
+    fail(DL_E_INVALID, "the BF16 contraction serves the gamma5 M form; use DL_FP32 eigenvectors with M^dag M");
+  // a handle lowered to BF16 also holds the FP32 basis, so it serves both
+  if (bt.eig_prec != DL_FP64)
+    for (const auto& it : items)
+      if (it.eig && it.eig->k > 0 && it.eig->lo_prec != bt.eig_prec &&
+          !(bt.eig_prec == DL_FP32 && it.eig->lo_prec == DL_BF16))
+        fail(DL_E_INVALID, "eigenvector handle not lowered to the requested storage (dl_eig_lower)");
   // everything a captured block could allocate or tune is settled first: the FP32 links and
   // the stencil launch shapes (tuning launches kernels and allocates)
   for (const auto& it : items) (void)op_links32_public(it.op);

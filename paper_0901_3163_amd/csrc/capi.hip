@@ -122,6 +122,7 @@ dl_next_opts next_defaults(const dl_next_opts* o) {
     d.net = o->net;
     d.graph = o->graph;
     if (o->inner_drop != 0.0) d.inner_drop = o->inner_drop;
+    d.eig_storage = o->eig_storage;
   }
   // per-cycle residual drop of the batched inner solve: BF16 storage limits what one cycle
   // can reach, so its cycles end earlier
@@ -356,6 +357,9 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     need(!(o.batched && o.storage == DL_FP64), "the batched path stores Krylov vectors in DL_FP32 or DL_BF16");
     need(o.inner_drop > 0.0 && o.inner_drop < 1.0, "inner_drop must be in (0, 1)");
     need(!o.net || o.batched, "the learned initial guess runs on the batched path (batched = 1)");
+    need(o.eig_storage == DL_FP64 || o.eig_storage == DL_FP32 || o.eig_storage == DL_BF16,
+         "eig_storage must be DL_FP64, DL_FP32 or DL_BF16");
+    need(o.eig_storage == DL_FP64 || o.batched, "lowered eigenvectors are read by the batched path (batched = 1)");
     need(!(o.net && o.x0_given), "x0_given and a learned initial guess exclude each other");
     if (o.net) check_net_op(o.net, op);
     use_device(op->ctx);
@@ -429,6 +433,8 @@ int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int
          "the multi-lattice batch runs the batched path (DL_FP32 or DL_BF16, batched = 1)");
     need(o.inner_drop > 0.0 && o.inner_drop < 1.0, "inner_drop must be in (0, 1)");
     need(!o.net, "the learned initial guess takes one operator per batch (dl_solve_next)");
+    need(o.eig_storage == DL_FP64 || o.eig_storage == DL_FP32 || o.eig_storage == DL_BF16,
+         "eig_storage must be DL_FP64, DL_FP32 or DL_BF16");
     use_device(ctx);
     std::vector<MultiItem> mi;
     std::vector<int> src;  // item index of each batch entry
@@ -720,6 +726,19 @@ int dl_eig_vectors(const dl_eig* eig, double* V, int mem) {
 
 void dl_eig_destroy(dl_eig* eig) { delete eig; }
 
+int dl_eig_lower(dl_op* op, dl_eig* eig, int prec, long* mvp) {
+  return guard([&] {
+    need(op && eig, "NULL argument");
+    need(prec == DL_FP64 || prec == DL_FP32 || prec == DL_BF16, "prec must be DL_FP64, DL_FP32 or DL_BF16");
+    if (eig->fingerprint != op->fingerprint || eig->kind != op->kind)
+      fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
+    use_device(op->ctx);
+    const long used = eig_lower(op, eig, prec);
+    if (mvp) *mvp = used;
+    return DL_OK;
+  });
+}
+
 int dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w, double* c, int subtract, int mem) {
   return guard([&] {
     need(ctx && V && w && c, "NULL argument");
@@ -804,6 +823,78 @@ int dl_tsk_project_multi(dl_ctx* ctx, long n, int nv, const double* V, int nw, c
     if (X) {
       TimeScope ts(ctx, T_TSK_UPDATE);
       tsk_update_multi(s, n, nv, vp, n, cp, nw, nullptr, xp, n);
+    }
+    if (mem == DL_HOST) {
+      DL_HIP(hipMemcpyAsync(C, cp, (size_t)nw * nv * sizeof(double2), hipMemcpyDeviceToHost, s));
+      if (X) DL_HIP(hipMemcpyAsync(X, xp, (size_t)nw * n * sizeof(double2), hipMemcpyDeviceToHost, s));
+    }
+    DL_HIP(hipStreamSynchronize(s));
+    return DL_OK;
+  });
+}
+
+int dl_tsk_project_lowp(dl_ctx* ctx, int prec, long n, int nv, const double* V, int nw, const double* W, double* C,
+                        double* X, int mem) {
+  return guard([&] {
+    need(ctx && V && W && C, "NULL argument");
+    need(prec == DL_FP32 || prec == DL_BF16, "prec must be DL_FP32 or DL_BF16");
+    need(n > 0 && nv > 0 && nv <= 512, "need n > 0 and 0 < nv <= 512");
+    need(nw >= 1 && nw <= 16, "need 1 <= nw <= 16");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    use_device(ctx);
+    hipStream_t s = ctx->stream;
+    DBuf<double2> Vd, Wd, Xd, Cd;
+    const double2* vp = reinterpret_cast<const double2*>(V);
+    const double2* wp = reinterpret_cast<const double2*>(W);
+    double2* xp = reinterpret_cast<double2*>(X);
+    double2* cp = reinterpret_cast<double2*>(C);
+    if (mem == DL_HOST) {
+      Vd.alloc((size_t)nv * n);
+      Wd.alloc((size_t)nw * n);
+      Cd.alloc((size_t)nw * nv);
+      DL_HIP(hipMemcpyAsync(Vd.get(), V, (size_t)nv * n * sizeof(double2), hipMemcpyHostToDevice, s));
+      DL_HIP(hipMemcpyAsync(Wd.get(), W, (size_t)nw * n * sizeof(double2), hipMemcpyHostToDevice, s));
+      vp = Vd.get();
+      wp = Wd.get();
+      cp = Cd.get();
+      if (X) {
+        Xd.alloc((size_t)nw * n);
+        DL_HIP(hipMemcpyAsync(Xd.get(), X, (size_t)nw * n * sizeof(double2), hipMemcpyHostToDevice, s));
+        xp = Xd.get();
+      }
+    }
+    // rounded copies at a stride that keeps every field 16-byte aligned
+    const long ld = (n + 3) / 4 * 4;
+    DBuf<float2> v32((size_t)nv * ld), w32, x32;
+    DBuf<bf2> v16, w16;
+    for (int j = 0; j < nv; ++j) round_f32(s, n, vp + (long)j * n, v32.get() + (long)j * ld);
+    if (prec == DL_BF16) {
+      v16.alloc((size_t)nv * ld);
+      w16.alloc((size_t)nw * ld);
+      for (int j = 0; j < nv; ++j) round_bf16(s, n, vp + (long)j * n, v16.get() + (long)j * ld);
+      for (int r = 0; r < nw; ++r) round_bf16(s, n, wp + (long)r * n, w16.get() + (long)r * ld);
+    } else {
+      w32.alloc((size_t)nw * ld);
+      for (int r = 0; r < nw; ++r) round_f32(s, n, wp + (long)r * n, w32.get() + (long)r * ld);
+    }
+    constexpr int kRows = 128;
+    DBuf<double> part((size_t)2 * kRows * nw * tsk_lowp_nblocks(n, prec));
+    for (int j0 = 0; j0 < nv; j0 += kRows) {
+      const int m = std::min(kRows, nv - j0);
+      int np;
+      {
+        TimeScope ts(ctx, T_TSK_DOTS);
+        np = prec == DL_BF16
+                 ? tsk_dots_lowp(s, n, m, v16.get() + (long)j0 * ld, ld, w16.get(), ld, nw, nullptr, part.get())
+                 : tsk_dots_lowp(s, n, m, v32.get() + (long)j0 * ld, ld, w32.get(), ld, nw, nullptr, part.get());
+      }
+      for (int r = 0; r < nw; ++r)
+        sum_partials(s, part.get() + (size_t)2 * r * m * np, np, 2 * m,
+                     reinterpret_cast<double*>(cp + (long)r * nv + j0));
+    }
+    if (X) {
+      TimeScope ts(ctx, T_TSK_UPDATE);
+      tsk_update_multi32(s, n, nv, v32.get(), ld, cp, nw, nullptr, xp, n);
     }
     if (mem == DL_HOST) {
       DL_HIP(hipMemcpyAsync(C, cp, (size_t)nw * nv * sizeof(double2), hipMemcpyDeviceToHost, s));

@@ -27,6 +27,13 @@ struct dl_eig {
   dl::DBuf<double> Zr, lamr;    // eigendecomposition of the real embedding of H = Y^H A Y
   std::vector<double> evals;    // Rayleigh quotients y_i^H A y_i
   std::vector<double> resid;    // ||A y_i - lambda_i y_i||
+  // Lowered copies for the batched projection (lo_prec = DL_FP32 or DL_BF16 once built): the
+  // FP32 rounding Y32 is the Galerkin basis (x += Y32 H32^-1 c, with H32 = Y32^H A Y32 built in
+  // FP64); c = Y^H r is contracted against Y32 (DL_FP32) or against the BF16 rounding Y16.
+  int lo_prec = DL_FP64;
+  dl::DBuf<float2> Y32;
+  dl::DBuf<dl::bf2> Y16;
+  dl::DBuf<double> Zr32, lamr32;
 };
 
 namespace dl {
@@ -71,6 +78,9 @@ struct MultiItem {
 int solve_next_multi(const std::vector<MultiItem>& items, const double2* B, double2* X, const dl_next_opts& o,
                      dl_stats* st);
 dl_eig* eig_build(dl_op* op, int k, DBuf<double2>&& Y, long* mvp);
+// Build the lowered copies of eig for prec (DL_FP32 or DL_BF16); k MVPs for H32 (once: a second
+// call with the same prec does nothing, DL_FP64 drops the copies).  Returns MVPs used.
+long eig_lower(dl_op* op, dl_eig* eig, int prec);
 const float2* op_links32_public(dl_op* op);  // FP32 links of the operator (made on first use)
 
 }  // namespace dl

@@ -599,6 +599,45 @@ dl_eig* eig_build(dl_op* op, int k, DBuf<double2>&& Y, long* mvp) {
   return e;
 }
 
+long eig_lower(dl_op* op, dl_eig* e, int prec) {
+  if (prec == DL_FP64) {
+    e->Y32 = DBuf<float2>();
+    e->Y16 = DBuf<bf2>();
+    e->Zr32 = DBuf<double>();
+    e->lamr32 = DBuf<double>();
+    e->lo_prec = DL_FP64;
+    return 0;
+  }
+  if (prec != DL_FP32 && prec != DL_BF16) fail(DL_E_INVALID, "eigenvector storage must be DL_FP64, DL_FP32 or DL_BF16");
+  if (e->lo_prec == prec || e->k == 0) {
+    e->lo_prec = prec;
+    return 0;
+  }
+  hipStream_t s = op->ctx->stream;
+  const long tot = (long)e->k * e->nc;
+  long mvp = 0;
+  if (e->lo_prec == DL_FP64) {
+    // the Galerkin basis is the FP32 rounding for both storages: its Gram matrix in FP64
+    e->Y32.alloc((size_t)tot);
+    round_f32(s, tot, e->Y.get(), e->Y32.get());
+    DBuf<double2> W((size_t)tot);
+    widen_f64(s, tot, e->Y32.get(), W.get());
+    dl_eig* g = eig_build(op, e->k, std::move(W), &mvp);
+    e->Zr32 = std::move(g->Zr);
+    e->lamr32 = std::move(g->lamr);
+    delete g;
+  }
+  if (prec == DL_BF16) {
+    e->Y16.alloc((size_t)tot);
+    round_bf16(s, tot, e->Y.get(), e->Y16.get());
+  } else {
+    e->Y16 = DBuf<bf2>();
+  }
+  DL_HIP(hipStreamSynchronize(s));
+  e->lo_prec = prec;
+  return mvp;
+}
+
 // ---- first right-hand side: Lan-DR / MinRes-DR --------------------------------------
 int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double tol, const dl_first_opts& o,
                 dl_eig** eig_out, dl_stats* st) {

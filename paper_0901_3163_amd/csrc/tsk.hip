@@ -125,6 +125,7 @@ k_tsk_combine(long n, int nv, const double2* __restrict__ base, long ld, const i
 // ---- several right-hand sides at once: C = V^H W and X += V D ---------------------------
 // W and X hold nw fields at stride ldw (nw <= NW).  V streams once for all nw columns.
 constexpr int kMultiNV = 64; // basis vectors per multi-column dots call
+constexpr int kLpMaxNV = 128; // basis vectors per low-precision dots call
 constexpr int kMultiBlocks = 2048;
 
 // C = V^H W as a tiled product: a block stages a 64-row tile of 32 basis vectors and of up
@@ -214,10 +215,14 @@ k_tsk_dots_multi(long n, int nv, int j0, int nj, const double2* __restrict__ bas
   }
 }
 
-// X_r += sum_j D[r*ldd + j] V_j for active r < nw (D complex, rhs-major, device memory).
-template <int NW>
+__device__ __forceinline__ double2 widen2(double2 a) { return a; }
+__device__ __forceinline__ double2 widen2(float2 a) { return make_double2(a.x, a.y); }
+
+// X_r += sum_j D[r*ldd + j] V_j for active r < nw (D complex, rhs-major, device memory).  The
+// basis is FP64 or FP32 (VB); the products and sums are FP64 either way.
+template <int NW, class VB>
 __global__ void __launch_bounds__(kBlock)
-k_tsk_update_multi(long n, int nv, const double2* __restrict__ base, long ld, const double2* __restrict__ D, int ldd,
+k_tsk_update_multi(long n, int nv, const VB* __restrict__ base, long ld, const double2* __restrict__ D, int ldd,
                    int nw, const int* __restrict__ active, double2* __restrict__ X, long ldx) {
   __shared__ double2 ds[kMaxNV / 4][NW];  // nv <= 128
   for (int t = threadIdx.x; t < nv * NW; t += kBlock) {
@@ -231,7 +236,7 @@ k_tsk_update_multi(long n, int nv, const double2* __restrict__ base, long ld, co
 #pragma unroll
     for (int r = 0; r < NW; ++r) acc[r] = make_double2(0.0, 0.0);
     for (int j = 0; j < nv; ++j) {
-      const double2 x = base[(long)j * ld + i];
+      const double2 x = widen2(base[(long)j * ld + i]);
 #pragma unroll
       for (int r = 0; r < NW; ++r) acc[r] = c_fma(ds[j][r], x, acc[r]);
     }
@@ -299,26 +304,219 @@ int tsk_dots_multi(hipStream_t s, long n, int nv, const double2* base, long ld, 
   return nb;
 }
 
-void tsk_update_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* D, int nw,
-                      const int* active, double2* X, long ldx) {
+template <class VB>
+static void update_multi(hipStream_t s, long n, int nv, const VB* base, long ld, const double2* D, int nw,
+                         const int* active, double2* X, long ldx) {
   if (nw < 1 || nw > 16) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
   const int nb = stream_blocks(n);
   constexpr int kChunk = kMaxNV / 4;  // basis vectors per launch (LDS holds kChunk x NW coefficients)
   for (int j0 = 0; j0 < nv; j0 += kChunk) {
     const int nc = nv - j0 < kChunk ? nv - j0 : kChunk;
-    const double2* b = base + (long)j0 * ld;
+    const VB* b = base + (long)j0 * ld;
     const double2* d = D + j0;
     if (nw <= 4)
-      hipLaunchKernelGGL((k_tsk_update_multi<4>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active, X,
-                         ldx);
+      hipLaunchKernelGGL((k_tsk_update_multi<4, VB>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active,
+                         X, ldx);
     else if (nw <= 8)
-      hipLaunchKernelGGL((k_tsk_update_multi<8>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active, X,
-                         ldx);
+      hipLaunchKernelGGL((k_tsk_update_multi<8, VB>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active,
+                         X, ldx);
     else
-      hipLaunchKernelGGL((k_tsk_update_multi<16>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active, X,
-                         ldx);
+      hipLaunchKernelGGL((k_tsk_update_multi<16, VB>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active,
+                         X, ldx);
     DL_HIP(hipGetLastError());
   }
+}
+
+void tsk_update_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* D, int nw,
+                      const int* active, double2* X, long ldx) {
+  update_multi(s, n, nv, base, ld, D, nw, active, X, ldx);
+}
+
+void tsk_update_multi32(hipStream_t s, long n, int nv, const float2* base, long ld, const double2* D, int nw,
+                        const int* active, double2* X, long ldx) {
+  update_multi(s, n, nv, base, ld, D, nw, active, X, ldx);
+}
+
+// ---- matrix-core contraction C = V^H W over FP32- or BF16-stored fields -----------------
+//
+// Each complex field of n elements is read as a real vector of 2n entries (re, im
+// interleaved).  Then Re C[j][r] = sum_p V_j[p] W_r[p] and Im C[j][r] = sum_p V_j[p] W'_r[p]
+// with W' the interleaved form of -i W (each pair (a, b) becomes (b, -a)), so one real
+// contraction against the 2*16 columns [W | W'] gives both parts.  Per wave, a step takes
+// one 16-byte load per lane from each of 16 basis vectors (lane % 16 picks the vector,
+// lane / 16 the 16-byte piece) and from 16 columns (lane % 16 picks the column), and feeds
+//   BF16: v_mfma_f32_16x16x32_bf16 (8 bf16 = 4 complex per lane, K = 32 per instruction),
+//   FP32: v_mfma_f32_16x16x4_f32 four times (4 floats = 2 complex per lane, K = 4 each).
+// The K ordering is the same for the A and B operands, so the sum is over the same real
+// positions whatever order the matrix core visits them in.  A wave walks pairs of steps
+// (128 contiguous bytes of each vector) strided over the grid; FP32 accumulation inside a
+// block, FP64 partials across blocks (summed in a fixed order by sum_partials).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kLpRows = 64;    // basis vectors per launch: four 16-row tiles
+constexpr int kLpBlocks = 512; // upper bound of partials per column
+
+template <class SV>
+struct LpTraits;
+template <>
+struct LpTraits<bf2> {
+  static constexpr int kCpl = 4;  // complex elements per 16-byte lane load
+};
+template <>
+struct LpTraits<float2> {
+  static constexpr int kCpl = 2;
+};
+
+// 16 bytes of a field starting at complex element e (zero past n; n need not be a multiple
+// of the load width, but the field base must be 16-byte aligned).
+template <class SV>
+__device__ __forceinline__ u32x4_t lp_load(const SV* __restrict__ f, long e, long n) {
+  constexpr int C = LpTraits<SV>::kCpl;
+  if (e + C <= n) return *reinterpret_cast<const u32x4_t*>(f + e);
+  u32x4_t v = {0u, 0u, 0u, 0u};
+  const unsigned int* w = reinterpret_cast<const unsigned int*>(f + e);
+  constexpr int kWords = sizeof(SV) / 4;  // 32-bit words per complex element
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    if (e + c < n) {
+#pragma unroll
+      for (int q = 0; q < kWords; ++q) v[c * kWords + q] = w[c * kWords + q];
+    }
+  return v;
+}
+
+// -i * w on 16 bytes of interleaved complex numbers
+__device__ __forceinline__ u32x4_t lp_rot(u32x4_t w, bf2*) {
+  u32x4_t o;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = ((w[q] >> 16) | (w[q] << 16)) ^ 0x80000000u;  // (a, b) -> (b, -a)
+  return o;
+}
+__device__ __forceinline__ u32x4_t lp_rot(u32x4_t w, float2*) {
+  u32x4_t o;
+  o[0] = w[1];
+  o[1] = w[0] ^ 0x80000000u;
+  o[2] = w[3];
+  o[3] = w[2] ^ 0x80000000u;
+  return o;
+}
+
+__device__ __forceinline__ void lp_mfma(f32x4_t& acc, u32x4_t a, u32x4_t b, bf2*) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                acc, 0, 0, 0);
+}
+__device__ __forceinline__ void lp_mfma(f32x4_t& acc, u32x4_t a, u32x4_t b, float2*) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[q]), __uint_as_float(b[q]), acc, 0, 0, 0);
+}
+
+// part[(2*(r*nv + j0 + j) + reim) * gridDim.x + blockIdx.x] for j < nj (<= 64), r < nw (<= 16).
+template <class SV>
+__global__ void __launch_bounds__(kBlock)
+k_tsk_dots_mfma(long n, int nv, int j0, int nj, const SV* __restrict__ base, long ld, const SV* __restrict__ W,
+                long ldw, int nw, const int* __restrict__ active, double* __restrict__ part) {
+  constexpr int C = LpTraits<SV>::kCpl;
+  constexpr int kStep = 4 * C;  // complex elements of each vector per step (4 lane groups)
+  constexpr int kNT = kLpRows / 16;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int li = lane & 15, grp = lane >> 4;
+  const bool col_on = li < nw && (!active || active[li]);
+  const SV* wcol = W + (long)li * ldw;
+  const SV* vrow[kNT];
+  bool row_on[kNT];
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) {
+    const int j = 16 * t + li;
+    row_on[t] = j < nj;
+    vrow[t] = base + (long)(j0 + (row_on[t] ? j : 0)) * ld;
+  }
+  f32x4_t acc[kNT][2];
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) acc[t][0] = acc[t][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const long nsteps = (n + kStep - 1) / kStep;
+  const long npairs = (nsteps + 1) / 2;
+  const long nwaves = (long)gridDim.x * (kBlock / 64);
+  const u32x4_t zero = {0u, 0u, 0u, 0u};
+  for (long pr = (long)blockIdx.x * (kBlock / 64) + wid; pr < npairs; pr += nwaves) {
+    u32x4_t a[2][kNT], b[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const long e = (2 * pr + u) * kStep + grp * C;
+      const bool in = e < n;
+      b[u] = (in && col_on) ? lp_load(wcol, e, n) : zero;
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) a[u][t] = (in && row_on[t]) ? lp_load(vrow[t], e, n) : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const u32x4_t bi = lp_rot(b[u], (SV*)nullptr);
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) {
+        lp_mfma(acc[t][0], a[u][t], b[u], (SV*)nullptr);
+        lp_mfma(acc[t][1], a[u][t], bi, (SV*)nullptr);
+      }
+    }
+  }
+  // add the four waves' tiles in a fixed order; acc[t][c][q] of lane l is row 16t + 4*(l/16) + q,
+  // column l % 16 of the real (c = 0) or imaginary (c = 1) part
+  __shared__ float red[kBlock / 64][kNT * 2 * 4][64];
+#pragma unroll
+  for (int t = 0; t < kNT; ++t)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[wid][(t * 2 + c) * 4 + q][lane] = acc[t][c][q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNT * 2 * 4 * 64; e += kBlock) {
+    const int slot = e / 64, l = e % 64;
+    const int t = slot / 8, c = (slot / 4) % 2, q = slot % 4;
+    const int j = 16 * t + 4 * (l / 16) + q, r = l % 16;
+    if (j >= nj || r >= nw) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) v += (double)red[w][slot][l];
+    part[(2L * ((long)r * nv + j0 + j) + c) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+template <class SV>
+static int dots_mfma(hipStream_t s, long n, int nv, const SV* base, long ld, const SV* W, long ldw, int nw,
+                     const int* active, double* part) {
+  if (nv < 1 || nv > kLpMaxNV) fail(DL_E_INVALID, "low-precision contraction takes 1..128 basis vectors");
+  if (nw < 1 || nw > 16) fail(DL_E_INVALID, "low-precision contraction takes 1..16 columns");
+  if (n < 1) fail(DL_E_INVALID, "empty fields");
+  constexpr int C = LpTraits<SV>::kCpl;
+  if ((reinterpret_cast<uintptr_t>(base) | reinterpret_cast<uintptr_t>(W)) % 16 != 0 || ld % C != 0 || ldw % C != 0)
+    fail(DL_E_INVALID, "low-precision contraction needs 16-byte aligned fields");
+  const int nb = tsk_lowp_nblocks(n, sizeof(SV) == 4 ? DL_BF16 : DL_FP32);
+  for (int j0 = 0; j0 < nv; j0 += kLpRows) {
+    const int nj = nv - j0 < kLpRows ? nv - j0 : kLpRows;
+    hipLaunchKernelGGL(k_tsk_dots_mfma<SV>, dim3(nb), dim3(kBlock), 0, s, n, nv, j0, nj, base, ld, W, ldw, nw, active,
+                       part);
+    DL_HIP(hipGetLastError());
+  }
+  return nb;
+}
+
+int tsk_lowp_nblocks(long n, int prec) {
+  const long step = prec == DL_BF16 ? 16 : 8;  // complex elements per wave step
+  long nb = (n + 8 * step - 1) / (8 * step);   // one pair of steps per wave, four waves per block
+  if (nb < 1) nb = 1;
+  if (nb > kLpBlocks) nb = kLpBlocks;
+  return (int)nb;
+}
+
+int tsk_dots_lowp(hipStream_t s, long n, int nv, const float2* base, long ld, const float2* W, long ldw, int nw,
+                  const int* active, double* part) {
+  return dots_mfma(s, n, nv, base, ld, W, ldw, nw, active, part);
+}
+
+int tsk_dots_lowp(hipStream_t s, long n, int nv, const bf2* base, long ld, const bf2* W, long ldw, int nw,
+                  const int* active, double* part) {
+  return dots_mfma(s, n, nv, base, ld, W, ldw, nw, active, part);
 }
 
 }  // namespace dl

@@ -27,5 +27,19 @@ int tsk_dots_multi(hipStream_t s, long n, int nv, const double2* base, long ld, 
 void tsk_update_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* D, int nw,
                       const int* active, double2* X, long ldx);
 int tsk_multi_nblocks(long n);
+// The same update over an FP32-stored basis (FP64 products and sums).
+void tsk_update_multi32(hipStream_t s, long n, int nv, const float2* base, long ld, const double2* D, int nw,
+                        const int* active, double2* X, long ldx);
+
+// Matrix-core form of the multi-column dots over FP32- or BF16-stored fields (FP32
+// accumulation, FP64 partials): part <- partials of c[r*nv + j] = <V_j, W_r> for nv <= 128,
+// nw <= 16 (sum with sum_partials(part, np, 2*nv*nw, c)); returns np = tsk_lowp_nblocks(n, prec)
+// (<= 512, so part needs 2*nv*nw*512 doubles).  Fields must be 16-byte aligned, with ld and
+// ldw multiples of the elements per 16 bytes (2 for FP32, 4 for BF16).
+int tsk_dots_lowp(hipStream_t s, long n, int nv, const float2* base, long ld, const float2* W, long ldw, int nw,
+                  const int* active, double* part);
+int tsk_dots_lowp(hipStream_t s, long n, int nv, const bf2* base, long ld, const bf2* W, long ldw, int nw,
+                  const int* active, double* part);
+int tsk_lowp_nblocks(long n, int prec);
 
 }  // namespace dl

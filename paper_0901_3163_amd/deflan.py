@@ -40,7 +40,7 @@ class dl_first_opts(C.Structure):
 class dl_next_opts(C.Structure):
     _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
                 ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p), ("graph", C.c_int),
-                ("inner_drop", C.c_double)]
+                ("inner_drop", C.c_double), ("eig_storage", C.c_int)]
 
 
 class dl_batch_item(C.Structure):
@@ -90,6 +90,8 @@ def _load():
         "dl_tsk_project": (I, [P, L, I, P, P, P, I, I]),
         "dl_tsk_combine": (I, [P, L, I, P, P, I, P, I]),
         "dl_tsk_project_multi": (I, [P, L, I, P, I, P, P, P, I]),
+        "dl_tsk_project_lowp": (I, [P, I, L, I, P, I, P, P, P, I]),
+        "dl_eig_lower": (I, [P, P, I, C.POINTER(L)]),
         "dl_small_eigh": (I, [P, I, P, P, P]),
         "dl_net_num_weights": (I, []),
         "dl_net_create": (I, [P, P, C.POINTER(P)]),
@@ -114,7 +116,7 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson",
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
-            "dl_solve_next_multi", "dl_tsk_project_multi")
+            "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower")
 
 
 def _check(rc):
@@ -216,6 +218,13 @@ class Eig:
         _check(lib.dl_eig_info(self.h, C.byref(k), None, None))
         return k.value
 
+    def lower(self, prec):
+        """Lowered copies for the batched projection (DL_FP32 or DL_BF16; DL_FP64 drops them).
+        Returns the MVPs used (k for the FP32 basis's Gram matrix, 0 if already built)."""
+        used = C.c_long()
+        _check(lib.dl_eig_lower(self.op.h, self.h, int(prec), C.byref(used)))
+        return used.value
+
     def vectors(self):
         V = np.zeros((self.k, self.op.V, 4, 3), dtype=np.complex128)
         if self.k:
@@ -284,13 +293,13 @@ class Operator:
         return x, eig, dict(st.as_dict(), rc=rc)
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
-                   reliable_every=None, net=None, graph=False, inner_drop=None):
+                   reliable_every=None, net=None, graph=False, inner_drop=None, eig_storage=DL_FP64):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
         o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
                          int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0,
-                         float(inner_drop or 0.0))
+                         float(inner_drop or 0.0), int(eig_storage))
         st = (dl_stats * max(nrhs, 1))()
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
@@ -403,7 +412,7 @@ def num_weights() -> int:
 
 
 def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s=None, graph=False,
-                     storage=DL_FP32, inner_drop=None):
+                     storage=DL_FP32, inner_drop=None, eig_storage=DL_FP64):
     """Later right-hand sides of several operators in one batched solve.
 
     items: sequence of (op, eig or None, B [nrhs][V][4][3], tol); all B numpy (host) or all
@@ -423,7 +432,7 @@ def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s
         keep.append(B)
         Xs.append(X)
     o = dl_next_opts(int(storage), int(reliable_every or 0), 1, 1 if x0s is not None else 0, int(max_mvp or 0), None,
-                     1 if graph else 0, float(inner_drop or 0.0))
+                     1 if graph else 0, float(inner_drop or 0.0), int(eig_storage))
     ntot = sum(int(B.shape[0]) for B in keep)
     st = (dl_stats * max(ntot, 1))()
     rc = _check(lib.dl_solve_next_multi(ctx.h, len(items), its, mem if mem is not None else DL_HOST, C.byref(o), st))
@@ -457,6 +466,21 @@ def dl_tsk_project_multi(ctx: Context, V, W, X=None):
     pC, _ = _ptr(C)
     pX = _ptr(Xo)[0] if Xo is not None else None
     _check(lib.dl_tsk_project_multi(ctx.h, int(V.shape[1]), int(V.shape[0]), pV, int(W.shape[0]), pW, pC, pX, mem))
+    return C, Xo
+
+
+def dl_tsk_project_lowp(ctx: Context, prec, V, W, X=None):
+    """C = q(V)^H q(W) per column ([nw][nv]) on the matrix cores, q = rounding to prec (DL_FP32 or
+    DL_BF16); if X is given, X + fp32(V) C^T per column in FP64."""
+    V, W = _c128(V), _c128(W)
+    C = _empty_like(W, (W.shape[0], V.shape[0]))
+    Xo = None if X is None else (_c128(X).copy() if isinstance(X, np.ndarray) else X.clone())
+    pV, mem = _ptr(V)
+    pW, _ = _ptr(W)
+    pC, _ = _ptr(C)
+    pX = _ptr(Xo)[0] if Xo is not None else None
+    _check(lib.dl_tsk_project_lowp(ctx.h, int(prec), int(V.shape[1]), int(V.shape[0]), pV, int(W.shape[0]), pW, pC,
+                                   pX, mem))
     return C, Xo
 
 
