@@ -1,0 +1,89 @@
+"""The benchmark workload at its full size (16^3x32 near-critical field, MinRes-DR(120,60) on
+gamma5 M, then the 12 point sources on the BF16 batched path with the BF16-contracted projection
+and a learned guess), checked on outputs the oracle can compute one by one: every solution's
+true residual with the oracle's Wilson matrix, sampled eigenpairs of the handle (Rayleigh
+quotient and residual), one lowered Galerkin projection against the oracle's, and agreement
+with the plain FP64 path."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from lattice_inputs import gaussian_spinor, net_weights, point_source, su3_links
+from oracle import cwilson, deflated, dirac, lowp
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_benchmark_workload_full_size(gpu_ctx):
+    import torch
+    from paper_0901_3163_amd import deflan
+    with open(os.path.join(ROOT, "tests", "golden", "kappa.json")) as fh:
+        e = json.load(fh)["16x16x16x32"]
+    dims, kappa = tuple(e["dims"]), e["kappa"]
+    U = su3_links(dims, e["seed"], e["eps"])
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    op = deflan.Operator(gpu_ctx, dims, torch.from_numpy(U).cuda(), kappa, deflan.DL_G5M)
+    b1 = gaussian_spinor(dims, 200)
+    x1, eig, st1 = op.solve_first(torch.from_numpy(b1).cuda(), 120, 60, 1e-10)
+    x1 = x1.cpu().numpy()
+    r1 = np.linalg.norm(b1.ravel() - ora.M(x1.ravel())) / np.linalg.norm(b1)
+    assert st1["relres"] <= 1e-10 and r1 <= 1.0001e-10
+    # sampled eigenpairs: the library's Rayleigh quotients and residual norms, recomputed by the oracle
+    evals, resid = eig.info()
+    Y = eig.vectors()
+    for i in (0, 1, 29, 59):
+        y = Y[i].ravel()
+        ay = ora.g5M(y)
+        lam = float(np.real(np.vdot(y, ay)))
+        assert abs(lam - evals[i]) <= 1e-12 + 1e-10 * abs(evals[i])
+        assert abs(np.linalg.norm(ay - evals[i] * y) - resid[i]) <= 1e-12 + 1e-8 * resid[i]
+        assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+    # one Galerkin projection of a Gaussian rhs (max_mvp stops the solve right after it): the
+    # BF16-contracted, FP32-corrected projection against the oracle's projection over the same
+    # rounded bases (FP32 accumulation of exact BF16 products on the GPU, 1e-5), and against the
+    # FP64-coefficient projection (the BF16 contraction perturbs each coefficient by about
+    # 1.6e-3 ||r|| / sqrt(n), amplified by 1/|lambda|: a few 1e-3 of the correction)
+    eig.lower(deflan.DL_BF16)
+    b = gaussian_spinor(dims, 202)
+    Xp, _, _ = op.solve_next(b[None], eig, 1e-10, storage=deflan.DL_BF16, batched=1,
+                             eig_storage=deflan.DL_BF16, max_mvp=1)
+    Yc = Y.reshape(len(evals), -1).T
+    Y32, Y16 = lowp.round_f32(Yc), lowp.round_bf16(Yc)
+    cw = cwilson.CWilson(U, dims, kappa)
+    H32 = lowp.gram(cw.g5M, Y32)
+    g5b = ora.g5(b.ravel())
+    want = lowp.lowered_projection(Y16, Y32, H32, g5b, "bf16")
+    exact = deflated.galerkin_projection(Y32, H32, g5b)
+    got = Xp[0].ravel()
+    assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
+    assert np.linalg.norm(got - exact) <= 2e-2 * np.linalg.norm(exact)
+    del Y, Yc, Y32, Y16
+    # the smallest |lambda| is the one the oracle's Lanczos run found when it fixed kappa (that
+    # estimate stopped on a 1e-4 relative change of the smallest Ritz value of M^dag M, which
+    # approaches from above)
+    lmin = np.min(np.abs(evals))
+    assert lmin <= e["min_abs_eig"] * (1 + 1e-6) and lmin >= 0.99 * e["min_abs_eig"], (lmin, e["min_abs_eig"])
+    # the timed path of the benchmark
+    net = deflan.Net(gpu_ctx, net_weights(7))
+    B = np.stack([point_source(dims, 0, s, c) for s in range(4) for c in range(3)])
+    Bd = torch.from_numpy(B).cuda()
+    X, sts, rc = op.solve_next(Bd, eig, 1e-10, storage=deflan.DL_BF16, batched=1, net=net,
+                               eig_storage=deflan.DL_BF16)
+    assert rc == deflan.DL_OK
+    X = X.cpu().numpy()
+    X64, st64, rc64 = op.solve_next(Bd, eig, 1e-10)
+    assert rc64 == deflan.DL_OK
+    X64 = X64.cpu().numpy()
+    for i in range(len(B)):
+        b = B[i].ravel()
+        r = np.linalg.norm(b - ora.M(X[i].ravel())) / np.linalg.norm(b)
+        assert sts[i]["relres"] <= 1e-10 and r <= 1.0001e-10, (i, r, sts[i]["relres"])
+        # the two paths agree to what 1e-10 residuals allow on a field with min|lambda| ~ 1e-4
+        assert np.linalg.norm(X[i] - X64[i]) / np.linalg.norm(X64[i]) < 1e-5
+    net.close()
+    eig.close()
+    op.close()
