@@ -80,11 +80,12 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ void sst(float2* p, float2 v) { *p = v; }
 __device__ __forceinline__ void sst(double2* p, double2 v) { *p = v; }
+// one v_cvt_pk_bf16_f32 (round to nearest even, as f2bf for every finite value)
+typedef float f32x2_st __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_st __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void sst(bf2* p, float2 v) {
-  bf2 b;
-  b.x = f2bf(v.x);
-  b.y = f2bf(v.y);
-  *p = b;
+  const f32x2_st f = {v.x, v.y};
+  *reinterpret_cast<unsigned*>(p) = __builtin_bit_cast(unsigned, __builtin_convertvector(f, bf16x2_st));
 }
 
 template <class R> struct CT;
