@@ -130,6 +130,12 @@ k_b_minres_start(Seg g, const double2* r64, SV* v, SV* vp, SV* d1, SV* d2, SV* e
     s[B_FLAG] = 0.0;
     s[B_NCUR] = 1.0;   // the first Lanczos vector is stored normalised
     s[B_NPREV] = 1.0;
+    // the update that the first fused step applies (of the iteration before the first) is
+    // d = (vp - 0 - 0) / 1 = 0, e += 0
+    s[B_TAU] = 0.0;
+    s[B_DELTA] = 0.0;
+    s[B_EPS] = 0.0;
+    s[B_GAMMA] = 1.0;
     invs[rhs] = 1.0;
   }
 }
@@ -140,31 +146,6 @@ __global__ void __launch_bounds__(kBlock) k_b_fin_alpha(const double* part, int 
   __shared__ double lds[kBlock / 64];
   const double s = b_fin_sum(part + (long)r * np, np, lds);
   if (threadIdx.x == 0) st[r * NS + B_ALPHA] = s;
-}
-
-// Lanczos vectors are kept unnormalised, u_j = n_j v_j, and w = A v_j (the
-// Wilson epilogue applied 1/n_j).  un = w - (alpha/n_j) u_j - (beta_j/n_{j-1}) u_{j-1},
-// written over u_{j-1}; partial ||un||^2.
-template <class SV>
-__global__ void __launch_bounds__(kBlock)
-k_b_lanczos3(Seg g, const double* st, const SV* u, SV* up, const SV* w, const int* __restrict__ active,
-             double* __restrict__ part) {
-  const int rhs = blockIdx.y;
-  double acc = 0.0;
-  if (!active || active[rhs]) {
-    const double* S = st + rhs * NS;
-    const float a = (float)(S[B_ALPHA] / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
-    const long off = seg_off(g, rhs), n = seg_len(g, rhs);
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-      float2 t = c_axpy(-a, sld(u + off + i), sld(w + off + i));
-      t = c_axpy(-b, sld(up + off + i), t);
-      sst(up + off + i, t);
-      acc = fma((double)t.x, (double)t.x, fma((double)t.y, (double)t.y, acc));
-    }
-  }
-  __shared__ double lds[kBlock / 64];
-  const double s = block_sum<kBlock>(acc, lds);
-  if (threadIdx.x == 0) part[(long)rhs * gridDim.x + blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -231,6 +212,44 @@ k_b_minres_update(Seg g, const double* st, const SV* u, const SV* d1, const SV* 
     sst(dn + off + i, d);
     sst(e + off + i, c_axpy(tau, d, sld(e + off + i)));
   }
+}
+
+// One pass for two steps of the batched MinRes.  Lanczos vectors are kept unnormalised,
+// u_j = n_j v_j, and w = A v_{j+1} (the Wilson epilogue applied 1/n_{j+1}).  The Lanczos step
+// of iteration j + 1: un = w - (alpha/n_{j+1}) u_{j+1} - (beta_{j+1}/n_j) u_j, written over
+// u_j, partial ||un||^2.  The solution update of iteration j, delayed by one iteration: as
+// k_b_minres_update on u_j with the rotation of iteration j, which the state holds until the
+// rotation of j + 1 is formed after this pass.  u_j is read once for both; the per-element
+// arithmetic and its order are those of the two steps done apart.
+template <class SV>
+__global__ void __launch_bounds__(kBlock)
+k_b_lanczos_minres(Seg g, const double* st, const SV* u, SV* up, const SV* w, const SV* d1, SV* d2, SV* e,
+                   const int* __restrict__ active, double* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  double acc = 0.0;
+  if (!active || active[rhs]) {
+    const double* S = st + rhs * NS;
+    const float a = (float)(S[B_ALPHA] / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
+    const float delta = (float)S[B_DELTA], eps = (float)S[B_EPS], ig = (float)(1.0 / S[B_GAMMA]);
+    const float tau = (float)S[B_TAU];
+    const float iu = (float)(1.0 / S[B_NPREV]);
+    const long off = seg_off(g, rhs), n = seg_len(g, rhs);
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+      const float2 uj = sld(up + off + i);
+      float2 d = c_axpy(-delta, sld(d1 + off + i), c_scale(uj, iu));
+      d = c_axpy(-eps, sld(d2 + off + i), d);
+      d = c_scale(d, ig);
+      sst(d2 + off + i, d);
+      sst(e + off + i, c_axpy(tau, d, sld(e + off + i)));
+      float2 t = c_axpy(-a, sld(u + off + i), sld(w + off + i));
+      t = c_axpy(-b, uj, t);
+      sst(up + off + i, t);
+      acc = fma((double)t.x, (double)t.x, fma((double)t.y, (double)t.y, acc));
+    }
+  }
+  __shared__ double lds[kBlock / 64];
+  const double s = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) part[(long)rhs * gridDim.x + blockIdx.x] = s;
 }
 
 // x64 += e (FP32 correction)
@@ -895,16 +914,17 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       hipLaunchKernelGGL((k_b_minres_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), u, up, d1, d2, e,
                          bt.st.get(), bt.invs.get(), bt.active.get());
       // one MinRes iteration; `check` (even) iterations return u, up, d1, d2 to their places,
-      // so a block of them is the same launch sequence every time (replayed as a graph)
+      // so a block of them is the same launch sequence every time (replayed as a graph).  The
+      // solution update of an iteration runs in the next iteration's Lanczos pass; an rhs stops
+      // only at a check, after an even number of iterations, so its buffers keep their roles
+      // and its last update is applied after the loop.
       auto iteration = [&]() {
         const int nbs = bwilson_lo(bt, 2, u, w, 2, bt.part.get(), bt.invs.get());
         hipLaunchKernelGGL(k_b_fin_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
                            bt.active.get());
-        hipLaunchKernelGGL((k_b_lanczos3<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, up, w,
-                           bt.active.get(), bt.part.get());
+        hipLaunchKernelGGL((k_b_lanczos_minres<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, up, w, d1,
+                           d2, e, bt.active.get(), bt.part.get());
         hipLaunchKernelGGL(k_b_fin_rot, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), G, bt.st.get(), bt.invs.get(),
-                           bt.active.get());
-        hipLaunchKernelGGL((k_b_minres_update<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, d1, d2, d2, e,
                            bt.active.get());
         DL_HIP(hipGetLastError());
         std::swap(d1, d2);
@@ -937,6 +957,9 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       }
       bt.h_active = inner_active;
       bt.push_active();
+      // the last iteration's solution update (its rotation is still in the state)
+      hipLaunchKernelGGL((k_b_minres_update<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), up, d1, d2, d2, e,
+                         bt.active.get());
       hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
     } else {
       SV *r32 = f0, *sv = f1, *p = f2, *q = f3, *e = f4;
