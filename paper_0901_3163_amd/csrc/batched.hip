@@ -930,6 +930,14 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
         std::swap(d1, d2);
         std::swap(u, up);
       };
+      // Host checks (a device-to-host copy and a wait) fall at multiples of `check`; the next
+      // one is scheduled from each active rhs's residual decay since its previous check: at
+      // 3/4 of the fewest iterations any of them needs to reach its target, between `check`
+      // and 8 * `check` iterations ahead (and not past an MVP cap).
+      std::vector<double> eta_prev(nr);
+      std::vector<long> it_prev(nr, 0);
+      for (int r = 0; r < nr; ++r) eta_prev[r] = bt.get(r, B_NRM);
+      long next_check = check;
       for (int it = 0; it < 100000; ++it) {
         if (use_graph) {
           if (it % check == 0) graphs.run(0, [&] { for (int q = 0; q < check; ++q) iteration(); });
@@ -940,19 +948,32 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
           iters[r] += bt.h_active[r];
           mvp[r] += bt.h_active[r];
         }
-        if ((it + 1) % check == 0) {
+        if (it + 1 == next_check) {
           bt.pull_state();
           bool changed = false;
+          double kmin = 8.0 * check;
           for (int r = 0; r < nr; ++r) {
             if (!bt.h_active[r]) continue;
             const double eta = std::fabs(bt.get(r, B_ETA));
             if (eta <= target[r] || bt.get(r, B_FLAG) != 0.0 || mvp[r] >= o.max_mvp) {
               bt.h_active[r] = 0;
               changed = true;
+              continue;
             }
+            double k = check;
+            if (eta < eta_prev[r] && eta_prev[r] > 0.0) {
+              const double rate = std::log(eta / eta_prev[r]) / (double)(it + 1 - it_prev[r]);
+              k = std::log(target[r] / eta) / rate;
+            }
+            k = std::min(k, (double)(o.max_mvp - mvp[r]));
+            kmin = std::min(kmin, k);
+            eta_prev[r] = eta;
+            it_prev[r] = it + 1;
           }
           if (changed) bt.push_active();
           if (bt.n_active() == 0) break;
+          const long ahead = (long)(0.75 * kmin) / check * check;
+          next_check = it + 1 + std::max<long>(check, std::min<long>(ahead, 8L * check));
         }
       }
       bt.h_active = inner_active;
