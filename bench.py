@@ -292,6 +292,111 @@ def precision_study(args):
     print(json.dumps(res), flush=True)
 
 
+def learned_study(args):
+    """The learned initial guess across gauge fields: 16^3x32, training fields with links seeds
+    10-17, held-out fields 20-23, all at the benchmark kappa (tuned on seed 0).  Per field the
+    first rhs (Gaussian) runs MinRes-DR(m,k) on gamma5 M; the training pairs are 256 Gaussian rhs
+    per training field (2048 in all) solved to tol by the batched path; the network is trained
+    in FP32 by Adam, cycling over the training fields; each held-out field then solves 64 Gaussian
+    rhs (in batches of 16) from net(b) + projection and from the projection alone.  The path is
+    the benchmark's (batched D-MinRes, BF16 storage, BF16-contracted projection).  Prints one JSON
+    line."""
+    import torch
+    from lattice_inputs import gaussian_spinor, net_weights, su3_links
+    from paper_0901_3163_amd import deflan
+    e = kappa_for("16x16x16x32")
+    dims, kappa, tol = tuple(e["dims"]), e["kappa"], args.tol
+    ctx = deflan.Context(0)
+    st_, est = deflan.DL_BF16, deflan.DL_BF16
+    per_train, per_test, bs = args.learned_pairs, args.learned_test, 16
+
+    def field(seed):
+        U = torch.from_numpy(su3_links(dims, seed, e["eps"])).cuda()
+        op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_G5M)
+        del U
+        t0 = time.time()
+        _, eig, st1 = op.solve_first(torch.from_numpy(gaussian_spinor(dims, 1000 + seed)).cuda(), args.m, args.k, tol)
+        eig.lower(est)
+        torch.cuda.synchronize()
+        log(f"learned: field {seed}: MinRes-DR({args.m},{args.k}) {st1['mvp']} MVPs, {time.time() - t0:.1f}s")
+        return op, eig, dict(seed=seed, first_rhs_mvp=st1["mvp"], first_rhs_seconds=round(time.time() - t0, 2))
+
+    def rhs(seed0, n):
+        return torch.from_numpy(np.stack([gaussian_spinor(dims, seed0 + i) for i in range(n)])).cuda()
+
+    def solve(op, eig, B, net=None):
+        its, kept, ok = [], [], True
+        t0 = time.time()
+        X = torch.empty_like(B)
+        for i in range(0, B.shape[0], bs):
+            Xi, sts, rc = op.solve_next(B[i:i + bs], eig, tol, storage=st_, batched=1, net=net, eig_storage=est)
+            X[i:i + bs] = Xi
+            its += [s["iters"] for s in sts]
+            kept += [s["guess"] for s in sts]
+            ok &= rc == 0 and all(s["relres"] <= tol for s in sts)
+        torch.cuda.synchronize()
+        return X, its, kept, ok, time.time() - t0
+
+    train, fields_info = [], []
+    t_pairs = 0.0
+    for seed in range(10, 18):
+        op, eig, info = field(seed)
+        B = rhs(20000 + 1000 * seed, per_train)
+        X, its, _, ok, dt = solve(op, eig, B)
+        t_pairs += dt
+        info.update(pairs=per_train, pair_iters_per_rhs=float(np.mean(its)), pairs_converged=bool(ok))
+        fields_info.append(info)
+        eig.close()
+        train.append((op, B, X))
+        log(f"learned: field {seed}: {per_train} pairs in {dt:.1f}s, {np.mean(its):.0f} iterations per rhs")
+    net = deflan.Net(ctx, net_weights(args.net_seed))
+    t0 = time.time()
+    losses = []
+    for ep in range(args.learned_epochs):
+        for op, B, X in train:
+            losses += list(net.train(op, B, X, batch=args.train_batch, steps=args.learned_steps, lr=args.train_lr))
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"learned: {len(losses)} Adam steps in {t_train:.1f}s, loss {losses[0]:.4f} -> {np.mean(losses[-20:]):.4f}")
+    for op, B, X in train:
+        op.close()
+    del train
+    torch.cuda.empty_cache()
+    held = []
+    for seed in range(20, 24):
+        op, eig, info = field(seed)
+        B = rhs(40000 + 1000 * seed, per_test)
+        solve(op, eig, B[:bs])  # launch-shape tuning and warm-up
+        X0, it0, _, ok0, dt0 = solve(op, eig, B)
+        X1, it1, kept, ok1, dt1 = solve(op, eig, B, net)
+        nx = torch.linalg.vector_norm(X0.reshape(per_test, -1), dim=1)
+        diff = float((torch.linalg.vector_norm((X1 - X0).reshape(per_test, -1), dim=1) / nx).max())
+        held.append(dict(info, rhs=per_test, projection_only=dict(value=round(per_test / dt0, 3), unit="RHS/s",
+                                                                   iters_per_rhs=float(np.mean(it0)),
+                                                                   all_rhs_converged=bool(ok0)),
+                         net_plus_projection=dict(value=round(per_test / dt1, 3), unit="RHS/s",
+                                                  iters_per_rhs=float(np.mean(it1)), all_rhs_converged=bool(ok1),
+                                                  guess_kept=float(np.mean(kept))),
+                         max_rel_difference_of_solutions=diff))
+        log(f"learned: held-out field {seed}: iterations {np.mean(it0):.1f} -> {np.mean(it1):.1f}, "
+            f"RHS/s {per_test / dt0:.1f} -> {per_test / dt1:.1f}")
+        eig.close()
+        op.close()
+    res = dict(workload=(f"16^3x32 Wilson (kappa {kappa:.6f} for every field), training fields 10-17, held-out 20-23, "
+                         f"Gaussian rhs, batched D-MinRes BF16 with BF16-contracted projection, tol {tol:g}"),
+               training=dict(fields=fields_info, pairs=per_train * 8, pair_seconds=round(t_pairs, 2),
+                             epochs=args.learned_epochs, steps_per_field=args.learned_steps,
+                             batch=args.train_batch, lr=args.train_lr, adam_steps=len(losses),
+                             train_seconds=round(t_train, 2), loss_first=round(float(losses[0]), 5),
+                             loss_last20=round(float(np.mean(losses[-20:])), 5)),
+               held_out=held,
+               iters_saved_per_rhs=float(np.mean([h["projection_only"]["iters_per_rhs"]
+                                                  - h["net_plus_projection"]["iters_per_rhs"] for h in held])))
+    net.close()
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def multi_lattice(args):
     """Uneven lattices in one batched solve: 16 Gaussian rhs on each of 8^4, 12^4, 16^3x32 and
     20^3x40 (64 in all), D-CG on M^dag M with k = 40, 60, 80, 100 eigenvectors from Lan-DR(k + 40, k)
@@ -456,6 +561,12 @@ def main():
     ap.add_argument("--prec-k", type=int, default=100)
     ap.add_argument("--no-proj-sweep", action="store_true", help="skip the deflation-contraction sweep")
     ap.add_argument("--proj-only", action="store_true", help="run only the deflation contraction (profiling)")
+    ap.add_argument("--learned", action="store_true",
+                    help="the learned-guess study across training and held-out fields instead (own JSON line)")
+    ap.add_argument("--learned-pairs", type=int, default=256)
+    ap.add_argument("--learned-test", type=int, default=64)
+    ap.add_argument("--learned-epochs", type=int, default=2)
+    ap.add_argument("--learned-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded across GPUs.",
@@ -470,6 +581,8 @@ def main():
         return precision_study(args)
     if args.proj_only:
         return projection_only(args)
+    if args.learned:
+        return learned_study(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
