@@ -127,6 +127,23 @@ def forward(U, w, b, dims, keep=False):
     return y
 
 
+def layer_rounded(U, W, psi, dims, rnd):
+    """layer() with its operands rounded by rnd: the weights and every transported input."""
+    out = np.zeros((psi.shape[0], W.shape[1], 3), dtype=np.complex128)
+    for h in range(9):
+        out += np.einsum("oi,xic->xoc", rnd(W[h]), rnd(transport(U, psi, dims, h)))
+    return out
+
+
+def forward_lowp(U, w, b, dims, rnd):
+    """net(b) with the 16 -> 16 layer computed by layer_rounded (the other layers exact)."""
+    Ws = split_weights(w)
+    s = input_scale(b)
+    a1 = nonlin(layer(U, Ws[0], b / s, dims))
+    a2 = nonlin(layer_rounded(U, Ws[1], a1, dims, rnd))
+    return s * layer(U, Ws[2], a2, dims)
+
+
 def weight_grad(U, g_out, psi_in, dims):
     """G_W[h, o, i] = sum_x sum_c G_out[x, o, c] conj(T_h psi_in)[x, i, c]."""
     return np.stack([np.einsum("xoc,xic->oi", g_out, np.conj(transport(U, psi_in, dims, h))) for h in range(9)])

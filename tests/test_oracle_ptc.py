@@ -170,3 +170,17 @@ def test_input_scale_is_the_rms_over_the_support():
     U = su3_links(DIMS, 31)
     y = ptc.forward(U, ptc.init_weights(32, scale=1.0), point_source(DIMS, 0, 0, 0), DIMS)
     assert 1e-2 < np.linalg.norm(y[0]) < 1e2
+
+
+def test_forward_with_rounded_middle_layer():
+    """With the identity as rounding it is the pinned forward pass; with BF16 rounding of the
+    16 -> 16 layer's operands it stays within the rounding's reach of it."""
+    from oracle import lowp
+    U = su3_links(DIMS, 40)
+    w = ptc.init_weights(41, scale=1.0)
+    b = gaussian_spinor(DIMS, 42)
+    y = ptc.forward(U, w, b, DIMS)
+    assert np.array_equal(ptc.forward_lowp(U, w, b, DIMS, lambda z: z), y)
+    yb = ptc.forward_lowp(U, w, b, DIMS, lowp.round_bf16)
+    rel = np.linalg.norm(yb - y) / np.linalg.norm(y)
+    assert 1e-5 < rel < 2e-2
