@@ -128,6 +128,8 @@ typedef struct {
                                1.6e-3 sqrt(k / n): BF16 storage, or FP32 storage on large lattices.
                                DL_BF16 is for the gamma5 M form only (DL_E_INVALID with M^dag M,
                                where the residual sees that error amplified by 1/sigma_min(M)). */
+  int    net_prec;          /* learned guess inference: DL_FP32 (default; 0 reads as DL_FP32) or
+                               DL_BF16 (as dl_net_apply_prec) */
 } dl_next_opts;
 
 /* Per-solve statistics. */
@@ -297,6 +299,11 @@ int  dl_net_set_weights(dl_net* net, const double* weights);
 void dl_net_destroy(dl_net* net);
 /* Y = net(B) for nrhs fields B ([nrhs][V][4][3] complex128) on op's lattice and links. */
 int  dl_net_apply(dl_net* net, dl_op* op, int nrhs, const double* B, double* Y, int mem);
+/* The same with prec DL_FP32 (as dl_net_apply) or DL_BF16: the 16 -> 16 layer's channel mixing
+ * with its transported inputs and weights rounded to BF16 on the matrix cores (FP32
+ * accumulation; transports, the other layers and the non-linearity stay FP32).  Inference
+ * only: training uses the FP32 forward pass. */
+int  dl_net_apply_prec(dl_net* net, dl_op* op, int prec, int nrhs, const double* B, double* Y, int mem);
 /* loss = (1/n) sum_j ||M (net(b_j) - x_j)||^2 / ||b_j||^2 over n pairs (B, X), with M in FP32;
  * grad (host complex128, may be NULL) = dloss/dRe W + i dloss/dIm W.  b_j = 0 is invalid. */
 int  dl_net_loss_grad(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem,

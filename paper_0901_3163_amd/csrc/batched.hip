@@ -840,7 +840,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
     std::vector<double> rp(nr);
     for (int r = 0; r < nr; ++r) rp[r] = bt.get(r, B_NRM);
     DBuf<double2> XN((size_t)bt.total), RN((size_t)bt.total);
-    net_apply(net, op, nr, B, XN.get());
+    net_apply(net, op, nr, B, XN.get(), o.net_prec == DL_BF16);
     start(XN.get(), RN.get(), false);
     bt.pull_state();
     // keep the better start per rhs, with its residual and residual state

@@ -123,7 +123,9 @@ dl_next_opts next_defaults(const dl_next_opts* o) {
     d.graph = o->graph;
     if (o->inner_drop != 0.0) d.inner_drop = o->inner_drop;
     d.eig_storage = o->eig_storage;
+    d.net_prec = o->net_prec;
   }
+  if (d.net_prec == 0) d.net_prec = DL_FP32;
   // per-cycle residual drop of the batched inner solve: BF16 storage limits what one cycle
   // can reach, so its cycles end earlier
   if (d.inner_drop == 0.0) d.inner_drop = d.storage == DL_BF16 ? 1e-2 : 1e-4;
@@ -360,6 +362,7 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     need(o.eig_storage == DL_FP64 || o.eig_storage == DL_FP32 || o.eig_storage == DL_BF16,
          "eig_storage must be DL_FP64, DL_FP32 or DL_BF16");
     need(o.eig_storage == DL_FP64 || o.batched, "lowered eigenvectors are read by the batched path (batched = 1)");
+    need(o.net_prec == DL_FP32 || o.net_prec == DL_BF16, "net_prec must be DL_FP32 or DL_BF16");
     need(!(o.net && o.x0_given), "x0_given and a learned initial guess exclude each other");
     if (o.net) check_net_op(o.net, op);
     use_device(op->ctx);
@@ -618,9 +621,10 @@ void dl_net_destroy(dl_net* net) {
   delete net;
 }
 
-int dl_net_apply(dl_net* net, dl_op* op, int nrhs, const double* B, double* Y, int mem) {
+static int net_apply_prec(dl_net* net, dl_op* op, int prec, int nrhs, const double* B, double* Y, int mem) {
   return guard([&] {
     need(net && op, "NULL argument");
+    need(prec == DL_FP32 || prec == DL_BF16, "prec must be DL_FP32 or DL_BF16");
     need(nrhs >= 0, "nrhs must be >= 0");
     if (nrhs == 0) return DL_OK;
     need(B && Y, "NULL argument");
@@ -629,10 +633,18 @@ int dl_net_apply(dl_net* net, dl_op* op, int nrhs, const double* B, double* Y, i
     use_device(op->ctx);
     DBuf<double2> bt = fields_in(op, B, nrhs, mem);
     DBuf<double2> yt((size_t)nrhs * op->lat.nc);
-    net_apply(net, op, nrhs, bt.get(), yt.get());
+    net_apply(net, op, nrhs, bt.get(), yt.get(), prec == DL_BF16);
     fields_out(op, yt.get(), Y, nrhs, mem);
     return DL_OK;
   });
+}
+
+int dl_net_apply(dl_net* net, dl_op* op, int nrhs, const double* B, double* Y, int mem) {
+  return net_apply_prec(net, op, DL_FP32, nrhs, B, Y, mem);
+}
+
+int dl_net_apply_prec(dl_net* net, dl_op* op, int prec, int nrhs, const double* B, double* Y, int mem) {
+  return net_apply_prec(net, op, prec, nrhs, B, Y, mem);
 }
 
 int dl_net_loss_grad(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem, double* loss,

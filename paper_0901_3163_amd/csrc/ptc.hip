@@ -141,6 +141,154 @@ k_ptc_layer(const float2* __restrict__ U, const float2* __restrict__ in, float2*
   }
 }
 
+// ---- 16 -> 16 layer with BF16 channel mixing on the matrix cores (inference) ------------------
+//
+// Per wave: one tile of 64 sites.  For each hop the wave transports its 16 input channels (FP32,
+// one thread per site), rounds them to BF16 and stages them in LDS; the channel mixing is then
+// the real form of a complex product: with K = (channel i, re/im) interleaved (32 per hop) and
+// rows m < 16 the real parts, m >= 16 the imaginary parts of the 16 output channels,
+//     A[o][2i] = Re W, A[o][2i+1] = -Im W, A[16+o][2i] = Im W, A[16+o][2i+1] = Re W,
+// and out[m][(site, colour)] += sum_k A[m][k] T[k][(site, colour)] on v_mfma_f32_32x32x16_bf16:
+// six 32-column tiles (3 colours x 2 halves of the tile's sites) and two K-steps per hop, FP32
+// accumulation over all nine hops.  Lane l supplies row / column l % 32 and K-slice 8 * (l / 32)
+// of both operands; the result register j of lane l is row 8 (j / 4) + 4 (l / 32) + j % 4, so a
+// lane holds the real and imaginary parts of 8 output channels for the 3 colours of two sites,
+// which is all the per-channel non-linearity needs.
+typedef __bf16 bf16x8_n __attribute__((ext_vector_type(8)));
+typedef float f32x16_n __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4_n __attribute__((ext_vector_type(4)));
+typedef float f32x2_n __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_n __attribute__((ext_vector_type(2)));
+
+constexpr int kMixRow = 40;  // BF16 entries per (colour, site) row of the LDS stage (32 used; 80 B keeps 16 B alignment)
+
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
+  const f32x2_n f = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f, bf16x2_n));
+}
+
+// A fragments of a 16 -> 16 layer: frag[(h * 2 + ks) * 64 + lane] = 8 BF16 entries
+// A[m = lane % 32][k = 16 ks + 8 (lane / 32) + j], j = 0..7.
+__global__ void k_ptc_wfrag16(const float2* __restrict__ W, u32x4_n* __restrict__ frag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * 2 * 64) return;
+  const int lane = t % 64, hk = t / 64, h = hk / 2, ks = hk % 2;
+  const int m = lane % 32, kb = 16 * ks + 8 * (lane / 32);
+  float v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kk = kb + j, i = kk / 2, p = kk % 2;
+    const int o = m % 16;
+    const float2 w = W[(h * 16 + o) * 16 + i];
+    v[j] = m < 16 ? (p == 0 ? w.x : -w.y) : (p == 0 ? w.y : w.x);
+  }
+  u32x4_n r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = pack_bf16x2(v[2 * q], v[2 * q + 1]);
+  frag[t] = r;
+}
+
+template <bool NONLIN>
+__global__ void __launch_bounds__(256)
+k_ptc_layer16_mfma(const float2* __restrict__ U, const float2* __restrict__ in, float2* __restrict__ out,
+                   const u32x4_n* __restrict__ frag, int Lx, int Ly, int Lz, int Lt, int V, int ntiles,
+                   long in_stride, long out_stride, const double* __restrict__ out_scale) {
+  __shared__ unsigned short stage[4][3][64 * kMixRow];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int tile = blockIdx.x * 4 + wid;
+  const int item = blockIdx.y;
+  if (tile >= ntiles) return;  // whole waves only: no barrier below spans waves
+  in += item * in_stride;
+  out += item * out_stride;
+  const int site = tile * 64 + lane;
+  const bool valid = site < V;
+  unsigned short* st = &stage[wid][0][0];
+  f32x16_n acc[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[q][j] = 0.f;
+  const int g = lane >> 5, col = lane & 31;
+#pragma unroll 1
+  for (int h = 0; h < 9; ++h) {
+    int nb = site, mu = 0;
+    bool fwd = true;
+    float2 u[9];
+    if (valid && h > 0) {
+      hop_geom(h, site, Lx, Ly, Lz, Lt, nb, mu, fwd);
+      const int ls = fwd ? site : nb;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = U[lnk_idx(ls, mu, e)];
+    }
+    // transport the 16 channels of this site's neighbour, BF16 into the stage [colour][site][k]
+#pragma unroll 2
+    for (int i = 0; i < 16; ++i) {
+      float2 a[3], tr[3];
+      if (valid) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[c] = in[act_idx(nb, 16, i, c)];
+        if (h == 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) tr[c] = a[c];
+        } else {
+          transport3(u, fwd, a, tr);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tr[c] = make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        *reinterpret_cast<unsigned*>(st + (c * 64 + lane) * kMixRow + 2 * i) = pack_bf16x2(tr[c].x, tr[c].y);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const u32x4_n af = frag[(h * 2 + ks) * 64 + lane];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const u32x4_n bf = *reinterpret_cast<const u32x4_n*>(st + (c * 64 + half * 32 + col) * kMixRow + 16 * ks +
+                                                               8 * g);
+          acc[c * 2 + half] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              __builtin_bit_cast(bf16x8_n, af), __builtin_bit_cast(bf16x8_n, bf), acc[c * 2 + half], 0, 0, 0);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  // epilogue: lane holds rows 8q + 4g + r (q, r < 4) of the six tiles: channel o = 8 (q % 2) + 4g + r,
+  // real part for q < 2, imaginary part (row 16 + o) for q >= 2
+  const float sc = out_scale ? (float)out_scale[item] : 1.f;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int s2 = tile * 64 + half * 32 + col;
+    const bool ok = s2 < V;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = 8 * q + 4 * g + r;
+        float2 z[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) z[c] = make_float2(acc[c * 2 + half][4 * q + r], acc[c * 2 + half][4 * (q + 2) + r]);
+        float gsc = sc;
+        if (NONLIN) {
+          float n2 = 0.f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) n2 += z[c].x * z[c].x + z[c].y * z[c].y;
+          gsc = 1.f / sqrtf(1.f + n2);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[act_idx(s2, 16, o, c)] = ok ? c_scale(z[c], gsc) : make_float2(0.f, 0.f);
+      }
+  }
+}
+
 // Backward of f: G_z = g G_f + 2 g' Re<G_f, z> z with g(s) = (1 + s)^-1/2, s = |z|^2 (in place on G).
 __global__ void k_ptc_nonlin_bwd(const float2* __restrict__ zs, float2* __restrict__ G, int C, int V, long stride) {
   const int item = blockIdx.y;
@@ -404,7 +552,7 @@ void layer_wgrad(hipStream_t s, const Lattice& lat, const float2* U, const float
 }
 
 // Forward pass; activations of layers 1, 2 (and pre-activations if keep) stay in net->acts.
-void forward(dl_net* net, dl_op* op, int nitems, const double2* B, float2* Y, bool keep) {
+void forward(dl_net* net, dl_op* op, int nitems, const double2* B, float2* Y, bool keep, bool bf16 = false) {
   hipStream_t s = net->ctx->stream;
   const Lattice& lat = op->lat;
   NetActs& a = net->acts;
@@ -421,8 +569,21 @@ void forward(dl_net* net, dl_op* op, int nitems, const double2* B, float2* Y, bo
   const float2* W = net->W.get();
   launch_layer(s, lat, U, a.a0.get(), a.a1.get(), keep ? a.z1.get() : nullptr, W + net_weight_offset(0), 4, 16, true,
                nitems, nullptr);
-  launch_layer(s, lat, U, a.a1.get(), a.a2.get(), keep ? a.z2.get() : nullptr, W + net_weight_offset(1), 16, 16,
-               true, nitems, nullptr);
+  if (bf16 && !keep) {
+    // inference: the 16 -> 16 layer's channel mixing in BF16 on the matrix cores
+    if (net->frag16.n < (size_t)9 * 2 * 64 * 4) net->frag16.alloc((size_t)9 * 2 * 64 * 4);
+    u32x4_n* fr = reinterpret_cast<u32x4_n*>(net->frag16.get());
+    hipLaunchKernelGGL(k_ptc_wfrag16, dim3((9 * 2 * 64 + 255) / 256), dim3(256), 0, s, W + net_weight_offset(1), fr);
+    const int* L = lat.L;
+    const int ntiles = (int)lat.ntiles;
+    hipLaunchKernelGGL((k_ptc_layer16_mfma<true>), dim3((ntiles + 3) / 4, nitems), dim3(256), 0, s, U, a.a1.get(),
+                       a.a2.get(), fr, L[0], L[1], L[2], L[3], (int)lat.V, ntiles, act_len(lat, 16),
+                       act_len(lat, 16), nullptr);
+    DL_HIP(hipGetLastError());
+  } else {
+    launch_layer(s, lat, U, a.a1.get(), a.a2.get(), keep ? a.z2.get() : nullptr, W + net_weight_offset(1), 16, 16,
+                 true, nitems, nullptr);
+  }
   launch_layer(s, lat, U, a.a2.get(), Y, nullptr, W + net_weight_offset(2), 16, 4, false, nitems, a.s.get());
 }
 
@@ -463,9 +624,9 @@ void NetActs::ensure(const Lattice& lat, int nitems) {
   gsc.alloc(nitems);
 }
 
-void net_apply(dl_net* net, dl_op* op, int nitems, const double2* B, double2* Y64) {
+void net_apply(dl_net* net, dl_op* op, int nitems, const double2* B, double2* Y64, bool bf16) {
   net->acts.ensure(op->lat, nitems);
-  forward(net, op, nitems, B, net->acts.y.get(), false);
+  forward(net, op, nitems, B, net->acts.y.get(), false, bf16);
   hipLaunchKernelGGL(k_to_f64, dim3(kStreamBlocks, nitems), dim3(256), 0, net->ctx->stream, net->acts.y.get(), Y64,
                      op->lat.nc);
   DL_HIP(hipGetLastError());

@@ -31,13 +31,15 @@ struct dl_net {
   dl::DBuf<float2> Wt;     // adjoint weights of the backward pass
   dl::DBuf<float> m, v;    // Adam moments (per real component)
   long step = 0;           // Adam steps taken
+  dl::DBuf<unsigned> frag16; // BF16 matrix-core operands of the 16 -> 16 layer (built per inference)
   dl::NetActs acts;
 };
 
 namespace dl {
 
-// Y64 (tiled FP64, nitems fields at stride lat.nc) = net(B) for tiled FP64 B.
-void net_apply(dl_net* net, dl_op* op, int nitems, const double2* B, double2* Y64);
+// Y64 (tiled FP64, nitems fields at stride lat.nc) = net(B) for tiled FP64 B; bf16: the 16 -> 16
+// layer's channel mixing with BF16 operands on the matrix cores (FP32 accumulation).
+void net_apply(dl_net* net, dl_op* op, int nitems, const double2* B, double2* Y64, bool bf16 = false);
 // Mean over items of ||M (net(b) - x)||^2 / ||b||^2; with grad, net->G holds its real gradient.
 double net_loss_grad(dl_net* net, dl_op* op, int nitems, const double2* B, const double2* X, bool grad);
 // One Adam step on net->W from net->G (bias-corrected, beta1 0.9, beta2 0.999, eps 1e-8).

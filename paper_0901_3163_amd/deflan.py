@@ -40,7 +40,7 @@ class dl_first_opts(C.Structure):
 class dl_next_opts(C.Structure):
     _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
                 ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p), ("graph", C.c_int),
-                ("inner_drop", C.c_double), ("eig_storage", C.c_int)]
+                ("inner_drop", C.c_double), ("eig_storage", C.c_int), ("net_prec", C.c_int)]
 
 
 class dl_batch_item(C.Structure):
@@ -99,6 +99,7 @@ def _load():
         "dl_net_set_weights": (I, [P, P]),
         "dl_net_destroy": (None, [P]),
         "dl_net_apply": (I, [P, P, I, P, P, I]),
+        "dl_net_apply_prec": (I, [P, P, I, I, P, P, I]),
         "dl_net_loss_grad": (I, [P, P, I, P, P, I, C.POINTER(D), P]),
         "dl_net_train": (I, [P, P, I, P, P, I, I, I, D, P]),
     }
@@ -116,7 +117,8 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson",
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
-            "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower")
+            "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower",
+            "dl_net_apply_prec")
 
 
 def _check(rc):
@@ -293,13 +295,14 @@ class Operator:
         return x, eig, dict(st.as_dict(), rc=rc)
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
-                   reliable_every=None, net=None, graph=False, inner_drop=None, eig_storage=DL_FP64):
+                   reliable_every=None, net=None, graph=False, inner_drop=None, eig_storage=DL_FP64,
+                   net_prec=DL_FP32):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
         o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
                          int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0,
-                         float(inner_drop or 0.0), int(eig_storage))
+                         float(inner_drop or 0.0), int(eig_storage), int(net_prec))
         st = (dl_stats * max(nrhs, 1))()
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
@@ -366,13 +369,16 @@ class Net:
             raise ValueError(f"expected {num_weights()} complex weights, got shape {w.shape}")
         _check(lib.dl_net_set_weights(self.h, w.ctypes.data_as(C.c_void_p)))
 
-    def apply(self, op: "Operator", B):
-        """net(b) for each field of B ([n][V][4][3])."""
+    def apply(self, op: "Operator", B, prec=None):
+        """net(b) for each field of B ([n][V][4][3]); prec DL_BF16: BF16 matrix-core inference."""
         B = _c128(B)
         Y = _empty_like(B)
         pB, mem = _ptr(B)
         pY, _ = _ptr(Y)
-        _check(lib.dl_net_apply(self.h, op.h, int(B.shape[0]), pB, pY, mem))
+        if prec is None:
+            _check(lib.dl_net_apply(self.h, op.h, int(B.shape[0]), pB, pY, mem))
+        else:
+            _check(lib.dl_net_apply_prec(self.h, op.h, int(prec), int(B.shape[0]), pB, pY, mem))
         return Y
 
     def loss_grad(self, op: "Operator", B, X, grad: bool = True):
@@ -432,7 +438,7 @@ def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s
         keep.append(B)
         Xs.append(X)
     o = dl_next_opts(int(storage), int(reliable_every or 0), 1, 1 if x0s is not None else 0, int(max_mvp or 0), None,
-                     1 if graph else 0, float(inner_drop or 0.0), int(eig_storage))
+                     1 if graph else 0, float(inner_drop or 0.0), int(eig_storage), DL_FP32)
     ntot = sum(int(B.shape[0]) for B in keep)
     st = (dl_stats * max(ntot, 1))()
     rc = _check(lib.dl_solve_next_multi(ctx.h, len(items), its, mem if mem is not None else DL_HOST, C.byref(o), st))

@@ -44,6 +44,33 @@ def test_forward_matches_oracle(gpu_ctx, dims):
     op.close()
 
 
+@pytest.mark.parametrize("dims", [RAGGED, (4, 4, 4, 4), (8, 8, 8, 8)])
+def test_bf16_inference_matches_oracle(gpu_ctx, dims):
+    """BF16 matrix-core inference of the 16 -> 16 layer against the oracle with that layer's
+    weights and transported inputs rounded to BF16 the same way (FP32 accumulation over 288
+    products, and the rare BF16 tie that the GPU's FP32 transport and the oracle's FP64 one
+    round apart: 1e-4 norm-wise), and against the exact oracle (the rounding itself: 2e-2)."""
+    from paper_0901_3163_amd import deflan
+    from oracle import lowp
+    U = su3_links(dims, 40)
+    w = ptc.init_weights(41, scale=1.0)
+    op = deflan.Operator(gpu_ctx, dims, U, 0.12, deflan.DL_G5M)
+    net = deflan.Net(gpu_ctx, w)
+    B = np.stack([gaussian_spinor(dims, 42 + i) for i in range(3)])
+    B[1] *= 1e3
+    Y = net.apply(op, B, prec=deflan.DL_BF16)
+    for i in range(3):
+        want = ptc.forward_lowp(U, w, B[i], dims, lowp.round_bf16)
+        assert _rel(Y[i], want) < 1e-4, (i, _rel(Y[i], want))
+        assert _rel(Y[i], ptc.forward(U, w, B[i], dims)) < 2e-2
+    Y32 = net.apply(op, B, prec=deflan.DL_FP32)
+    assert np.array_equal(Y32, net.apply(op, B))
+    with pytest.raises(deflan.DeflanError):
+        net.apply(op, B, prec=deflan.DL_FP64)
+    net.close()
+    op.close()
+
+
 def test_weights_roundtrip_and_zero_net(gpu_ctx):
     from paper_0901_3163_amd import deflan
     dims = RAGGED
@@ -161,6 +188,17 @@ def test_training_lowers_loss_and_guess_helps_solve(gpu_ctx, c1_config):
         assert _rel(Xn[i], Xh[i]) < 1e-6
         assert stn[i]["guess"] == 1 and stp[i]["guess"] == 0
     assert sum(s["iters"] for s in stn) <= 1.05 * sum(s["iters"] for s in stp)
+    # BF16 inference of the guess: the same solutions to tol, the learned start still kept
+    Xb, stb, rc = op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net,
+                                net_prec=deflan.DL_BF16)
+    assert rc == deflan.DL_OK
+    for i in range(4):
+        r = np.linalg.norm(Bh[i].ravel() - ora.M(Xb[i].ravel())) / np.linalg.norm(Bh[i])
+        assert stb[i]["relres"] <= 1e-10 and r <= 1.0001e-10
+        assert stb[i]["guess"] == 1
+    assert sum(s["iters"] for s in stb) <= 1.05 * sum(s["iters"] for s in stp)
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net, net_prec=7)
     eig.close()
     net.close()
     op.close()
