@@ -255,7 +255,7 @@ def precision_study(args):
     nx = torch.linalg.vector_norm(X64.reshape(nrhs, -1), dim=1)
     cases = {}
     for sname, scode in (("fp32", deflan.DL_FP32), ("bf16", deflan.DL_BF16)):
-        op.solve_next(B[:2], eig, tol, storage=scode, batched=1)  # launch-shape tuning for this storage
+        op.solve_next(B, eig, tol, storage=scode, batched=1, reliable_every=50)  # tuning and warm-up, 12 rhs
         # (the BF16 contraction serves the gamma5 M form only: on M^dag M its error reaches the
         # residual amplified by 1/sigma_min(M))
         for ename, ecode in (("fp64", deflan.DL_FP64), ("fp32", deflan.DL_FP32)):
@@ -324,12 +324,13 @@ def learned_study(args):
     def rhs(seed0, n):
         return torch.from_numpy(np.stack([gaussian_spinor(dims, seed0 + i) for i in range(n)])).cuda()
 
-    def solve(op, eig, B, net=None):
+    def solve(op, eig, B, net=None, nprec=deflan.DL_FP32):
         its, kept, ok = [], [], True
         t0 = time.time()
         X = torch.empty_like(B)
         for i in range(0, B.shape[0], bs):
-            Xi, sts, rc = op.solve_next(B[i:i + bs], eig, tol, storage=st_, batched=1, net=net, eig_storage=est)
+            Xi, sts, rc = op.solve_next(B[i:i + bs], eig, tol, storage=st_, batched=1, net=net, eig_storage=est,
+                                        net_prec=nprec)
             X[i:i + bs] = Xi
             its += [s["iters"] for s in sts]
             kept += [s["guess"] for s in sts]
@@ -369,6 +370,7 @@ def learned_study(args):
         solve(op, eig, B[:bs])  # launch-shape tuning and warm-up
         X0, it0, _, ok0, dt0 = solve(op, eig, B)
         X1, it1, kept, ok1, dt1 = solve(op, eig, B, net)
+        _, it2, kept2, ok2, dt2 = solve(op, eig, B, net, deflan.DL_BF16)
         nx = torch.linalg.vector_norm(X0.reshape(per_test, -1), dim=1)
         diff = float((torch.linalg.vector_norm((X1 - X0).reshape(per_test, -1), dim=1) / nx).max())
         held.append(dict(info, rhs=per_test, projection_only=dict(value=round(per_test / dt0, 3), unit="RHS/s",
@@ -376,10 +378,15 @@ def learned_study(args):
                                                                    all_rhs_converged=bool(ok0)),
                          net_plus_projection=dict(value=round(per_test / dt1, 3), unit="RHS/s",
                                                   iters_per_rhs=float(np.mean(it1)), all_rhs_converged=bool(ok1),
-                                                  guess_kept=float(np.mean(kept))),
+                                                  guess_kept=float(np.mean(kept)), inference="fp32"),
+                         net_bf16_plus_projection=dict(value=round(per_test / dt2, 3), unit="RHS/s",
+                                                       iters_per_rhs=float(np.mean(it2)),
+                                                       all_rhs_converged=bool(ok2),
+                                                       guess_kept=float(np.mean(kept2)), inference="bf16"),
                          max_rel_difference_of_solutions=diff))
-        log(f"learned: held-out field {seed}: iterations {np.mean(it0):.1f} -> {np.mean(it1):.1f}, "
-            f"RHS/s {per_test / dt0:.1f} -> {per_test / dt1:.1f}")
+        log(f"learned: held-out field {seed}: iterations {np.mean(it0):.1f} -> {np.mean(it1):.1f} "
+            f"(BF16 inference {np.mean(it2):.1f}), RHS/s {per_test / dt0:.1f} -> {per_test / dt1:.1f} "
+            f"(BF16 inference {per_test / dt2:.1f})")
         eig.close()
         op.close()
     res = dict(workload=(f"16^3x32 Wilson (kappa {kappa:.6f} for every field), training fields 10-17, held-out 20-23, "
@@ -553,6 +560,8 @@ def main():
                     help="Krylov-vector storage of the timed fast path")
     ap.add_argument("--eig-storage", choices=("fp64", "fp32", "bf16"), default="bf16",
                     help="eigenvectors the projection of the timed fast path reads")
+    ap.add_argument("--net-prec", choices=("fp32", "bf16"), default="bf16",
+                    help="inference precision of the learned guess on the timed fast path")
     ap.add_argument("--multi", action="store_true", help="the uneven multi-lattice batch instead (own JSON line)")
     ap.add_argument("--multi-storage", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--precision", action="store_true",
@@ -628,10 +637,13 @@ def main():
     torch.cuda.synchronize()
     lowering = dict(mvp=lower_mvp, seconds=round(time.time() - t0, 2))
 
-    def fast(use_net=True, st=None, eig_st=None):
+    net_prec = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.net_prec]
+
+    def fast(use_net=True, st=None, eig_st=None, nprec=None):
         return op.solve_next(B, eig, args.tol, storage=storage if st is None else st, batched=1,
                              net=net if use_net else None,
-                             eig_storage=eig_storage if eig_st is None else eig_st)
+                             eig_storage=eig_storage if eig_st is None else eig_st,
+                             net_prec=net_prec if nprec is None else nprec)
 
     def plain():
         return op.solve_next(B, eig, args.tol)
@@ -660,19 +672,22 @@ def main():
     if net is not None:
         net_info["guess_kept_per_rhs"] = float(np.mean(kept))
     E64, E32, E16 = deflan.DL_FP64, deflan.DL_FP32, deflan.DL_BF16
-    for name, st_, use_net, est in (("fp32", deflan.DL_FP32, False, E64), ("bf16", deflan.DL_BF16, False, E64),
-                                    ("fp32+guess", deflan.DL_FP32, True, E64),
-                                    ("bf16+guess", deflan.DL_BF16, True, E64),
-                                    ("fp32+eig_fp32", deflan.DL_FP32, False, E32),
-                                    ("bf16+eig_bf16", deflan.DL_BF16, False, E16),
-                                    ("bf16+eig_bf16+guess", deflan.DL_BF16, True, E16)):
+    N32, N16 = deflan.DL_FP32, deflan.DL_BF16
+    for name, st_, use_net, est, npr in (("fp32", deflan.DL_FP32, False, E64, N32),
+                                         ("bf16", deflan.DL_BF16, False, E64, N32),
+                                         ("fp32+guess", deflan.DL_FP32, True, E64, N32),
+                                         ("bf16+guess", deflan.DL_BF16, True, E64, N32),
+                                         ("fp32+eig_fp32", deflan.DL_FP32, False, E32, N32),
+                                         ("bf16+eig_bf16", deflan.DL_BF16, False, E16, N32),
+                                         ("bf16+eig_bf16+guess", deflan.DL_BF16, True, E16, N32),
+                                         ("bf16+eig_bf16+guess_bf16", deflan.DL_BF16, True, E16, N16)):
         if use_net and net is None:
             continue
-        fast(use_net, st_, est)
+        fast(use_net, st_, est, npr)
         torch.cuda.synchronize()
         t0 = time.time()
         for s in range(args.ablation_steps):
-            Xm, stm, _ = fast(use_net, st_, est)
+            Xm, stm, _ = fast(use_net, st_, est, npr)
         torch.cuda.synchronize()
         dtm = time.time() - t0
         ablation[name] = dict(value=round(nrhs * args.ablation_steps / dtm, 3), unit="RHS/s",
@@ -717,8 +732,9 @@ def main():
                                        "fp32": "FP32 eigenvectors (matrix-core contraction)",
                                        "bf16": "BF16-contracted, FP32-corrected eigenvectors (matrix cores)"}[
                                            args.eig_storage]
-                                    + (", learned initial guess (net(b) + projection, kept per rhs when its "
-                                       "residual is smaller)" if net is not None else ""))),
+                                    + (f", learned initial guess ({args.net_prec.upper()} inference; net(b) + "
+                                       "projection, kept per rhs when its residual is smaller)"
+                                       if net is not None else ""))),
                   all_rhs_converged=bool(all_ok), iters_per_rhs=float(np.mean(iters)),
                   learned_guess=net_info, ablation_batched=ablation,
                   plain_fp64=dict(value=round(plain_value, 3), unit="RHS/s", steps=args.plain_steps,
