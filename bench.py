@@ -404,6 +404,60 @@ def learned_study(args):
     print(json.dumps(res), flush=True)
 
 
+def ksweep_study(args):
+    """The paper's k-sweep on a 20^3x32 near-critical field (Section 3, Figs. 5 and 6): for the
+    first rhs, unrestarted CG on the normal equations and MinRes on gamma5 M against
+    Lan-DR(200, k) and MinRes-DR(200, k) for k = 20, 60, 150 (MVPs to a relative residual of 1e-8
+    when the linear system converges, and in all, the run continuing for the eigenvectors); for a
+    second rhs, D-CG and D-MinRes with each k against plain CG and MinRes.  All FP64, one rhs at a
+    time, MVPs as in the paper (M^dag M counts 2).  Prints one JSON line."""
+    import torch
+    from lattice_inputs import gaussian_spinor, su3_links
+    from paper_0901_3163_amd import deflan
+    os.environ.setdefault("DEFLAN_VERBOSE", "1")
+    try:
+        e = kappa_for("20x20x20x32")
+    except KeyError:
+        sys.exit("no kappa stored for 20x20x20x32: run `python -m oracle.kappa ksweep`")
+    dims, kappa, tol, m = tuple(e["dims"]), e["kappa"], 1e-8, 200
+    ctx = deflan.Context(0)
+    U = torch.from_numpy(su3_links(dims, e["seed"], e["eps"])).cuda()
+    b1 = torch.from_numpy(gaussian_spinor(dims, 500)).cuda()
+    b2 = torch.from_numpy(gaussian_spinor(dims, 501)).cuda()[None]
+    out = dict(workload=(f"20^3x32 Wilson near-critical (kappa {kappa:.6f}, min|lambda(gamma5 M)| "
+                         f"{e['min_abs_eig']:.2e}), m = {m}, tol {tol:g}, FP64"), methods={})
+    for name, kind, first, nxt in (("M^dag M", deflan.DL_MDAGM, "Lan-DR", "D-CG"),
+                                   ("gamma5 M", deflan.DL_G5M, "MinRes-DR", "D-MinRes")):
+        op = deflan.Operator(ctx, dims, U, kappa, kind)
+        _, s_p1, _ = op.solve_next(b1[None], None, tol)  # unrestarted CG / MinRes
+        _, s_plain, _ = op.solve_next(b2, None, tol)
+        plain = "CG" if kind == deflan.DL_MDAGM else "MinRes"
+        res = dict(plain_first_rhs=dict(method=plain, mvp=s_p1[0]["mvp"], iters=s_p1[0]["iters"]),
+                   plain_second_rhs=dict(method=plain, mvp=s_plain[0]["mvp"], iters=s_plain[0]["iters"]), k={})
+        log(f"ksweep {name}: {plain} {s_p1[0]['mvp']} MVPs on the first rhs, {s_plain[0]['mvp']} on a second")
+        for k in (20, 60, 150):
+            t0 = time.time()
+            _, eig, st1 = op.solve_first(b1, m, k, tol)
+            torch.cuda.synchronize()
+            t1 = time.time() - t0
+            _, s2, _ = op.solve_next(b2, eig, tol)
+            ev, rs = eig.info()
+            res["k"][str(k)] = dict(first_rhs=dict(method=f"{first}({m},{k})", mvp_to_tol=st1["mvp_lin"],
+                                                   mvp=st1["mvp"], stop_rule=st1["stop_rule"],
+                                                   seconds=round(t1, 2)),
+                                    second_rhs=dict(method=nxt, mvp=s2[0]["mvp"], iters=s2[0]["iters"]),
+                                    smallest_abs_eigenvalue=float(np.min(np.abs(ev))),
+                                    largest_kept_abs_eigenvalue=float(np.max(np.abs(ev))),
+                                    max_eigen_residual=float(np.max(rs)))
+            log(f"ksweep {name} k={k}: {first} {st1['mvp_lin']} MVPs to tol ({st1['mvp']} in all, {t1:.1f}s); "
+                f"{nxt} {s2[0]['mvp']} MVPs")
+            eig.close()
+        out["methods"][name] = res
+        op.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def multi_lattice(args):
     """Uneven lattices in one batched solve: 16 Gaussian rhs on each of 8^4, 12^4, 16^3x32 and
     20^3x40 (64 in all), D-CG on M^dag M with k = 40, 60, 80, 100 eigenvectors from Lan-DR(k + 40, k)
@@ -570,6 +624,8 @@ def main():
     ap.add_argument("--prec-k", type=int, default=100)
     ap.add_argument("--no-proj-sweep", action="store_true", help="skip the deflation-contraction sweep")
     ap.add_argument("--proj-only", action="store_true", help="run only the deflation contraction (profiling)")
+    ap.add_argument("--ksweep", action="store_true",
+                    help="the k-sweep on a 20^3x32 field instead (own JSON line)")
     ap.add_argument("--learned", action="store_true",
                     help="the learned-guess study across training and held-out fields instead (own JSON line)")
     ap.add_argument("--learned-pairs", type=int, default=256)
@@ -592,6 +648,8 @@ def main():
         return projection_only(args)
     if args.learned:
         return learned_study(args)
+    if args.ksweep:
+        return ksweep_study(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

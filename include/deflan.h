@@ -98,11 +98,12 @@ typedef struct {
   int    storage;           /* DL_FP64 (default): plain FP64 D-CG / D-MinRes.
                                DL_FP32 / DL_BF16: low-precision Krylov storage and Dslash,
                                FP32 arithmetic, FP64 reliable updates and FP64 true residual. */
-  int    reliable_every;    /* batched path: the FP32 inner solve restarts from the FP64 residual
+  int    reliable_every;    /* batched path: the inner solve restarts from the FP64 residual
                                b - M x64, with a new projection over the eigenvectors, after each
-                               1e-4 reduction; within such a cycle D-CG also makes a reliable update
-                               every reliable_every iterations (x64 += e, r = b - M x64 in FP64,
-                               search direction kept).  0 = default 50, < 0 = no reliable updates */
+                               inner_drop reduction; within such a cycle D-CG also makes a reliable
+                               update every reliable_every iterations (x64 += e, r = b - M x64 in
+                               FP64, search direction kept).  0 = default: 10 for D-CG with DL_BF16
+                               storage, else 50; < 0 = no reliable updates */
   int    batched;           /* 0: one rhs after another; 1: all rhs advance together through
                                the multi-rhs kernels (links read once per site for all rhs) */
   int    x0_given;          /* 1: X holds initial guesses on entry (default 0: x0 = 0) */
@@ -115,8 +116,8 @@ typedef struct {
                                captured HIP graph (fewer launches for small lattices); ignored
                                while kernel timing (dl_timing) is on.  Default 0. */
   double inner_drop;        /* batched path: residual reduction that ends an inner cycle (then
-                               FP64 residual, projection, restart); 0 = default: 1e-4 with DL_FP32
-                               storage, 1e-2 with DL_BF16 (whose rounding limits one cycle) */
+                               FP64 residual, projection, restart); 0 = default: 1e-2 for D-MinRes
+                               with DL_BF16 storage (whose rounding limits one cycle), else 1e-4 */
   int    eig_storage;       /* batched path: eigenvectors the Galerkin projection reads.  DL_FP64
                                (0, default): the handle's FP64 basis.  DL_FP32 / DL_BF16: the
                                lowered copies made by dl_eig_lower (DL_E_INVALID if missing):
