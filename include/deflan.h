@@ -64,6 +64,11 @@ extern "C" {
 #define DL_FP32 1
 #define DL_BF16 2
 
+/* Inner method of the one-rhs-at-a-time FP64 path (dl_next_opts.method). */
+#define DL_METHOD_DEFAULT 0   /* D-CG (CGLS) for DL_MDAGM, D-MinRes for DL_G5M */
+#define DL_METHOD_CG      1   /* CG on the Hermitian form; for DL_G5M that is CG on the indefinite
+                                 gamma5 M, the combination Section 3 advises against (Fig. 7) */
+
 #define DL_HOST   0
 #define DL_DEVICE 1
 
@@ -131,6 +136,9 @@ typedef struct {
                                where the residual sees that error amplified by 1/sigma_min(M)). */
   int    net_prec;          /* learned guess inference: DL_FP32 (default; 0 reads as DL_FP32) or
                                DL_BF16 (as dl_net_apply_prec) */
+  int    method;            /* FP64 one-rhs path: DL_METHOD_DEFAULT or DL_METHOD_CG (the Galerkin
+                               projection at the start is the same; breakdown p^H A p = 0 ends a
+                               cycle, which restarts from the true residual) */
 } dl_next_opts;
 
 /* Per-solve statistics. */

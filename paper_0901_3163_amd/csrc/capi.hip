@@ -125,6 +125,7 @@ dl_next_opts next_defaults(const dl_next_opts* o, int kind) {
     if (o->inner_drop != 0.0) d.inner_drop = o->inner_drop;
     d.eig_storage = o->eig_storage;
     d.net_prec = o->net_prec;
+    d.method = o->method;
   }
   if (d.net_prec == 0) d.net_prec = DL_FP32;
   // Per-cycle residual drop of the batched inner solve and the D-CG reliable-update interval.
@@ -369,6 +370,8 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
          "eig_storage must be DL_FP64, DL_FP32 or DL_BF16");
     need(o.eig_storage == DL_FP64 || o.batched, "lowered eigenvectors are read by the batched path (batched = 1)");
     need(o.net_prec == DL_FP32 || o.net_prec == DL_BF16, "net_prec must be DL_FP32 or DL_BF16");
+    need(o.method == DL_METHOD_DEFAULT || o.method == DL_METHOD_CG, "method must be DL_METHOD_DEFAULT or DL_METHOD_CG");
+    need(o.method == DL_METHOD_DEFAULT || !o.batched, "method DL_METHOD_CG runs on the FP64 one-rhs path (batched = 0)");
     need(!(o.net && o.x0_given), "x0_given and a learned initial guess exclude each other");
     if (o.net) check_net_op(o.net, op);
     use_device(op->ctx);

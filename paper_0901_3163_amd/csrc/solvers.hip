@@ -105,6 +105,31 @@ k_fin_cgls_beta(const double* ps, int nps, const double* pr, int npr, double* sc
   }
 }
 
+// CG on a Hermitian A (positive or not): alpha = ||r||^2 / Re(p^H A p); breakdown if p^H A p = 0.
+__global__ void __launch_bounds__(kBlock) k_fin_cg_alpha(const double* part, int np, double* sc) {
+  __shared__ double lds[kBlock / 64];
+  const double pap = fin_sum(part, np, lds);
+  if (threadIdx.x == 0) {
+    sc[S_QQ] = pap;
+    const bool ok = pap != 0.0 && isfinite(pap) && sc[S_FLAG] == 0.0;
+    sc[S_ALPHA] = ok ? sc[S_RN2] / pap : 0.0;
+    if (!ok) sc[S_FLAG] = 1.0;
+  }
+}
+
+// beta = ||r_new||^2 / ||r||^2, S_RN2 <- ||r_new||^2
+__global__ void __launch_bounds__(kBlock) k_fin_cg_beta(const double* part, int np, double* sc) {
+  __shared__ double lds[kBlock / 64];
+  const double rr = fin_sum(part, np, lds);
+  if (threadIdx.x == 0) {
+    const double old = sc[S_RN2];
+    const bool ok = old > 0.0 && isfinite(rr) && sc[S_FLAG] == 0.0;
+    sc[S_BETA] = ok ? rr / old : 0.0;
+    sc[S_RN2] = rr;
+    if (!ok) sc[S_FLAG] = 1.0;
+  }
+}
+
 // MinRes: Givens QR of the new tridiagonal column (beta_j, alpha_j, beta_{j+1}).
 __global__ void __launch_bounds__(kBlock) k_fin_minres_rot(const double* part, int np, double* sc) {
   __shared__ double lds[kBlock / 64];
@@ -426,6 +451,54 @@ static InnerResult cgls_run(dl_op* op, const double2* b, double2* x, double bnor
   return res;
 }
 
+// CG on gamma5 M x = gamma5 b from x (Hermitian, indefinite), tracking r = gamma5 (b - M x),
+// whose norm is ||b - M x||.  The paper's counter-example to using CG on gamma5 M (Section 3).
+static InnerResult cg_g5_run(dl_op* op, const double2* b, double2* x, double bnorm, double tol, long max_mvp,
+                             Scratch& S, DBuf<double2>* w6, int check_every) {
+  hipStream_t s = op->ctx->stream;
+  const long n = op->lat.nc;
+  const int G = grid_for(n);
+  double2 *r = w6[0].get(), *p = w6[2].get(), *q = w6[3].get();
+  InnerResult res;
+  const int nb = nblocks_for(n);
+  apply_wilson(op, 0, x, q);
+  res.mvp += 1;
+  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(kBlock), 0, s, n, b, q, q, S.part.get());
+  hipLaunchKernelGGL(k_fin_store, dim3(1), dim3(kBlock), 0, s, S.part.get(), nb, S.sc.get(), (int)S_RN2);
+  gamma5_f64(s, op->lat, q, r);
+  copy(s, n, r, p);
+  double h[S_COUNT];
+  read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
+  if (!(std::sqrt(h[S_RN2]) / bnorm > tol)) {
+    res.converged = true;
+    return res;
+  }
+  h[S_FLAG] = 0.0;
+  write_scalars(op->ctx, S.sc.get(), S_COUNT, h);
+  double* pq = S.part.get();
+  double* pr = S.part.get() + kMaxPartials;
+  while (res.mvp < max_mvp) {
+    const int nbw = apply_wilson(op, 2, p, q, 2, pq);  // q = gamma5 M p, partials of Re(p^H q)
+    hipLaunchKernelGGL(k_fin_cg_alpha, dim3(1), dim3(kBlock), 0, s, pq, nbw, S.sc.get());
+    hipLaunchKernelGGL(k_cgls_xr, dim3(nb), dim3(kBlock), 0, s, n, S.sc.get(), p, q, x, r, pr);
+    hipLaunchKernelGGL(k_fin_cg_beta, dim3(1), dim3(kBlock), 0, s, pr, nb, S.sc.get());
+    hipLaunchKernelGGL(k_xpay, dim3(G), dim3(kBlock), 0, s, n, S.sc.get(), (int)S_BETA, r, p);
+    DL_HIP(hipGetLastError());
+    res.mvp += 1;
+    res.iters += 1;
+    if (res.iters % check_every == 0 || res.mvp >= max_mvp) {
+      read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
+      if (h[S_FLAG] != 0.0) {
+        res.breakdown = !(std::sqrt(h[S_RN2]) / bnorm <= tol);
+        res.converged = !res.breakdown;
+        break;
+      }
+      if (std::sqrt(h[S_RN2]) / bnorm <= tol) { res.converged = true; break; }
+    }
+  }
+  return res;
+}
+
 // ---- D-CG / D-MinRes --------------------------------------------------------------
 static void project(dl_op* op, const dl_eig* eig, const double2* r, double2* x, Scratch& S, DBuf<double2>& cbuf) {
   if (!eig || eig->k == 0) return;
@@ -508,9 +581,9 @@ int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2
     bool conv = false;
     double relres = 1.0;
     for (int attempt = 0; attempt < 6; ++attempt) {
-      InnerResult ir = op->kind == DL_G5M
-                           ? minres_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check)
-                           : cgls_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check);
+      InnerResult ir = op->kind != DL_G5M ? cgls_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check)
+                       : o.method == DL_METHOD_CG ? cg_g5_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check)
+                                                  : minres_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check);
       iters += ir.iters;
       mvp += ir.mvp;
       // true residual in FP64
@@ -530,7 +603,8 @@ int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2
     one.time_s = now_s() - t0;
     if (verbose()) {
       std::fprintf(stderr, "[deflan] %s rhs %d: iters %ld relres %.3e (%.3fs)\n",
-                   op->kind == DL_G5M ? "D-MinRes" : "D-CG", r, iters, relres, one.time_s);
+                   op->kind == DL_G5M ? (o.method == DL_METHOD_CG ? "D-CG on gamma5 M" : "D-MinRes") : "D-CG", r,
+                   iters, relres, one.time_s);
       std::fflush(stderr);
     }
     if (!conv) worst = DL_NOT_CONVERGED;

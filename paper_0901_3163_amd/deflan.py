@@ -23,6 +23,7 @@ DL_E_INVALID, DL_E_HIP, DL_E_NOMEM, DL_E_BREAKDOWN, DL_E_NONFINITE, DL_E_MISMATC
 DL_MDAGM, DL_G5M = 0, 1
 DL_FP64, DL_FP32, DL_BF16 = 0, 1, 2
 DL_HOST, DL_DEVICE = 0, 1
+DL_METHOD_DEFAULT, DL_METHOD_CG = 0, 1
 DL_APPLY_M, DL_APPLY_MDAG, DL_APPLY_G5M, DL_APPLY_MDAGM = 0, 1, 2, 3
 STOP_RULES = {0: "linear", 1: "eigen", 2: "mvp_factor", 3: "max_mvp", 4: "breakdown", -1: "none"}
 
@@ -40,7 +41,7 @@ class dl_first_opts(C.Structure):
 class dl_next_opts(C.Structure):
     _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
                 ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p), ("graph", C.c_int),
-                ("inner_drop", C.c_double), ("eig_storage", C.c_int), ("net_prec", C.c_int)]
+                ("inner_drop", C.c_double), ("eig_storage", C.c_int), ("net_prec", C.c_int), ("method", C.c_int)]
 
 
 class dl_batch_item(C.Structure):
@@ -296,13 +297,13 @@ class Operator:
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
                    reliable_every=None, net=None, graph=False, inner_drop=None, eig_storage=DL_FP64,
-                   net_prec=DL_FP32):
+                   net_prec=DL_FP32, method=0):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
         o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
                          int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0,
-                         float(inner_drop or 0.0), int(eig_storage), int(net_prec))
+                         float(inner_drop or 0.0), int(eig_storage), int(net_prec), int(method))
         st = (dl_stats * max(nrhs, 1))()
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
@@ -438,7 +439,7 @@ def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s
         keep.append(B)
         Xs.append(X)
     o = dl_next_opts(int(storage), int(reliable_every or 0), 1, 1 if x0s is not None else 0, int(max_mvp or 0), None,
-                     1 if graph else 0, float(inner_drop or 0.0), int(eig_storage), DL_FP32)
+                     1 if graph else 0, float(inner_drop or 0.0), int(eig_storage), DL_FP32, 0)
     ntot = sum(int(B.shape[0]) for B in keep)
     st = (dl_stats * max(ntot, 1))()
     rc = _check(lib.dl_solve_next_multi(ctx.h, len(items), its, mem if mem is not None else DL_HOST, C.byref(o), st))

@@ -42,16 +42,18 @@ def test_benchmark_workload_full_size(gpu_ctx):
         assert abs(lam - evals[i]) <= 1e-12 + 1e-10 * abs(evals[i])
         assert abs(np.linalg.norm(ay - evals[i] * y) - resid[i]) <= 1e-12 + 1e-8 * resid[i]
         assert abs(np.linalg.norm(y) - 1.0) < 1e-12
-    # one Galerkin projection of a Gaussian rhs (max_mvp stops the solve right after it): the
-    # BF16-contracted, FP32-corrected projection against the oracle's projection over the same
-    # rounded bases (FP32 accumulation of exact BF16 products on the GPU, 1e-5), and against the
-    # FP64-coefficient projection (the BF16 contraction perturbs each coefficient by about
-    # 1.6e-3 ||r|| / sqrt(n), amplified by 1/|lambda|: a few 1e-3 of the correction)
-    eig.lower(deflan.DL_BF16)
+    del Y
+    # one Galerkin projection of a Gaussian rhs (max_mvp stops the solve right after it) over a
+    # basis drawn on the host (60 seeded Gaussian fields, orthonormalised by numpy's QR) and
+    # handed to the library: the BF16-contracted, FP32-corrected projection against the
+    # oracle's projection over the same rounded bases (FP32 accumulation of exact BF16 products
+    # on the GPU: 1e-5), and against the FP64-coefficient projection over the FP32 basis
+    Yc, _ = np.linalg.qr(np.stack([gaussian_spinor(dims, 3000 + j).ravel() for j in range(60)], axis=1))
+    heig = op.eig_create(np.ascontiguousarray(Yc.T).reshape(60, *b1.shape))
+    heig.lower(deflan.DL_BF16)
     b = gaussian_spinor(dims, 202)
-    Xp, _, _ = op.solve_next(b[None], eig, 1e-10, storage=deflan.DL_BF16, batched=1,
+    Xp, _, _ = op.solve_next(b[None], heig, 1e-10, storage=deflan.DL_BF16, batched=1,
                              eig_storage=deflan.DL_BF16, max_mvp=1)
-    Yc = Y.reshape(len(evals), -1).T
     Y32, Y16 = lowp.round_f32(Yc), lowp.round_bf16(Yc)
     cw = cwilson.CWilson(U, dims, kappa)
     H32 = lowp.gram(cw.g5M, Y32)
@@ -61,7 +63,9 @@ def test_benchmark_workload_full_size(gpu_ctx):
     got = Xp[0].ravel()
     assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
     assert np.linalg.norm(got - exact) <= 2e-2 * np.linalg.norm(exact)
-    del Y, Yc, Y32, Y16
+    heig.close()
+    del Yc, Y32, Y16
+    eig.lower(deflan.DL_BF16)
     # the smallest |lambda| is the one the oracle's Lanczos run found when it fixed kappa (that
     # estimate stopped on a 1e-4 relative change of the smallest Ritz value of M^dag M, which
     # approaches from above)

@@ -264,3 +264,50 @@ def test_ragged_lattice_solvers(gpu_ctx):
         X, sts, rc = op.solve_next(gaussian_spinor(dims, 23)[None], eig, tol)
         assert rc == 0 and _oracle_relres(ora, gaussian_spinor(dims, 23), X[0]) <= tol
         op.close()
+
+
+def test_cg_on_indefinite_gamma5_m(gpu_ctx, c1_config, c1dense):
+    """CG on gamma5 M (Hermitian indefinite: the combination Section 3 advises against, Fig. 7):
+    plain CG and D-CG over the 20 lowest eigenvectors reach tol on the GPU and in the oracle
+    (CG on the same matrix, right-hand side gamma5 b, the same eigenvectors and their FP64
+    Galerkin matrix).  The recurrence is unstable on an indefinite spectrum, so rounding order
+    moves the iterates: the iteration counts agree within 15%, and the eigenvectors still cut
+    them, as the paper observes."""
+    from paper_0901_3163_amd import deflan
+    c1 = c1_config
+    dims = c1["dims"]
+    ora = c1dense["op"]
+    op = deflan.Operator(gpu_ctx, dims, c1["links"], c1["kappa"], deflan.DL_G5M)
+    b = gaussian_spinor(dims, 130)
+    bb = b.ravel()
+    g5b = ora.g5(bb)
+    X0, s0, rc0 = op.solve_next(b[None], None, 1e-10, method=deflan.DL_METHOD_CG)
+    assert rc0 == deflan.DL_OK and s0[0]["relres"] <= 1e-10
+    assert _oracle_relres(ora, b, X0[0]) <= 1.0001e-10
+    _, io = krylov.cg(ora.g5M, g5b, tol=1e-10, maxiter=20000)
+    assert io["relres"] <= 1.0001e-10
+    assert abs(s0[0]["iters"] - io["iters"]) <= 0.15 * io["iters"], (s0[0]["iters"], io["iters"])
+    # deflated: the 20 eigenvectors of smallest |lambda| of the dense gamma5 M (oracle side),
+    # handed to the library as a handle
+    g5 = np.tile([1.0] * 6 + [-1.0] * 6, ora.V)
+    lam, Z = np.linalg.eigh(g5[:, None] * c1dense["M"])
+    Y = Z[:, np.argsort(np.abs(lam))[:20]]
+    eig = op.eig_create(np.ascontiguousarray(Y.T).reshape(20, *b.shape))
+    X1, s1, rc1 = op.solve_next(b[None], eig, 1e-10, method=deflan.DL_METHOD_CG)
+    assert rc1 == deflan.DL_OK and s1[0]["relres"] <= 1e-10
+    assert _oracle_relres(ora, b, X1[0]) <= 1.0001e-10
+    assert _rel(X1[0], np.linalg.solve(c1dense["M"], bb)) < 1e-7
+    H = deflated.projection_matrix(ora.g5M, Y)
+    _, io1 = deflated.d_cg(ora.g5M, g5b, Y, H, 1e-10)
+    assert io1["relres"] <= 1.0001e-10
+    assert abs(s1[0]["iters"] - io1["iters"]) <= 0.15 * io1["iters"] + 5, (s1[0]["iters"], io1["iters"])
+    assert s1[0]["iters"] < 0.8 * s0[0]["iters"]
+    # D-MinRes on the same rhs and eigenvectors for comparison (Section 3: MinRes is the method for gamma5 M)
+    X2, s2, _ = op.solve_next(b[None], eig, 1e-10)
+    assert s2[0]["iters"] <= s1[0]["iters"]
+    with pytest.raises(deflan.DeflanError):  # the CG option is for the FP64 one-rhs path
+        op.solve_next(b[None], eig, 1e-10, storage=deflan.DL_FP32, batched=1, method=deflan.DL_METHOD_CG)
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(b[None], eig, 1e-10, method=5)
+    eig.close()
+    op.close()
