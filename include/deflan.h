@@ -107,8 +107,10 @@ typedef struct {
                                b - M x64, with a new projection over the eigenvectors, after each
                                inner_drop reduction; within such a cycle D-CG also makes a reliable
                                update every reliable_every iterations (x64 += e, r = b - M x64 in
-                               FP64, search direction kept).  0 = default: 10 for D-CG with DL_BF16
-                               storage, else 50; < 0 = no reliable updates */
+                               FP64, search direction kept).  0 = default: 8 for D-CG with DL_BF16
+                               storage, else 50; < 0 = no reliable updates.  With DL_BF16 a D-CG
+                               cycle also ends when its residual has not reached a new low (by
+                               10%) for 200 iterations. */
   int    batched;           /* 0: one rhs after another; 1: all rhs advance together through
                                the multi-rhs kernels (links read once per site for all rhs) */
   int    x0_given;          /* 1: X holds initial guesses on entry (default 0: x0 = 0) */
@@ -121,8 +123,9 @@ typedef struct {
                                captured HIP graph (fewer launches for small lattices); ignored
                                while kernel timing (dl_timing) is on.  Default 0. */
   double inner_drop;        /* batched path: residual reduction that ends an inner cycle (then
-                               FP64 residual, projection, restart); 0 = default: 1e-2 for D-MinRes
-                               with DL_BF16 storage (whose rounding limits one cycle), else 1e-4 */
+                               FP64 residual, projection, restart); 0 = default: 1e-4 with DL_FP32
+                               storage; with DL_BF16 (whose rounding limits one cycle) 1e-2 for
+                               D-MinRes and 1e-3 for D-CG */
   int    eig_storage;       /* batched path: eigenvectors the Galerkin projection reads.  DL_FP64
                                (0, default): the handle's FP64 basis.  DL_FP32 / DL_BF16: the
                                lowered copies made by dl_eig_lower (DL_E_INVALID if missing):

@@ -1017,6 +1017,10 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
         hipLaunchKernelGGL((k_b_cg_xpay<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, bt.active.get());
         DL_HIP(hipGetLastError());
       };
+      constexpr long kStall = 25L * check;
+      std::vector<double> best(nr);
+      std::vector<long> best_it(nr, 0);
+      for (int r = 0; r < nr; ++r) best[r] = bt.get(r, B_NRM);
       for (int it = 0; it < 100000; ++it) {
         const bool update = rel_every > 0 && (it + 1) % rel_every == 0;
         if (use_graph) {
@@ -1041,7 +1045,14 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
           for (int r = 0; r < nr; ++r) {
             if (!bt.h_active[r]) continue;
             const double rn = std::sqrt(bt.get(r, B_RR));
-            if (rn <= target[r] || bt.get(r, B_FLAG) != 0.0 || mvp[r] >= o.max_mvp) {
+            // with BF16 storage a cycle also ends when its residual has not reached a new low
+            // (by 10%) for kStall iterations: the rounding can hold it above the cycle's target
+            if (rn < 0.9 * best[r]) {
+              best[r] = rn;
+              best_it[r] = it + 1;
+            }
+            const bool stalled = bf16 && it + 1 - best_it[r] >= kStall;
+            if (rn <= target[r] || stalled || bt.get(r, B_FLAG) != 0.0 || mvp[r] >= o.max_mvp) {
               bt.h_active[r] = 0;
               changed = true;
             }
