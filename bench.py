@@ -217,8 +217,9 @@ def precision_study(args):
     """The precision ablation on the 24^3x48 near-critical lattice (min|lambda(gamma5 M)| ~ 1e-3):
     FP64 Lan-DR(200,100) on M^dag M for a Gaussian first rhs (seed 299), the eigenvectors
     lowered to FP32 and BF16, then D-CG for 12 Gaussian rhs (seeds 300-311) on the batched path
-    with FP32 or BF16 Krylov storage (FP32 arithmetic, reliable updates every 50 iterations,
-    FP64 restarts) and the projection over FP64 or FP32 eigenvectors.  Each
+    with FP32 or BF16 Krylov storage (FP32 arithmetic, FP64 restarts; reliable updates every 50
+    iterations with FP32, the BF16 D-CG defaults with BF16) and the projection over FP64 or FP32
+    eigenvectors.  Each
     case: RHS/s, iterations, the library's FP64 true residual and the relative error against
     the plain FP64 D-CG solutions of the same rhs on the GPU (the parity-checked FP64 path).
     Prints one JSON line."""
@@ -255,13 +256,16 @@ def precision_study(args):
     nx = torch.linalg.vector_norm(X64.reshape(nrhs, -1), dim=1)
     cases = {}
     for sname, scode in (("fp32", deflan.DL_FP32), ("bf16", deflan.DL_BF16)):
-        op.solve_next(B, eig, tol, storage=scode, batched=1, reliable_every=50)  # tuning and warm-up, 12 rhs
+        # reliable updates every 50 iterations with FP32 storage; BF16 takes the library's BF16
+        # D-CG settings (updates every 8 iterations in 1e-3 cycles)
+        rel = 50 if scode == deflan.DL_FP32 else None
+        op.solve_next(B, eig, tol, storage=scode, batched=1, reliable_every=rel)  # tuning and warm-up, 12 rhs
         # (the BF16 contraction serves the gamma5 M form only: on M^dag M its error reaches the
         # residual amplified by 1/sigma_min(M))
         for ename, ecode in (("fp64", deflan.DL_FP64), ("fp32", deflan.DL_FP32)):
             torch.cuda.synchronize()
             t0 = time.time()
-            X, sts, rc = op.solve_next(B, eig, tol, storage=scode, batched=1, reliable_every=50, eig_storage=ecode)
+            X, sts, rc = op.solve_next(B, eig, tol, storage=scode, batched=1, reliable_every=rel, eig_storage=ecode)
             torch.cuda.synchronize()
             dt = time.time() - t0
             err = torch.linalg.vector_norm((X - X64).reshape(nrhs, -1), dim=1) / nx
@@ -468,8 +472,6 @@ def multi_lattice(args):
     from lattice_inputs import gaussian_spinor, su3_links
     from paper_0901_3163_amd import deflan
     os.environ.setdefault("DEFLAN_VERBOSE", "1")
-    # FP32 storage: with BF16 vectors the normal-equations CG needs about 4x the iterations
-    # (cycles limited to a 1e-2 drop each restart its recurrence), so D-CG batches run FP32
     storage = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.multi_storage]
     kappa, tol = 0.145, args.tol
     lats = [((8, 8, 8, 8), 40), ((12, 12, 12, 12), 60), ((16, 16, 16, 32), 80), ((20, 20, 20, 40), 100)]
@@ -617,7 +619,7 @@ def main():
     ap.add_argument("--net-prec", choices=("fp32", "bf16"), default="bf16",
                     help="inference precision of the learned guess on the timed fast path")
     ap.add_argument("--multi", action="store_true", help="the uneven multi-lattice batch instead (own JSON line)")
-    ap.add_argument("--multi-storage", choices=("fp32", "bf16"), default="fp32")
+    ap.add_argument("--multi-storage", choices=("fp32", "bf16"), default="bf16")
     ap.add_argument("--precision", action="store_true",
                     help="the 24^3x48 precision study instead (own JSON line)")
     ap.add_argument("--prec-m", type=int, default=200)
