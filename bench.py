@@ -455,6 +455,14 @@ def ksweep_study(args):
                                     max_eigen_residual=float(np.max(rs)))
             log(f"ksweep {name} k={k}: {first} {st1['mvp_lin']} MVPs to tol ({st1['mvp']} in all, {t1:.1f}s); "
                 f"{nxt} {s2[0]['mvp']} MVPs")
+            if kind == deflan.DL_G5M and k == 150:
+                # CG on the indefinite gamma5 M with and without these eigenvectors (Section 3, Fig. 7)
+                _, sc0, rc0 = op.solve_next(b1[None], None, tol, method=deflan.DL_METHOD_CG)
+                _, sc1, rc1 = op.solve_next(b2, eig, tol, method=deflan.DL_METHOD_CG)
+                res["cg_on_gamma5_m"] = dict(first_rhs=dict(mvp=sc0[0]["mvp"], converged=bool(rc0 == 0)),
+                                             second_rhs_deflated_k150=dict(mvp=sc1[0]["mvp"],
+                                                                           converged=bool(rc1 == 0)))
+                log(f"ksweep gamma5 M: CG {sc0[0]['mvp']} MVPs, D-CG (k=150) {sc1[0]['mvp']} MVPs")
             eig.close()
         out["methods"][name] = res
         op.close()
