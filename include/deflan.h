@@ -102,7 +102,10 @@ typedef struct {
 typedef struct {
   int    storage;           /* DL_FP64 (default): plain FP64 D-CG / D-MinRes.
                                DL_FP32 / DL_BF16: low-precision Krylov storage and Dslash,
-                               FP32 arithmetic, FP64 reliable updates and FP64 true residual. */
+                               FP32 arithmetic, FP64 reliable updates and FP64 true residual.
+                               A BF16 batch whose cycle stalls above its target (modes below
+                               what BF16 resolves, e.g. a near-critical field with too little
+                               deflation) continues with FP32 storage and FP32 cycle settings. */
   int    reliable_every;    /* batched path: the inner solve restarts from the FP64 residual
                                b - M x64, with a new projection over the eigenvectors, after each
                                inner_drop reduction; within such a cycle D-CG also makes a reliable

@@ -731,11 +731,14 @@ struct GraphCache {
     }
     DL_HIP(hipGraphLaunch(it->second, s));
   }
-  ~GraphCache() {
+  void clear() {
     if (!exec.empty()) (void)hipStreamSynchronize(s);
     for (auto& kv : exec) (void)hipGraphExecDestroy(kv.second);
     for (auto& kv : graph) (void)hipGraphDestroy(kv.second);
+    exec.clear();
+    graph.clear();
   }
+  ~GraphCache() { clear(); }
 };
 
 // The batched solve over a list of operators.  B, X: all fields of the batch, field r at
@@ -775,7 +778,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   S.ensure_part((size_t)2 * kmax * tsk_nblocks(bt.nmax) + 64);
   DBuf<double2> R64((size_t)bt.total), T64((size_t)bt.total);
   // low-precision Krylov vectors: FP32 or BF16 storage (FP32 arithmetic either way)
-  const bool bf16 = o.storage == DL_BF16;
+  bool bf16 = o.storage == DL_BF16;  // BF16 storage; a stalled BF16 cycle moves the batch to FP32
   DBuf<float2> f[6];
   DBuf<bf2> h[6];
   for (int q = 0; q < 6; ++q) {
@@ -865,7 +868,9 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       std::fflush(stderr);
     }
   }
-  const double inner_drop = o.inner_drop > 0.0 ? o.inner_drop : 1e-4;  // residual drop that ends a cycle
+  double inner_drop = o.inner_drop > 0.0 ? o.inner_drop : 1e-4;  // residual drop that ends a cycle
+  int rel_opt = o.reliable_every;
+  bool stalled_any = false;
   const int check = 8;                 // iterations between host checks (even)
   const Seg g = bt.seg;
   // Graph replay of the `check`-iteration blocks: off while kernel timing is on (its events
@@ -901,7 +906,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
     // feeds the deflated low modes back in and only the projection removes them cheaply.
     // Within a cycle, CG replaces its residual by the FP64 one every reliable_every iterations
     // and keeps its search direction (a reliable update).
-    const bool reliable = !mr && o.reliable_every > 0;
+    const bool reliable = !mr && rel_opt > 0;
     std::vector<double> target(nr);
     for (int r = 0; r < nr; ++r) target[r] = std::max(inner_drop * bt.get(r, B_NRM), 0.5 * tol[r] * bnorm[r]);
     std::vector<int> inner_active = bt.h_active;
@@ -934,9 +939,10 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       // one is scheduled from each active rhs's residual decay since its previous check: at
       // 3/4 of the fewest iterations any of them needs to reach its target, between `check`
       // and 8 * `check` iterations ahead (and not past an MVP cap).
-      std::vector<double> eta_prev(nr);
-      std::vector<long> it_prev(nr, 0);
-      for (int r = 0; r < nr; ++r) eta_prev[r] = bt.get(r, B_NRM);
+      std::vector<double> eta_prev(nr), mr_best(nr);
+      std::vector<long> it_prev(nr, 0), mr_best_it(nr, 0);
+      constexpr long kStallMR = 25L * check;
+      for (int r = 0; r < nr; ++r) eta_prev[r] = mr_best[r] = bt.get(r, B_NRM);
       long next_check = check;
       for (int it = 0; it < 100000; ++it) {
         if (use_graph) {
@@ -955,7 +961,15 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
           for (int r = 0; r < nr; ++r) {
             if (!bt.h_active[r]) continue;
             const double eta = std::fabs(bt.get(r, B_ETA));
-            if (eta <= target[r] || bt.get(r, B_FLAG) != 0.0 || mvp[r] >= o.max_mvp) {
+            // with BF16 storage a cycle also ends when eta has not reached a new low (by 10%)
+            // for kStall iterations (the rounding can hold it above the cycle's target)
+            if (eta < 0.9 * mr_best[r]) {
+              mr_best[r] = eta;
+              mr_best_it[r] = it + 1;
+            }
+            const bool stalled = bf16 && it + 1 - mr_best_it[r] >= kStallMR && eta > target[r];
+            stalled_any |= stalled;
+            if (eta <= target[r] || stalled || bt.get(r, B_FLAG) != 0.0 || mvp[r] >= o.max_mvp) {
               bt.h_active[r] = 0;
               changed = true;
               continue;
@@ -993,8 +1007,8 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       for (int r = 0; r < nr; ++r) mvp[r] += bt.h_active[r];
       // With graphs, reliable updates fall on the last iteration of every `rel_blocks`-th block.
       const int rel_every = !reliable ? 0
-                            : use_graph ? check * std::max(1, (o.reliable_every + check / 2) / check)
-                                        : o.reliable_every;
+                            : use_graph ? check * std::max(1, (rel_opt + check / 2) / check)
+                                        : rel_opt;
       auto iteration = [&](bool update) {
         bwilson_lo(bt, 0, p, q, 1, bt.part.get());
         hipLaunchKernelGGL(k_b_cg_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
@@ -1051,7 +1065,8 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
               best[r] = rn;
               best_it[r] = it + 1;
             }
-            const bool stalled = bf16 && it + 1 - best_it[r] >= kStall;
+            const bool stalled = bf16 && it + 1 - best_it[r] >= kStall && rn > target[r];
+            stalled_any |= stalled;
             if (rn <= target[r] || stalled || bt.get(r, B_FLAG) != 0.0 || mvp[r] >= o.max_mvp) {
               bt.h_active[r] = 0;
               changed = true;
@@ -1069,6 +1084,25 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
     if (bf16) inner(h[0].get(), h[1].get(), h[2].get(), h[3].get(), h[4].get(), h[5].get());
     else inner(f[0].get(), f[1].get(), f[2].get(), f[3].get(), f[4].get(), f[5].get());
     DL_HIP(hipGetLastError());
+    if (bf16 && stalled_any) {
+      // A BF16 cycle stalled above its target: the modes left in the residual are below what
+      // BF16 vectors resolve (near-critical fields without enough deflation).  The batch goes
+      // on with FP32 storage and the FP32 cycle settings; cycles restart from the FP64 state.
+      for (int q = 0; q < 6; ++q) {
+        h[q].release();
+        f[q].alloc((size_t)bt.total);
+      }
+      if (bt.single()) (void)wilson_cfg(items[0].op, DL_FP32, nr);
+      graphs.clear();  // captured blocks name the BF16 buffers
+      bf16 = false;
+      // the BF16 defaults (1e-3 / 1e-2 drops, updates every 8) give way to the FP32 ones
+      if (inner_drop == 1e-3 || inner_drop == 1e-2) inner_drop = 1e-4;
+      if (rel_opt == 8) rel_opt = 50;
+      if (verbose()) {
+        std::fprintf(stderr, "[deflan] batched: a BF16 cycle stalled, continuing with FP32 storage\n");
+        std::fflush(stderr);
+      }
+    }
   }
   // final FP64 true residuals for every rhs
   std::fill(bt.h_active.begin(), bt.h_active.end(), 1);

@@ -91,3 +91,41 @@ def test_benchmark_workload_full_size(gpu_ctx):
     net.close()
     eig.close()
     op.close()
+
+
+def test_precision_workload_full_size(gpu_ctx):
+    """The 24^3x48 near-critical lattice (min|lambda(gamma5 M)| ~ 1e-3) on the launch configuration
+    of the precision study: batched D-CG with BF16 and FP32 Krylov storage (their default cycle and
+    reliable-update settings) for 12 Gaussian rhs, projected over 12 host-drawn orthonormal fields
+    lowered to FP32.  Every solution's true residual is recomputed by the oracle's C Wilson
+    matrix, and the solutions agree with the plain FP64 D-CG path."""
+    import torch
+    from paper_0901_3163_amd import deflan
+    with open(os.path.join(ROOT, "tests", "golden", "kappa.json")) as fh:
+        e = json.load(fh)["24x24x24x48"]
+    dims, kappa = tuple(e["dims"]), e["kappa"]
+    U = su3_links(dims, e["seed"], e["eps"])
+    cw = cwilson.CWilson(U, dims, kappa)
+    op = deflan.Operator(gpu_ctx, dims, torch.from_numpy(U).cuda(), kappa, deflan.DL_MDAGM)
+    shape = gaussian_spinor((2, 2, 2, 2), 0).shape[1:]
+    Yc, _ = np.linalg.qr(np.stack([gaussian_spinor(dims, 3100 + j).ravel() for j in range(12)], axis=1))
+    eig = op.eig_create(np.ascontiguousarray(Yc.T).reshape(12, -1, *shape))
+    del Yc
+    eig.lower(deflan.DL_FP32)
+    B = np.stack([gaussian_spinor(dims, 300 + i) for i in range(12)])
+    Bd = torch.from_numpy(B).cuda()
+    X64, s64, rc64 = op.solve_next(Bd[:2], eig, 1e-10)
+    assert rc64 == deflan.DL_OK
+    X64 = X64.cpu().numpy()
+    for storage in (deflan.DL_BF16, deflan.DL_FP32):
+        X, sts, rc = op.solve_next(Bd, eig, 1e-10, storage=storage, batched=1, eig_storage=deflan.DL_FP32)
+        assert rc == deflan.DL_OK
+        X = X.cpu().numpy()
+        for i in range(12):
+            b = B[i].ravel()
+            r = np.linalg.norm(b - cw.M(X[i].ravel())) / np.linalg.norm(b)
+            assert sts[i]["relres"] <= 1e-10 and r <= 1.0001e-10, (storage, i, r)
+        for i in range(2):
+            assert np.linalg.norm(X[i] - X64[i]) / np.linalg.norm(X64[i]) < 1e-6
+    eig.close()
+    op.close()
