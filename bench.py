@@ -600,6 +600,35 @@ def projection_only(args):
     ctx.close()
 
 
+def net_only(args):
+    """The learned guess's forward pass alone, for rocprofv3 runs: 12 point sources on the 16^3x32
+    benchmark field, reps calls each with FP32 inference and with the BF16 matrix-core middle layer."""
+    import torch
+    from lattice_inputs import net_weights
+    from paper_0901_3163_amd import deflan
+    e = kappa_for("16x16x16x32")
+    dims = tuple(e["dims"])
+    ctx = deflan.Context(0)
+    op = deflan.Operator(ctx, dims, torch.from_numpy(tiled_links(dims)).cuda(), e["kappa"], deflan.DL_G5M)
+    net = deflan.Net(ctx, net_weights(args.net_seed, scale=1.0))
+    B = torch.from_numpy(point_sources(dims)).cuda()
+    out = {}
+    for name, prec in (("fp32", deflan.DL_FP32), ("bf16", deflan.DL_BF16)):
+        net.apply(op, B, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(args.reps):
+            net.apply(op, B, prec=prec)
+        torch.cuda.synchronize()
+        out[name] = round((time.time() - t0) / args.reps * 1e3, 3)
+        log(f"net forward {name}: {out[name]} ms per call (12 fields, including the host-side copies)")
+    print(json.dumps(dict(kernel="learned-guess forward pass", dims=list(dims), nrhs=12, reps=args.reps,
+                          ms_per_call=out)))
+    net.close()
+    op.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -636,6 +665,7 @@ def main():
     ap.add_argument("--proj-only", action="store_true", help="run only the deflation contraction (profiling)")
     ap.add_argument("--ksweep", action="store_true",
                     help="the k-sweep on a 20^3x32 field instead (own JSON line)")
+    ap.add_argument("--net-only", action="store_true", help="run only the network's forward pass (profiling)")
     ap.add_argument("--learned", action="store_true",
                     help="the learned-guess study across training and held-out fields instead (own JSON line)")
     ap.add_argument("--learned-pairs", type=int, default=256)
@@ -658,6 +688,8 @@ def main():
         return projection_only(args)
     if args.learned:
         return learned_study(args)
+    if args.net_only:
+        return net_only(args)
     if args.ksweep:
         return ksweep_study(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
