@@ -140,14 +140,6 @@ k_b_minres_start(Seg g, const double2* r64, SV* v, SV* vp, SV* d1, SV* d2, SV* e
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_b_fin_alpha(const double* part, int np, double* st, const int* active) {
-  const int r = blockIdx.x;
-  if (active && !active[r]) return;
-  __shared__ double lds[kBlock / 64];
-  const double s = b_fin_sum(part + (long)r * np, np, lds);
-  if (threadIdx.x == 0) st[r * NS + B_ALPHA] = s;
-}
-
 __global__ void __launch_bounds__(kBlock)
 k_b_fin_rot(const double* part, int np, double* st, double* invs, const int* active) {
   const int r = blockIdx.x;
@@ -221,15 +213,26 @@ k_b_minres_update(Seg g, const double* st, const SV* u, const SV* d1, const SV* 
 // k_b_minres_update on u_j with the rotation of iteration j, which the state holds until the
 // rotation of j + 1 is formed after this pass.  u_j is read once for both; the per-element
 // arithmetic and its order are those of the two steps done apart.
+// alpha = <v_{j+1}, A v_{j+1}> is summed from the stencil's partials (apart, anp per rhs) by
+// every block in the same fixed order; block 0 of each rhs stores it for the rotation.
 template <class SV>
 __global__ void __launch_bounds__(kBlock)
-k_b_lanczos_minres(Seg g, const double* st, const SV* u, SV* up, const SV* w, const SV* d1, SV* d2, SV* e,
-                   const int* __restrict__ active, double* __restrict__ part) {
+k_b_lanczos_minres(Seg g, double* st, const SV* u, SV* up, const SV* w, const SV* d1, SV* d2, SV* e,
+                   const int* __restrict__ active, const double* __restrict__ apart, int anp,
+                   double* __restrict__ part) {
   const int rhs = blockIdx.y;
   double acc = 0.0;
+  __shared__ double lds[kBlock / 64];
   if (!active || active[rhs]) {
+    __shared__ double alpha_s;
+    const double asum = b_fin_sum(apart + (long)rhs * anp, anp, lds);
+    if (threadIdx.x == 0) {
+      alpha_s = asum;
+      if (blockIdx.x == 0) st[rhs * NS + B_ALPHA] = asum;
+    }
+    __syncthreads();
     const double* S = st + rhs * NS;
-    const float a = (float)(S[B_ALPHA] / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
+    const float a = (float)(alpha_s / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
     const float delta = (float)S[B_DELTA], eps = (float)S[B_EPS], ig = (float)(1.0 / S[B_GAMMA]);
     const float tau = (float)S[B_TAU];
     const float iu = (float)(1.0 / S[B_NPREV]);
@@ -247,7 +250,7 @@ k_b_lanczos_minres(Seg g, const double* st, const SV* u, SV* up, const SV* w, co
       acc = fma((double)t.x, (double)t.x, fma((double)t.y, (double)t.y, acc));
     }
   }
-  __shared__ double lds[kBlock / 64];
+  __syncthreads();  // lds is reused
   const double s = block_sum<kBlock>(acc, lds);
   if (threadIdx.x == 0) part[(long)rhs * gridDim.x + blockIdx.x] = s;
 }
@@ -925,11 +928,9 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       // and its last update is applied after the loop.
       auto iteration = [&]() {
         const int nbs = bwilson_lo(bt, 2, u, w, 2, bt.part.get(), bt.invs.get());
-        hipLaunchKernelGGL(k_b_fin_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
-                           bt.active.get());
         hipLaunchKernelGGL((k_b_lanczos_minres<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), u, up, w, d1,
-                           d2, e, bt.active.get(), bt.part.get());
-        hipLaunchKernelGGL(k_b_fin_rot, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), G, bt.st.get(), bt.invs.get(),
+                           d2, e, bt.active.get(), bt.part.get(), nbs, bt.part2.get());
+        hipLaunchKernelGGL(k_b_fin_rot, dim3(nr), dim3(kBlock), 0, s, bt.part2.get(), G, bt.st.get(), bt.invs.get(),
                            bt.active.get());
         DL_HIP(hipGetLastError());
         std::swap(d1, d2);
