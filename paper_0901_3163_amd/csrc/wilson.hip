@@ -194,15 +194,18 @@ __device__ __forceinline__ double wilson_site(const typename CT<R>::type* __rest
     const R mk = (R)(-kappa);
     const SV* ip = in + sp_base(site);
     SV* op = out + sp_base(site);
+    R sred = 0;  // this site's share of the reduction, summed in R
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       const C p = sld(ip + c * kTile);
       C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
       if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
       sst(op + c * kTile, r);
-      if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
-      if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
+      if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
+      if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
     }
+    if (RED == 1) red += (double)sred;
+    if (RED == 2) red += (double)sred * sc;
   }
   return red;
 }
@@ -384,15 +387,18 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
         mul_half<true>(u, h, gb);
       }
       SV* op = out + sp_base(site);
+      R sred = 0;  // this site's share of the reduction, summed in R
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const C p = cen[c];
         C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
         if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
         sst(op + c * kTile, r);
-        if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
-        if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
+        if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
+        if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
       }
+      if (RED == 1) red += (double)sred;
+      if (RED == 2) red += (double)sred * sc;
 #pragma unroll
       for (int c = 0; c < 12; ++c) cen[c] = nx[c];
     }
@@ -623,15 +629,18 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
         mul_half<true>(u, h, gb);
       }
       SV* op = out + sp_base(site);
+      R sred = 0;  // this site's share of the reduction, summed in R
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const C p = cen[c];
         C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
         if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
         sst(op + c * kTile, r);
-        if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
-        if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
+        if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
+        if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
       }
+      if (RED == 1) red += (double)sred;
+      if (RED == 2) red += (double)sred * sc;
 #pragma unroll
       for (int c = 0; c < 12; ++c) cen[c] = nx[c];
     }
@@ -764,15 +773,18 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
         mul_half<true>(u, h, gb);
       }
       SV* op = out + sp_base(site);
+      R sred = 0;  // this site's share of the reduction, summed in R
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const C p = cen[c];
         C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
         if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
         sst(op + c * kTile, r);
-        if (RED == 1) red += (double)r.x * r.x + (double)r.y * r.y;
-        if (RED == 2) red += ((double)p.x * r.x + (double)p.y * r.y) * sc;
+        if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
+        if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
       }
+      if (RED == 1) red += (double)sred;
+      if (RED == 2) red += (double)sred * sc;
 #pragma unroll
       for (int c = 0; c < 12; ++c) cen[c] = nx[c];
     }
