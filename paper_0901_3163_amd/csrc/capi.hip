@@ -211,6 +211,7 @@ void dl_ctx_destroy(dl_ctx* ctx) {
   ctx->timers.collect();
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  dl::dmem_trim(ctx->device);
   delete ctx;
 }
 

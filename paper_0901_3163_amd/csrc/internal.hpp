@@ -60,8 +60,9 @@ struct Lattice {
 Lattice make_lattice(const int dims[4]);
 
 // ---- device memory --------------------------------------------------------
-void* dmalloc(size_t bytes);
+void* dmalloc(size_t bytes);  // cached per device (freed blocks are reused by size)
 void dfree(void* p);
+void dmem_trim(int dev);      // release the device's cached blocks
 
 template <class T>
 struct DBuf {

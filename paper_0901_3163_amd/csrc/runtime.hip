@@ -2,7 +2,11 @@
 #include "internal.hpp"
 
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <stdexcept>
+#include <unordered_map>
+#include <vector>
 
 namespace dl {
 
@@ -20,19 +24,113 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
   fail(e == hipErrorOutOfMemory ? DL_E_NOMEM : DL_E_HIP, buf);
 }
 
+// Device memory is cached per device: a freed block goes to a free list keyed by its
+// (rounded) size and is handed out again by the next request of that size, so repeated
+// solves of one shape map no new memory.  Sizes round to 512 B, and to 2 MiB from 1 MiB up.
+// A block is cached only after a device-wide synchronisation (what hipFree implies), so a
+// block never changes hands while a kernel on any stream may still use it.  The cache holds
+// at most an eighth of the device's memory; an allocation that fails releases the device's
+// cache and tries once more; dmem_trim releases it on request (context destruction).
+namespace {
+struct Block {
+  int dev;
+  size_t bytes;
+};
+struct MemCache {
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free_list;
+  std::unordered_map<void*, Block> live;
+  std::map<int, size_t> cached, cap;
+};
+MemCache& mem_cache() {
+  static MemCache* c = new MemCache;  // never destroyed: blocks may be returned during exit
+  return *c;
+}
+size_t round_bytes(size_t b) {
+  const size_t g = b >= (size_t(1) << 20) ? (size_t(1) << 21) : 512;
+  return (b + g - 1) / g * g;
+}
+void trim_locked(MemCache& c, int dev) {
+  for (auto it = c.free_list.begin(); it != c.free_list.end();) {
+    if (it->first.first == dev) {
+      for (void* p : it->second) (void)hipFree(p);
+      it = c.free_list.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  c.cached[dev] = 0;
+}
+}  // namespace
+
 void* dmalloc(size_t bytes) {
+  int dev = 0;
+  DL_HIP(hipGetDevice(&dev));
+  const size_t rb = round_bytes(bytes);
+  MemCache& c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.free_list.find({dev, rb});
+  if (it != c.free_list.end() && !it->second.empty()) {
+    void* p = it->second.back();
+    it->second.pop_back();
+    c.cached[dev] -= rb;
+    c.live[p] = Block{dev, rb};
+    return p;
+  }
   void* p = nullptr;
-  const hipError_t e = hipMalloc(&p, bytes);
+  hipError_t e = hipMalloc(&p, rb);
+  if (e == hipErrorOutOfMemory && c.cached[dev] > 0) {
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    trim_locked(c, dev);
+    e = hipMalloc(&p, rb);
+  }
   if (e != hipSuccess) {
+    (void)hipGetLastError();
     char buf[256];
     std::snprintf(buf, sizeof buf, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     fail(e == hipErrorOutOfMemory ? DL_E_NOMEM : DL_E_HIP, buf);
   }
+  c.live[p] = Block{dev, rb};
   return p;
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  MemCache& c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) {  // not ours
+    (void)hipFree(p);
+    return;
+  }
+  const Block b = it->second;
+  c.live.erase(it);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != b.dev) (void)hipSetDevice(b.dev);
+  if (!c.cap.count(b.dev)) {
+    size_t fr = 0, tot = 0;
+    c.cap[b.dev] = hipMemGetInfo(&fr, &tot) == hipSuccess ? tot / 8 : 0;
+  }
+  if (hipDeviceSynchronize() == hipSuccess && c.cached[b.dev] + b.bytes <= c.cap[b.dev]) {
+    c.free_list[{b.dev, b.bytes}].push_back(p);
+    c.cached[b.dev] += b.bytes;
+  } else {
+    (void)hipFree(p);
+  }
+  if (cur != b.dev) (void)hipSetDevice(cur);
+}
+
+void dmem_trim(int dev) {
+  MemCache& c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != dev) (void)hipSetDevice(dev);
+  (void)hipDeviceSynchronize();
+  trim_locked(c, dev);
+  if (cur != dev) (void)hipSetDevice(cur);
 }
 
 Lattice make_lattice(const int dims[4]) {
