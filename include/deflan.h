@@ -145,6 +145,14 @@ typedef struct {
   int    method;            /* FP64 one-rhs path: DL_METHOD_DEFAULT or DL_METHOD_CG (the Galerkin
                                projection at the start is the same; breakdown p^H A p = 0 ends a
                                cycle, which restarts from the true residual) */
+  int    minres_window;     /* batched D-MinRes without graph replay: the Lanczos vectors of a
+                               cycle are kept in a ring and every minres_window iterations one
+                               pass adds their share of the solution (the iteration's own pass
+                               then moves 4 fields instead of 9).  0 = default: 64, halved down
+                               to 8 while the ring (minres_window + 2 fields per rhs) exceeds
+                               24 GiB; 1..64 = that window; < 0 = the fused short-recurrence
+                               form (the form graph replay uses).  > 64: DL_E_INVALID.  Both
+                               forms compute the same iterates up to rounding. */
 } dl_next_opts;
 
 /* Per-solve statistics. */

@@ -40,7 +40,7 @@ namespace dl {
 // per-rhs device state, st[r * NS + field]
 enum {
   B_ALPHA = 0, B_BETA, B_BNEXT, B_COLD, B_SOLD, B_C, B_S, B_ETA, B_TAU, B_DELTA, B_EPS, B_GAMMA,
-  B_INV, B_NRM, B_FLAG, B_SS, B_QQ, B_RR, B_CGA, B_CGB, B_NCUR, B_NPREV, NS
+  B_INV, B_NRM, B_FLAG, B_SS, B_QQ, B_RR, B_CGA, B_CGB, B_NCUR, B_NPREV, B_WSTART, B_WCNT, NS
 };
 
 // Field layout of a batch: rhs r starts at off[r] and has len[r] complex elements (device
@@ -52,6 +52,8 @@ struct Seg {
 };
 __device__ __forceinline__ long seg_off(const Seg& g, int r) { return g.off ? g.off[r] : (long)r * g.n; }
 __device__ __forceinline__ long seg_len(const Seg& g, int r) { return g.off ? g.len[r] : g.n; }
+
+constexpr int kMaxWindow = 64;  // longest window of the windowed MinRes
 
 static int bgrid(long n) {
   long nb = (n + kBlock - 1) / kBlock;
@@ -136,12 +138,17 @@ k_b_minres_start(Seg g, const double2* r64, SV* v, SV* vp, SV* d1, SV* d2, SV* e
     s[B_DELTA] = 0.0;
     s[B_EPS] = 0.0;
     s[B_GAMMA] = 1.0;
+    s[B_WSTART] = 0.0;  // windowed form: no rotation recorded yet
+    s[B_WCNT] = 0.0;
     invs[rhs] = 1.0;
   }
 }
 
+// coef != nullptr (windowed MinRes): the rotation's (tau, delta, eps, gamma, n_j) is also
+// recorded at slot B_WCNT of the rhs's window (W slots) and B_WCNT is advanced.
 __global__ void __launch_bounds__(kBlock)
-k_b_fin_rot(const double* part, int np, double* st, double* invs, const int* active) {
+k_b_fin_rot(const double* part, int np, double* st, double* invs, const int* active, double* coef = nullptr,
+            int W = 0) {
   const int r = blockIdx.x;
   if (active && !active[r]) return;
   __shared__ double lds[kBlock / 64];
@@ -181,6 +188,20 @@ k_b_fin_rot(const double* part, int np, double* st, double* invs, const int* act
       S[B_BNEXT] = 0.0;
       invs[r] = 0.0;
       if (S[B_FLAG] == 0.0) S[B_FLAG] = 1.0;
+    }
+    if (coef) {
+      const int L = (int)S[B_WCNT];
+      if (L < W) {
+        double* c = coef + ((long)r * W + L) * 5;
+        c[0] = S[B_TAU];
+        c[1] = S[B_DELTA];
+        c[2] = S[B_EPS];
+        c[3] = S[B_GAMMA];
+        c[4] = S[B_NPREV];
+        S[B_WCNT] = L + 1;
+      } else {
+        S[B_FLAG] = 3.0;  // a window overran (the host flushes every W iterations)
+      }
     }
   }
 }
@@ -253,6 +274,127 @@ k_b_lanczos_minres(Seg g, double* st, const SV* u, SV* up, const SV* w, const SV
   __syncthreads();  // lds is reused
   const double s = block_sum<kBlock>(acc, lds);
   if (threadIdx.x == 0) part[(long)rhs * gridDim.x + blockIdx.x] = s;
+}
+
+// ---- windowed MinRes ---------------------------------------------------------------
+// The same iterates as the fused form above, with the solution kept apart from the Lanczos
+// pass: the unnormalised Lanczos vectors u_j of the cycle go to a ring of R = W + 2 slots
+// (u_j in slot j mod R, u_0 = 0), each rotation's coefficients are recorded, and every W
+// iterations one pass forms the window's share of the solution update and the last two
+// search directions from the stored vectors.  The per-iteration pass then reads three
+// vectors and writes one instead of reading six and writing three.
+
+// Lanczos step alone: un = w - (alpha/n_{j+1}) u - (beta_{j+1}/n_j) up, partial ||un||^2;
+// alpha is summed from the stencil partials as in k_b_lanczos_minres.
+template <class SV>
+__global__ void __launch_bounds__(kBlock)
+k_b_lanczos_w(Seg g, double* st, const SV* u, const SV* up, const SV* w, SV* un, const int* __restrict__ active,
+              const double* __restrict__ apart, int anp, double* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  double acc = 0.0;
+  __shared__ double lds[kBlock / 64];
+  if (!active || active[rhs]) {
+    __shared__ double alpha_s;
+    const double asum = b_fin_sum(apart + (long)rhs * anp, anp, lds);
+    if (threadIdx.x == 0) {
+      alpha_s = asum;
+      if (blockIdx.x == 0) st[rhs * NS + B_ALPHA] = asum;
+    }
+    __syncthreads();
+    const double* S = st + rhs * NS;
+    const float a = (float)(alpha_s / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
+    const long off = seg_off(g, rhs), n = seg_len(g, rhs);
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+      float2 t = c_axpy(-a, sld(u + off + i), sld(w + off + i));
+      t = c_axpy(-b, sld(up + off + i), t);
+      sst(un + off + i, t);
+      acc = fma((double)t.x, (double)t.x, fma((double)t.y, (double)t.y, acc));
+    }
+  }
+  __syncthreads();  // lds is reused
+  const double s = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) part[(long)rhs * gridDim.x + blockIdx.x] = s;
+}
+
+// Coefficients of a window, one block per rhs.  Over the basis B = (d_{J-1}, d_J, u_{J+1},
+// ..., u_{J+L}) (J = B_WSTART, L = B_WCNT recorded rotations), the search directions
+// d_j = (u_j / n_j - delta_j d_{j-1} - eps_j d_{j-2}) / gamma_j are carried as coefficient
+// vectors in FP64, thread b holding component b.  Out, per rhs (stride 2 + 3 (W + 2)): J, L,
+// then the coefficients of sum_j tau_j d_j, of d_{J+L} and of d_{J+L-1}.  The window is then
+// closed: B_WSTART += L, B_WCNT = 0.
+__global__ void __launch_bounds__(128)
+k_b_wcoef(double* st, const double* coef, int W, double* out, const int* __restrict__ active) {
+  const int r = blockIdx.x;
+  if (active && !active[r]) return;
+  double* S = st + r * NS;
+  const int L = (int)S[B_WCNT];
+  const double J = S[B_WSTART];
+  __syncthreads();
+  const int b = threadIdx.x;
+  const long stride = 2 + 3L * (W + 2);
+  double* o = out + r * stride;
+  if (b < W + 2) {
+    double dm2 = b == 0 ? 1.0 : 0.0, dm1 = b == 1 ? 1.0 : 0.0, cx = 0.0;
+    for (int i = 1; i <= L; ++i) {
+      const double* c = coef + ((long)r * W + i - 1) * 5;
+      double d = (b == 1 + i ? 1.0 / c[4] : 0.0) - c[1] * dm1 - c[2] * dm2;
+      d /= c[3];
+      cx = fma(c[0], d, cx);
+      dm2 = dm1;
+      dm1 = d;
+    }
+    o[2 + b] = cx;
+    o[2 + (W + 2) + b] = dm1;
+    o[2 + 2 * (W + 2) + b] = dm2;
+  }
+  if (b == 0) {
+    o[0] = J;
+    o[1] = L;
+    S[B_WSTART] = J + L;
+    S[B_WCNT] = 0.0;
+  }
+}
+
+// The window's pass: e += sum_j tau_j d_j, d1 = d_{J+L}, d2 = d_{J+L-1} over the basis of
+// k_b_wcoef (d1, d2 hold d_J, d_{J-1} on entry; each element is read and written by one
+// thread, so the update is in place).  ring: R slots of `stride` elements.
+template <class SV>
+__global__ void __launch_bounds__(kBlock)
+k_b_wflush(Seg g, const SV* ring, long stride, int R, const double* cf, int W, SV* d1, SV* d2, SV* e,
+           const int* __restrict__ active) {
+  constexpr int kMaxB = 130;
+  const int rhs = blockIdx.y;
+  if (active && !active[rhs]) return;
+  const double* o = cf + rhs * (2 + 3L * (W + 2));
+  const long J = (long)o[0];
+  const int L = (int)o[1];
+  if (L == 0) return;
+  __shared__ float cx[kMaxB], c1[kMaxB], c2[kMaxB];
+  __shared__ long so[kMaxB];
+  for (int b = threadIdx.x; b < L + 2; b += kBlock) {
+    cx[b] = (float)o[2 + b];
+    c1[b] = (float)o[2 + (W + 2) + b];
+    c2[b] = (float)o[2 + 2 * (W + 2) + b];
+    so[b] = b >= 2 ? ((J + b - 1) % R) * stride : 0;
+  }
+  __syncthreads();
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    const float2 p2 = sld(d2 + off + i), p1 = sld(d1 + off + i);
+    float2 x = c_axpy(cx[1], p1, c_axpy(cx[0], p2, sld(e + off + i)));
+    float2 n1 = c_axpy(c1[1], p1, c_scale(p2, c1[0]));
+    float2 n2 = c_axpy(c2[1], p1, c_scale(p2, c2[0]));
+#pragma unroll 4
+    for (int b = 2; b < L + 2; ++b) {
+      const float2 v = sld(ring + so[b] + off + i);
+      x = c_axpy(cx[b], v, x);
+      n1 = c_axpy(c1[b], v, n1);
+      n2 = c_axpy(c2[b], v, n2);
+    }
+    sst(e + off + i, x);
+    sst(d1 + off + i, n1);
+    sst(d2 + off + i, n2);
+  }
 }
 
 // x64 += e (FP32 correction)
@@ -789,6 +931,12 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
     else f[q].alloc((size_t)bt.total);
   }
   DBuf<double2> cbuf(2 * (size_t)nrmax * kmax + 2);
+  // windowed MinRes (without graph capture): the ring of Lanczos vectors (W + 2 fields per
+  // rhs; W from 64 down to 8 while the ring exceeds 24 GiB), the recorded rotations and the
+  // window coefficients
+  DBuf<float2> ring32;
+  DBuf<bf2> ring16;
+  DBuf<double> wrot((size_t)nr * kMaxWindow * 5), wcf((size_t)nr * (2 + 3 * (kMaxWindow + 2)));
   std::vector<long> iters(nr, 0), mvp(nr, 0);
   std::vector<double> bnorm(nr), rel(nr, 1.0), tol(nr);
   for (int r = 0; r < nr; ++r) tol[r] = items[bt.item_of[r]].tol;
@@ -919,8 +1067,46 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
     using SV = std::remove_pointer_t<decltype(f0)>;
     if (mr) {
       SV *u = f0, *up = f1, *w = f2, *d1 = f3, *d2 = f4, *e = f5;
-      hipLaunchKernelGGL((k_b_minres_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), u, up, d1, d2, e,
-                         bt.st.get(), bt.invs.get(), bt.active.get());
+      // Without graph capture the MinRes runs windowed (Lanczos vectors kept in a ring, the
+      // solution formed every W iterations); graphs replay the fused form, whose launch
+      // sequence repeats every two iterations.
+      const bool windowed = !use_graph && o.minres_window >= 0;
+      int W = o.minres_window > 0 ? std::min(o.minres_window, kMaxWindow) : kMaxWindow;
+      SV* ring = nullptr;
+      if (windowed) {
+        if (o.minres_window == 0)
+          while (W > 8 && (size_t)(W + 2) * bt.total * sizeof(SV) > (size_t(24) << 30)) W /= 2;
+        const size_t need = (size_t)(W + 2) * bt.total;
+        if constexpr (std::is_same_v<SV, bf2>) {
+          if (ring16.n != need) ring16.alloc(need);
+          ring = ring16.get();
+        } else {
+          if (ring32.n != need) ring32.alloc(need);
+          ring = ring32.get();
+        }
+      }
+      const int R = W + 2;
+      auto slot = [&](long j) { return ring + (j % R) * (long)bt.total; };
+      hipLaunchKernelGGL((k_b_minres_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(),
+                         windowed ? slot(1) : u, windowed ? slot(0) : up, d1, d2, e, bt.st.get(), bt.invs.get(),
+                         bt.active.get());
+      auto flush = [&]() {
+        hipLaunchKernelGGL(k_b_wcoef, dim3(nr), dim3(128), 0, s, bt.st.get(), wrot.get(), W, wcf.get(),
+                           bt.active.get());
+        hipLaunchKernelGGL((k_b_wflush<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, ring, (long)bt.total, R,
+                           wcf.get(), W, d1, d2, e, bt.active.get());
+      };
+      long wit = 0;  // iterations of this cycle (windowed form)
+      auto iteration_w = [&]() {
+        SV* uc = slot(wit + 1);
+        const int nbs = bwilson_lo(bt, 2, uc, w, 2, bt.part.get(), bt.invs.get());
+        hipLaunchKernelGGL((k_b_lanczos_w<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), uc, slot(wit), w,
+                           slot(wit + 2), bt.active.get(), bt.part.get(), nbs, bt.part2.get());
+        hipLaunchKernelGGL(k_b_fin_rot, dim3(nr), dim3(kBlock), 0, s, bt.part2.get(), G, bt.st.get(), bt.invs.get(),
+                           bt.active.get(), wrot.get(), W);
+        DL_HIP(hipGetLastError());
+        if (++wit % W == 0) flush();
+      };
       // one MinRes iteration; `check` (even) iterations return u, up, d1, d2 to their places,
       // so a block of them is the same launch sequence every time (replayed as a graph).  The
       // solution update of an iteration runs in the next iteration's Lanczos pass; an rhs stops
@@ -948,6 +1134,8 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       for (int it = 0; it < 100000; ++it) {
         if (use_graph) {
           if (it % check == 0) graphs.run(0, [&] { for (int q = 0; q < check; ++q) iteration(); });
+        } else if (windowed) {
+          iteration_w();
         } else {
           iteration();
         }
@@ -993,9 +1181,13 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       }
       bt.h_active = inner_active;
       bt.push_active();
-      // the last iteration's solution update (its rotation is still in the state)
-      hipLaunchKernelGGL((k_b_minres_update<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), up, d1, d2, d2, e,
-                         bt.active.get());
+      if (windowed) {
+        flush();  // every rhs's open window (rhs that stopped early keep theirs in the ring)
+      } else {
+        // the last iteration's solution update (its rotation is still in the state)
+        hipLaunchKernelGGL((k_b_minres_update<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), up, d1, d2, d2,
+                           e, bt.active.get());
+      }
       hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
     } else {
       SV *r32 = f0, *sv = f1, *p = f2, *q = f3, *e = f4;
@@ -1093,6 +1285,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
         h[q].release();
         f[q].alloc((size_t)bt.total);
       }
+      ring16.release();
       if (bt.single()) (void)wilson_cfg(items[0].op, DL_FP32, nr);
       graphs.clear();  // captured blocks name the BF16 buffers
       bf16 = false;

@@ -126,6 +126,7 @@ dl_next_opts next_defaults(const dl_next_opts* o, int kind) {
     d.eig_storage = o->eig_storage;
     d.net_prec = o->net_prec;
     d.method = o->method;
+    d.minres_window = o->minres_window;
   }
   if (d.net_prec == 0) d.net_prec = DL_FP32;
   // Per-cycle residual drop of the batched inner solve and the D-CG reliable-update interval.
@@ -375,6 +376,7 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     need(o.method == DL_METHOD_DEFAULT || o.method == DL_METHOD_CG, "method must be DL_METHOD_DEFAULT or DL_METHOD_CG");
     need(o.method == DL_METHOD_DEFAULT || !o.batched, "method DL_METHOD_CG runs on the FP64 one-rhs path (batched = 0)");
     need(!(o.net && o.x0_given), "x0_given and a learned initial guess exclude each other");
+    need(o.minres_window <= 64, "minres_window must be at most 64");
     if (o.net) check_net_op(o.net, op);
     use_device(op->ctx);
     if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
@@ -448,6 +450,7 @@ int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int
          "the multi-lattice batch runs the batched path (DL_FP32 or DL_BF16, batched = 1)");
     need(o.inner_drop > 0.0 && o.inner_drop < 1.0, "inner_drop must be in (0, 1)");
     need(!o.net, "the learned initial guess takes one operator per batch (dl_solve_next)");
+    need(o.minres_window <= 64, "minres_window must be at most 64");
     need(o.eig_storage == DL_FP64 || o.eig_storage == DL_FP32 || o.eig_storage == DL_BF16,
          "eig_storage must be DL_FP64, DL_FP32 or DL_BF16");
     use_device(ctx);

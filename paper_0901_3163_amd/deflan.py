@@ -41,7 +41,8 @@ class dl_first_opts(C.Structure):
 class dl_next_opts(C.Structure):
     _fields_ = [("storage", C.c_int), ("reliable_every", C.c_int), ("batched", C.c_int),
                 ("x0_given", C.c_int), ("max_mvp", C.c_long), ("net", C.c_void_p), ("graph", C.c_int),
-                ("inner_drop", C.c_double), ("eig_storage", C.c_int), ("net_prec", C.c_int), ("method", C.c_int)]
+                ("inner_drop", C.c_double), ("eig_storage", C.c_int), ("net_prec", C.c_int), ("method", C.c_int),
+                ("minres_window", C.c_int)]
 
 
 class dl_batch_item(C.Structure):
@@ -297,13 +298,14 @@ class Operator:
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
                    reliable_every=None, net=None, graph=False, inner_drop=None, eig_storage=DL_FP64,
-                   net_prec=DL_FP32, method=0):
+                   net_prec=DL_FP32, method=0, minres_window=0):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
         o = dl_next_opts(int(storage), int(reliable_every or 0), int(batched), 1 if x0 is not None else 0,
                          int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0,
-                         float(inner_drop or 0.0), int(eig_storage), int(net_prec), int(method))
+                         float(inner_drop or 0.0), int(eig_storage), int(net_prec), int(method),
+                         int(minres_window))
         st = (dl_stats * max(nrhs, 1))()
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
@@ -419,7 +421,7 @@ def num_weights() -> int:
 
 
 def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s=None, graph=False,
-                     storage=DL_FP32, inner_drop=None, eig_storage=DL_FP64):
+                     storage=DL_FP32, inner_drop=None, eig_storage=DL_FP64, minres_window=0):
     """Later right-hand sides of several operators in one batched solve.
 
     items: sequence of (op, eig or None, B [nrhs][V][4][3], tol); all B numpy (host) or all
@@ -439,7 +441,8 @@ def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s
         keep.append(B)
         Xs.append(X)
     o = dl_next_opts(int(storage), int(reliable_every or 0), 1, 1 if x0s is not None else 0, int(max_mvp or 0), None,
-                     1 if graph else 0, float(inner_drop or 0.0), int(eig_storage), DL_FP32, 0)
+                     1 if graph else 0, float(inner_drop or 0.0), int(eig_storage), DL_FP32, 0,
+                     int(minres_window))
     ntot = sum(int(B.shape[0]) for B in keep)
     st = (dl_stats * max(ntot, 1))()
     rc = _check(lib.dl_solve_next_multi(ctx.h, len(items), its, mem if mem is not None else DL_HOST, C.byref(o), st))

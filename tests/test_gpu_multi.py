@@ -92,14 +92,16 @@ def test_graph_replay_matches_eager(gpu_ctx, c1_config, kind):
     """Inner iteration blocks replayed as HIP graphs (dozens of replays per solve, each followed
     by the solver's own host synchronisation and mask update) give bitwise the eager results,
     for one operator and for a two-lattice batch; reliable updates every 16 iterations fall on
-    the same iterations in both modes."""
+    the same iterations in both modes.  Graphs replay the fused MinRes form, so the eager
+    MinRes runs in that form too (minres_window < 0)."""
     from paper_0901_3163_amd import deflan
     k = deflan.DL_G5M if kind == "g5m" else deflan.DL_MDAGM
     c1 = c1_config
     op = deflan.Operator(gpu_ctx, c1["dims"], c1["links"], c1["kappa"], k)
     _, eig, _ = op.solve_first(gaussian_spinor(c1["dims"], 100), 60, 20, 1e-10)
     B = np.stack([gaussian_spinor(c1["dims"], 300 + i) for i in range(3)] + [point_source(c1["dims"], 0, 2, 2)])
-    Xe, ste, rce = op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1, reliable_every=16)
+    Xe, ste, rce = op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1, reliable_every=16,
+                                 minres_window=-1)
     for rep in range(2):
         Xg, stg, rcg = op.solve_next(B, eig, 1e-10, storage=deflan.DL_FP32, batched=1, reliable_every=16,
                                      graph=True)
@@ -111,7 +113,7 @@ def test_graph_replay_matches_eager(gpu_ctx, c1_config, kind):
     op2 = deflan.Operator(gpu_ctx, d2, su3_links(d2, 8), 0.13, k)
     B2 = np.stack([gaussian_spinor(d2, 310 + i) for i in range(2)])
     items = [(op, eig, B, 1e-10), (op2, None, B2, 1e-10)]
-    Xm, sm, rcm = deflan.solve_next_multi(gpu_ctx, items, reliable_every=16)
+    Xm, sm, rcm = deflan.solve_next_multi(gpu_ctx, items, reliable_every=16, minres_window=-1)
     Xmg, smg, rcmg = deflan.solve_next_multi(gpu_ctx, items, reliable_every=16, graph=True)
     assert rcm == rcmg == deflan.DL_OK
     for j in range(2):
@@ -122,3 +124,37 @@ def test_graph_replay_matches_eager(gpu_ctx, c1_config, kind):
     eig.close()
     op.close()
     op2.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_windowed_minres_matches_fused(gpu_ctx, c1_config, storage):
+    """The windowed batched D-MinRes (Lanczos vectors in a ring, the solution formed once per
+    window) against the fused short-recurrence form, for windows of 1, 3, 8 and 64 iterations
+    and the default: rhs that converge at different iterations close their partial windows at
+    the cycle end; the iterates agree up to rounding, so every rhs takes the same number of
+    iterations within a few and reaches the dense solution.  A window above 64 is refused."""
+    from paper_0901_3163_amd import deflan
+    c1 = c1_config
+    st_code = deflan.DL_FP32 if storage == "fp32" else deflan.DL_BF16
+    op = deflan.Operator(gpu_ctx, c1["dims"], c1["links"], c1["kappa"], deflan.DL_G5M)
+    _, eig, _ = op.solve_first(gaussian_spinor(c1["dims"], 100), 60, 20, 1e-10)
+    B = np.stack([gaussian_spinor(c1["dims"], 320 + i) for i in range(3)] + [point_source(c1["dims"], 5, 1, 2),
+                                                                            np.zeros_like(gaussian_spinor(c1["dims"], 0))])
+    ora = dirac.WilsonOperator(c1["links"], c1["dims"], c1["kappa"])
+    M = dirac.dense(ora.M, ora.n)
+    Xf, sf, rcf = op.solve_next(B, eig, 1e-10, storage=st_code, batched=1, minres_window=-1)
+    assert rcf == deflan.DL_OK
+    for win in (1, 3, 8, 64, 0):
+        X, sw, rc = op.solve_next(B, eig, 1e-10, storage=st_code, batched=1, minres_window=win)
+        assert rc == deflan.DL_OK, win
+        assert np.all(X[4] == 0) and sw[4]["relres"] == 0.0
+        for i in range(4):
+            r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+            assert sw[i]["relres"] <= 1e-10 and r <= 1.0001e-10, (win, i, r)
+            assert np.linalg.norm(X[i].ravel() - np.linalg.solve(M, B[i].ravel())) <= 1e-6 * np.linalg.norm(X[i])
+            assert abs(sw[i]["iters"] - sf[i]["iters"]) <= 0.05 * sf[i]["iters"] + 16, (win, i, sw[i]["iters"],
+                                                                                         sf[i]["iters"])
+    with pytest.raises(deflan.DeflanError):
+        op.solve_next(B, eig, 1e-10, storage=st_code, batched=1, minres_window=65)
+    eig.close()
+    op.close()
