@@ -304,7 +304,22 @@ k_b_lanczos_w(Seg g, double* st, const SV* u, const SV* up, const SV* w, SV* un,
     const double* S = st + rhs * NS;
     const float a = (float)(alpha_s / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
     const long off = seg_off(g, rhs), n = seg_len(g, rhs);
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    // four elements per thread and step (fields are whole 64-site tiles: n and off are
+    // multiples of 768 elements), one 16-byte (BF16) or two (FP32) accesses per field
+    const long n4 = n >> 2;
+    for (long q = (long)blockIdx.x * kBlock + threadIdx.x; q < n4; q += (long)gridDim.x * kBlock) {
+      float2 vu[4], vw[4], vp[4];
+      sld4(u + off + 4 * q, vu);
+      sld4(w + off + 4 * q, vw);
+      sld4(up + off + 4 * q, vp);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        vw[k] = c_axpy(-b, vp[k], c_axpy(-a, vu[k], vw[k]));
+        acc = fma((double)vw[k].x, (double)vw[k].x, fma((double)vw[k].y, (double)vw[k].y, acc));
+      }
+      sst4(un + off + 4 * q, vw);
+    }
+    for (long i = 4 * n4 + (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
       float2 t = c_axpy(-a, sld(u + off + i), sld(w + off + i));
       t = c_axpy(-b, sld(up + off + i), t);
       sst(un + off + i, t);

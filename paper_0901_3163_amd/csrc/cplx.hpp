@@ -88,6 +88,37 @@ __device__ __forceinline__ void sst(bf2* p, float2 v) {
   *reinterpret_cast<unsigned*>(p) = __builtin_bit_cast(unsigned, __builtin_convertvector(f, bf16x2_st));
 }
 
+// Four consecutive storage elements (16 B of BF16, 32 B of FP32; the address a multiple of
+// four elements) widened to / rounded from FP32.
+__device__ __forceinline__ void sld4(const float2* p, float2* o) {
+  const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+  o[0] = make_float2(a.x, a.y);
+  o[1] = make_float2(a.z, a.w);
+  o[2] = make_float2(b.x, b.y);
+  o[3] = make_float2(b.z, b.w);
+}
+__device__ __forceinline__ float2 bf_word(unsigned w) {
+  return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u));
+}
+__device__ __forceinline__ void sld4(const bf2* p, float2* o) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  o[0] = bf_word(u.x);
+  o[1] = bf_word(u.y);
+  o[2] = bf_word(u.z);
+  o[3] = bf_word(u.w);
+}
+__device__ __forceinline__ void sst4(float2* p, const float2* v) {
+  reinterpret_cast<float4*>(p)[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+  reinterpret_cast<float4*>(p)[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+}
+__device__ __forceinline__ unsigned bf_pack(float2 v) {
+  const f32x2_st f = {v.x, v.y};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f, bf16x2_st));
+}
+__device__ __forceinline__ void sst4(bf2* p, const float2* v) {
+  *reinterpret_cast<uint4*>(p) = make_uint4(bf_pack(v[0]), bf_pack(v[1]), bf_pack(v[2]), bf_pack(v[3]));
+}
+
 template <class R> struct CT;
 template <> struct CT<double> {
   using type = double2;
