@@ -124,7 +124,9 @@ typedef struct {
                                true residual ||b - M x0|| (costs one extra projection per rhs) */
   int    graph;             /* batched path: 1 = replay each block of 8 inner iterations as a
                                captured HIP graph (fewer launches for small lattices); ignored
-                               while kernel timing (dl_timing) is on.  Default 0. */
+                               while kernel timing (dl_timing) is on.  Default 0.  D-MinRes
+                               then runs its fused form (see minres_window), which moves more
+                               data per iteration: on large lattices graph replay is slower. */
   double inner_drop;        /* batched path: residual reduction that ends an inner cycle (then
                                FP64 residual, projection, restart); 0 = default: 1e-4 with DL_FP32
                                storage; with DL_BF16 (whose rounding limits one cycle) 1e-2 for
