@@ -42,3 +42,34 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert rc == deflan.DL_E_INVALID
     rc = deflan.lib.dl_solve_next(None, None, 0, None, None, 0, 1e-10, None, None)
     assert rc == deflan.DL_E_INVALID  # op is NULL
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every option / statistics struct of the binding has the size and field offsets that a
+    C compiler gives the header's declaration (a field added on one side only fails here)."""
+    import shutil
+    import subprocess
+    import pytest
+    from paper_0901_3163_amd import deflan
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [deflan.dl_first_opts, deflan.dl_next_opts, deflan.dl_stats, deflan.dl_batch_item]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "deflan.h"', "int main(void) {"]
+    for s in structs:
+        n = s.__name__
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for f, _ in s._fields_:
+            lines.append(f'  printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                         text=True).stdout.splitlines())
+    for s in structs:
+        n = s.__name__
+        assert int(got[f"{n} size"]) == ctypes.sizeof(s), n
+        for f, _ in s._fields_:
+            assert int(got[f"{n} {f}"]) == getattr(s, f).offset, (n, f)
