@@ -163,3 +163,27 @@ def test_batched_cg_reliable_updates(gpu_ctx, c1_config):
     assert its[50] <= 1.25 * its[-1] and its[10] <= 1.5 * its[-1], its
     eig.close()
     op.close()
+
+
+@pytest.mark.parametrize("kind", ["g5m", "mdagm"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_bf16_stall_moves_batch_to_fp32(gpu_ctx, c1_config, kind, graph):
+    """A cycle drop of 1e-5 is beyond what BF16 Krylov vectors reach on the near-critical 4^4
+    field without deflation: the BF16 cycle stalls (no 10% new low of its residual for 200
+    iterations), the batch continues with FP32 storage (captured graphs dropped and captured
+    again for the FP32 buffers), and every rhs still reaches tol and the dense solution."""
+    from paper_0901_3163_amd import deflan
+    dims, U, kappa = c1_config["dims"], c1_config["links"], c1_config["kappa"]
+    k = deflan.DL_G5M if kind == "g5m" else deflan.DL_MDAGM
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, k)
+    B = np.stack([gaussian_spinor(dims, 330 + i) for i in range(2)] + [point_source(dims, 3, 0, 1)])
+    X, sts, rc = op.solve_next(B, None, 1e-10, storage=deflan.DL_BF16, batched=1, inner_drop=1e-5, graph=graph)
+    assert rc == deflan.DL_OK
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    M = dirac.dense(ora.M, ora.n)
+    for i in range(len(B)):
+        r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+        assert sts[i]["relres"] <= 1e-10 and r <= 1.0001e-10, (i, r)
+        assert _rel(X[i], np.linalg.solve(M, B[i].ravel())) < 1e-6
+        assert sts[i]["iters"] > 200  # at least the stalled BF16 stretch
+    op.close()
