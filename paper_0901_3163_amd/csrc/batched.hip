@@ -15,7 +15,9 @@
 // eigenvectors at every restart.  The inner MinRes / CG runs on the
 // correction e with A e = gamma5 r64 (MinRes) or M e = r64 (CG on the normal
 // equations), and x64 += e closes each cycle.  The batched CG instead keeps its
-// search direction across FP64 reliable updates (x64 += e, r = b - M x64).
+// search direction across FP64 reliable updates (x64 += e, r = b - M x64).  The batched
+// MinRes keeps a cycle's Lanczos vectors in a ring and adds their share of e once per
+// window of iterations (graph replay runs the fused short-recurrence form instead).
 //
 // A batch may hold several operators (lattices of different sizes): field j of the
 // batch then starts at offs[j] and has length lens[j] (Seg), the stencil runs as one
