@@ -629,6 +629,45 @@ def net_only(args):
     ctx.close()
 
 
+def window_sweep(args):
+    """The batched D-MinRes of the benchmark workload in its fused short-recurrence form
+    (minres_window < 0) and windowed with W = 8, 16, 32, 64: BF16 storage with the
+    BF16-contracted projection, and FP32 storage with FP64 eigenvectors; projection-only
+    starts, reps timed solves of the 12 point sources each.  Prints one JSON line."""
+    import torch
+    from lattice_inputs import gaussian_spinor, su3_links
+    from paper_0901_3163_amd import deflan
+    e = kappa_for("16x16x16x32")
+    dims = tuple(e["dims"])
+    ctx = deflan.Context(0)
+    op = deflan.Operator(ctx, dims, torch.from_numpy(su3_links(dims, e["seed"], e["eps"])).cuda(), e["kappa"],
+                         deflan.DL_G5M)
+    _, eig, _ = op.solve_first(torch.from_numpy(gaussian_spinor(dims, 200)).cuda(), args.m, args.k, args.tol)
+    eig.lower(deflan.DL_BF16)
+    B = torch.from_numpy(point_sources(dims)).cuda()
+    out = dict(workload=f"16^3x32 Wilson near-critical (kappa {e['kappa']:.7f}), 12 point sources, tol {args.tol:g}",
+               reps=args.reps, runs={})
+    for name, stg, est in (("bf16", deflan.DL_BF16, deflan.DL_BF16), ("fp32", deflan.DL_FP32, deflan.DL_FP64)):
+        for win in (-1, 8, 16, 32, 64):
+            kw = dict(storage=stg, batched=1, eig_storage=est, minres_window=win)
+            op.solve_next(B, eig, args.tol, **kw)  # warm-up (tuning)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            for _ in range(args.reps):
+                _, sts, rc = op.solve_next(B, eig, args.tol, **kw)
+            torch.cuda.synchronize()
+            dt = (time.time() - t0) / args.reps
+            key = f"{name}/{'fused' if win < 0 else f'W{win}'}"
+            out["runs"][key] = dict(value=round(12 / dt, 2), unit="RHS/s",
+                                    iters_per_rhs=round(float(np.mean([s["iters"] for s in sts])), 1),
+                                    max_relres=max(s["relres"] for s in sts), rc=rc)
+            log(f"window sweep {key}: {12 / dt:.2f} RHS/s, {out['runs'][key]['iters_per_rhs']} iterations per rhs")
+    print(json.dumps(out))
+    eig.close()
+    op.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -668,6 +707,8 @@ def main():
     ap.add_argument("--net-only", action="store_true", help="run only the network's forward pass (profiling)")
     ap.add_argument("--learned", action="store_true",
                     help="the learned-guess study across training and held-out fields instead (own JSON line)")
+    ap.add_argument("--window-sweep", action="store_true",
+                    help="the D-MinRes window sweep on the benchmark workload instead (own JSON line)")
     ap.add_argument("--learned-pairs", type=int, default=256)
     ap.add_argument("--learned-test", type=int, default=64)
     ap.add_argument("--learned-epochs", type=int, default=2)
@@ -692,6 +733,8 @@ def main():
         return net_only(args)
     if args.ksweep:
         return ksweep_study(args)
+    if args.window_sweep:
+        return window_sweep(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
