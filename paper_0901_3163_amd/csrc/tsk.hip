@@ -320,6 +320,9 @@ static void update_multi(hipStream_t s, long n, int nv, const VB* base, long ld,
     else if (nw <= 8)
       hipLaunchKernelGGL((k_tsk_update_multi<8, VB>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active,
                          X, ldx);
+    else if (nw <= 12)  // the 12 spin-colour sources: no FP64 work on padding columns
+      hipLaunchKernelGGL((k_tsk_update_multi<12, VB>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active,
+                         X, ldx);
     else
       hipLaunchKernelGGL((k_tsk_update_multi<16, VB>), dim3(nb), dim3(kBlock), 0, s, n, nc, b, ld, d, nv, nw, active,
                          X, ldx);

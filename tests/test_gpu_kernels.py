@@ -179,8 +179,8 @@ def test_multi_rhs_apply_every_variant(gpu_ctx, dims, monkeypatch):
     op.close()
 
 
-@pytest.mark.parametrize("n,nv,nw", [(1000, 1, 1), (3072, 61, 12), (100003, 130, 16), (1572864, 60, 12),
-                                     (8000000, 8, 3)])
+@pytest.mark.parametrize("n,nv,nw", [(1000, 1, 1), (3072, 61, 12), (5000, 7, 9), (100003, 130, 16),
+                                     (1572864, 60, 12), (8000000, 8, 3)])
 def test_tsk_project_multi(gpu_ctx, n, nv, nw):
     """C = V^H W for several columns at once and X += V C^T, against numpy (FP64, 1e-12).
 
