@@ -73,3 +73,19 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got[f"{n} size"]) == ctypes.sizeof(s), n
         for f, _ in s._fields_:
             assert int(got[f"{n} {f}"]) == getattr(s, f).offset, (n, f)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The package copied without libdeflan.so cannot be imported: there is no CPU fallback."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_0901_3163_amd"
+    pkg.mkdir()
+    src = os.path.join(ROOT, "paper_0901_3163_amd")
+    for f in ("__init__.py", "deflan.py"):
+        shutil.copy(os.path.join(src, f), pkg / f)
+    p = subprocess.run([sys.executable, "-c", "import paper_0901_3163_amd"], cwd=tmp_path, capture_output=True,
+                       text=True, timeout=120, env=dict(os.environ, PYTHONPATH=str(tmp_path)))
+    assert p.returncode != 0
+    assert "ImportError" in p.stderr and "libdeflan.so is missing" in p.stderr
