@@ -869,7 +869,8 @@ def main():
                                        f"{args.k}) on gamma5 M then D-MinRes on 12 point sources, tol "
                                        f"{args.tol:g}", lattice=list(dims), kappa=kappa, nrhs=nrhs,
                               m=args.m, k=args.k,
-                              path=(f"batched D-MinRes, {args.storage.upper()} Krylov vectors and Wilson apply "
+                              path=("batched D-MinRes (windowed: Lanczos vectors in a ring, solution formed "
+                                    f"every 64 iterations), {args.storage.upper()} Krylov vectors and Wilson apply "
                                     "(FP32 arithmetic and links), FP64 residuals and solution, projection over "
                                     + {"fp64": "FP64 eigenvectors",
                                        "fp32": "FP32 eigenvectors (matrix-core contraction)",
