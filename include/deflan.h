@@ -178,8 +178,14 @@ int dl_version(void);
 
 /* ---- context ------------------------------------------------------------ */
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
- * enqueue on (NULL: the library creates its own stream). */
+ * enqueue on (NULL: the library creates its own stream).
+ * Device memory: the library keeps the device buffers it frees (solver work
+ * fields, handles closed) in a per-device cache and reuses them for requests of
+ * the same rounded size, holding at most an eighth of the device's memory; a
+ * failed allocation releases the cache and retries once. */
 int  dl_ctx_create(int device, void* hip_stream, dl_ctx** out);
+/* Wait for the context's stream, release the context, and return the device's
+ * cached buffers to HIP (buffers of live operators and handles stay theirs). */
 void dl_ctx_destroy(dl_ctx* ctx);
 /* Block until all work queued by the library on the context's stream is done. */
 int  dl_ctx_sync(dl_ctx* ctx);
