@@ -31,6 +31,11 @@ last paragraph) times the count at linear convergence.  ||A||_est is the largest
 infinity norm of the projected matrices T_m seen so far (a bound on ||A||
 within the Krylov space); every cycle ends with a check of the true residual
 that costs ``res_mvp`` MVPs (one application of M for the Wilson systems).
+The solution returned is the cycle-end iterate with the smallest true residual:
+once the linear system has met tol the further cycles serve the eigenvectors
+(Section 2, last paragraph), and at the FP64 residual floor (near 1e-11 for the
+normal equations of a near-critical lattice) their corrections can move the
+residual up or down by small factors.
 """
 from __future__ import annotations
 
@@ -133,6 +138,7 @@ def lan_dr(A, bA, m, k, tol, residual=None, eig_tol=1e-12, past_conv_factor=2.0,
     stop = _Stopper(tol, k, eig_tol, past_conv_factor, max_mvp)
     hist, cycles = [], 0
     anorm = 0.0
+    best = (np.inf, x)
     while True:
         mm, mvp, brk = _lanczos_extend(A, V, Tb, j0, m, apv, mvp, 1e-14 * max(anorm, 1e-300) if anorm else 0.0)
         Tm = Tb[:mm, :mm]
@@ -148,6 +154,8 @@ def lan_dr(A, bA, m, k, tol, residual=None, eig_tol=1e-12, past_conv_factor=2.0,
         mvp += res_mvp
         hist.append(relres)
         cycles += 1
+        if relres < best[0]:
+            best = (relres, x.copy())
         if brk or stop.done(relres, rho, anorm, mvp):
             break
         # thick restart: V_k <- V_m G_k, v_{k+1} <- v_{m+1}; arrowhead T-bar
@@ -163,8 +171,8 @@ def lan_dr(A, bA, m, k, tol, residual=None, eig_tol=1e-12, past_conv_factor=2.0,
         j0 = k
     vecs = V[:, :mm] @ G[:, keep]
     eig = dict(vals=theta[keep].copy(), vecs=vecs, rho=rho)
-    return x, eig, dict(mvp=mvp, cycles=cycles, relres=hist[-1], history=hist,
-                        rule=stop.rule if not brk else "breakdown", mvp_lin=stop.mvp_lin)
+    return best[1], eig, dict(mvp=mvp, cycles=cycles, relres=best[0], history=hist,
+                              rule=stop.rule if not brk else "breakdown", mvp_lin=stop.mvp_lin)
 
 
 def _harmonic_ritz(Tb):
@@ -210,6 +218,7 @@ def minres_dr(A, bA, m, k, tol, residual=None, eig_tol=1e-12, past_conv_factor=2
     S = np.zeros((0, 0))
     lam = np.zeros(0)
     rho = np.zeros(0)
+    best = (np.inf, x)
     while True:
         mm, mvp, brk = _lanczos_extend(A, V, Tb, j0, m, apv, mvp, 1e-14 * anorm if anorm else 0.0)
         if brk:  # invariant subspace: the square problem is exact
@@ -247,6 +256,8 @@ def minres_dr(A, bA, m, k, tol, residual=None, eig_tol=1e-12, past_conv_factor=2
         mvp += res_mvp
         hist.append(relres)
         cycles += 1
+        if relres < best[0]:
+            best = (relres, x.copy())
         # restart: V_{k+1} <- V_{m+1} Q, Tbar <- Q^H Tbar Q, c <- Q^H s
         V = np.concatenate([V @ Q, np.zeros((n, m - k), dtype=np.complex128)], axis=1)
         Tb = np.zeros((m + 1, m))
@@ -258,8 +269,8 @@ def minres_dr(A, bA, m, k, tol, residual=None, eig_tol=1e-12, past_conv_factor=2
             break
     vecs = V[:, :k] @ S
     eig = dict(vals=lam, vecs=vecs, rho=rho, harmonic=theta[keep].copy())
-    return x, eig, dict(mvp=mvp, cycles=cycles, relres=hist[-1], history=hist, rule=stop.rule,
-                        mvp_lin=stop.mvp_lin)
+    return best[1], eig, dict(mvp=mvp, cycles=cycles, relres=best[0], history=hist, rule=stop.rule,
+                              mvp_lin=stop.mvp_lin)
 
 
 # --------------------------------------------------------------------------

@@ -174,6 +174,10 @@ def main(argv=None):
         res["16x16x16x32"] = search_large((16, 16, 16, 32), 1e-4, log=lambda m: print(m, flush=True))
     if "precision" in argv:
         res["24x24x24x48"] = search_large((24, 24, 24, 48), 1e-3, log=lambda m: print(m, flush=True))
+    if "learned" in argv:
+        # the learned-guess workload: one kappa for every field, tuned on the first training field
+        res["16x16x16x32/seed10"] = search_large((16, 16, 16, 32), 1e-3, seed=10, k0=0.145, k1=0.1474,
+                                                 log=lambda m: print(m, flush=True))
     if "ksweep" in argv:
         res["20x20x20x32"] = search_large((20, 20, 20, 32), 1e-3, k0=0.145, k1=0.1474,
                                           log=lambda m: print(m, flush=True))
