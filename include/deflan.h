@@ -78,6 +78,15 @@ extern "C" {
 #define DL_APPLY_G5M   2
 #define DL_APPLY_MDAGM 3
 
+/* Re-orthogonalisation of the Lanczos vectors of the first right-hand side (dl_first_opts.reorth) */
+#define DL_REORTH_FULL 0   /* every step: classical Gram-Schmidt twice against the whole basis (default) */
+#define DL_REORTH_KEPT 1   /* the paper's policy (Section 2, last paragraph): each step orthogonalises
+                              against the two previous Lanczos vectors (twice), the first step after
+                              a restart against the whole basis, and every reorth_period steps the
+                              new vector is also orthogonalised (twice) against the vectors kept at
+                              the last restart.  Reads 2k instead of 2j fields per step (k kept, j the
+                              basis size), so it is cheaper for k well below m. */
+
 /* stop rules reported in dl_stats.stop_rule for dl_solve_first */
 #define DL_STOP_LINEAR     0  /* k = 0: stopped at linear convergence */
 #define DL_STOP_EIGEN      1  /* every kept eigen-residual <= eig_tol * ||A||_est */
@@ -96,6 +105,12 @@ typedef struct {
   double past_conv_factor;  /* run past linear convergence up to this MVP factor; default 2.0
                                (the paper: "at most a factor of two in MVPs", Section 2) */
   long   max_mvp;           /* hard cap on MVPs; default 1000000 */
+  int    reorth;            /* DL_REORTH_FULL (0, default) or DL_REORTH_KEPT */
+  int    reorth_period;     /* DL_REORTH_KEPT: steps between orthogonalisations against the kept
+                               vectors; 0 = default 1.  On the near-critical 4^4 lattice and the
+                               indefinite diagonal example of Section 1 a period of 2 or more
+                               already lets the kept eigenvectors lose orthogonality (MinRes-DR)
+                               or the recurrence diverge (Lan-DR, period 4), so 1 is the default. */
 } dl_first_opts;
 
 /* Options for later right-hand sides.  Pass NULL for the defaults. */
@@ -168,6 +183,21 @@ typedef struct {
   long   iters;             /* Krylov iterations */
   double relres;            /* true ||b - M x|| / ||b||, recomputed in FP64 at return */
   double time_s;            /* wall time of the call */
+  /* Residual history (the paper's plots of residual norm against MVPs, Figs. 2 and 4-7).
+   * INPUT fields, read before the call writes the struct: history points to caller memory of
+   * history_cap (mvp, relres) pairs, i.e. 2 * history_cap doubles (host memory), or is NULL
+   * (no history; history_cap is then ignored).  Set both to 0 in a fresh struct.  OUTPUT:
+   * history_len = pairs written (at most history_cap; later points are dropped).  Points:
+   *   dl_solve_first: the true residual at the end of every restart cycle;
+   *   dl_solve_next, one rhs at a time (FP64): the residual after the projection, then the
+   *     recurrence residual (CG) or |eta| (MinRes) of every iteration, and the true residual
+   *     that closes every inner run;
+   *   dl_solve_next batched / dl_solve_next_multi: the true residual at the start of every
+   *     inner cycle and the inner estimate at every host check (every 8 to 64 iterations).
+   * relres is relative to ||b||; mvp counts MVPs of that right-hand side so far. */
+  double* history;
+  int    history_cap;
+  int    history_len;
 } dl_stats;
 
 /* ---- library ----------------------------------------------------------- */
@@ -191,13 +221,15 @@ void dl_ctx_destroy(dl_ctx* ctx);
 int  dl_ctx_sync(dl_ctx* ctx);
 /* Kernel timing: when enabled, every launch of the kernel families below is
  * bracketed by HIP events on the context's stream and its duration summed.
- * name: "wilson" (every M / M^dag / gamma5 M launch in the precision used),
- * "tsk_dots" (V^H w), "tsk_update" (V c / V Y), "small" (one-workgroup FP64
- * problems).  dl_kernel_time returns launches, total milliseconds and (bytes
- * may be NULL) the algorithmic bytes those launches moved -- for "wilson" the
- * input spinors, links and output spinors counted once: 960 B/site in FP64,
- * 288 + 192 * nrhs B/site for an FP32 batch -- since the last reset
- * (dl_timing resets). */
+ * name: "wilson" (every M / M^dag / gamma5 M launch with FP32 or BF16 spinors),
+ * "wilson64" (every FP64 launch: the FP64 solvers, and the true residuals and
+ * projections of the batched path), "tsk_dots" (V^H w), "tsk_update" (V c / V Y),
+ * "small" (one-workgroup FP64 problems).  dl_kernel_time returns launches, total
+ * milliseconds and (bytes may be NULL) the algorithmic bytes those launches moved
+ * -- for the stencils the input spinors, links and output spinors counted once:
+ * 576 + 384 * nrhs B/site in FP64, 288 + 192 * nrhs (FP32 spinors) or 288 + 96 * nrhs
+ * (BF16 spinors) B/site with FP32 links, nrhs counting the active rhs of a launch --
+ * since the last reset (dl_timing resets). */
 int  dl_timing(dl_ctx* ctx, int enable);
 int  dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_ms, double* bytes);
 
@@ -211,6 +243,11 @@ int  dl_op_create(dl_ctx* ctx, const int dims[4], const double* links, int mem,
 void dl_op_destroy(dl_op* op);
 /* Number of complex entries N = 12 V of one spinor. */
 long dl_op_size(const dl_op* op);
+/* The operator's fingerprint: a hash of dims, kappa, kind and every link as stored on the
+ * device (so the same links give the same value whether they came from host or device
+ * memory, and a change of any one link changes it).  Eigenvector handles carry the
+ * fingerprint of the operator they were built for (DL_E_MISMATCH elsewhere). */
+int  dl_op_fingerprint(const dl_op* op, unsigned long long* out);
 
 /* out = op(in) with op one of DL_APPLY_* (FP64).  in/out are N complex each
  * and may not alias. */
@@ -304,6 +341,17 @@ int  dl_eig_vectors(const dl_eig* eig, double* V, int mem);
  * receives the MVPs used. */
 int  dl_eig_lower(dl_op* op, dl_eig* eig, int prec, long* mvp);
 void dl_eig_destroy(dl_eig* eig);
+/* Checkpoint of a handle (the point of the method, abstract: eigenvectors computed with the
+ * first right-hand side serve every later one, also in a later process).  dl_eig_save writes
+ * the k FP64 eigenvectors (interleaved complex128, [k][V][4][3]), the eigenvalues, residual
+ * norms, the eigendecomposition of H = Y^H A Y that the projection uses, and the operator's
+ * fingerprint, dims, kappa and kind, to the file `path` (created or truncated; about
+ * 16 * 12 * V * k bytes).  dl_eig_load reads such a file for op: DL_E_MISMATCH if it was saved
+ * for another operator (dims, kappa, kind or links differ), DL_E_INVALID if it is not a
+ * complete handle file.  The loaded handle equals the saved one bit for bit (a solve with it
+ * gives the same iterates); its lowered copies (dl_eig_lower) are not saved.  No MVPs. */
+int  dl_eig_save(const dl_eig* eig, const char* path);
+int  dl_eig_load(dl_op* op, const char* path, dl_eig** out);
 
 /* ---- learned initial guess ---------------------------------------------------
  * Not part of the paper's method: an optional starting vector for the later

@@ -255,7 +255,10 @@ k_b_lanczos_minres(Seg g, double* st, const SV* u, SV* up, const SV* w, const SV
     }
     __syncthreads();
     const double* S = st + rhs * NS;
-    const float a = (float)(alpha_s / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
+    // after an exact breakdown (n_{j+1} = 0) the rhs's vectors are zero until the host check
+    // retires it: a = 0/0 would put NaN into the solution update
+    const float a = S[B_NCUR] > 0.0 ? (float)(alpha_s / S[B_NCUR]) : 0.f;
+    const float b = (float)(S[B_BETA] / S[B_NPREV]);
     const float delta = (float)S[B_DELTA], eps = (float)S[B_EPS], ig = (float)(1.0 / S[B_GAMMA]);
     const float tau = (float)S[B_TAU];
     const float iu = (float)(1.0 / S[B_NPREV]);
@@ -304,7 +307,10 @@ k_b_lanczos_w(Seg g, double* st, const SV* u, const SV* up, const SV* w, SV* un,
     }
     __syncthreads();
     const double* S = st + rhs * NS;
-    const float a = (float)(alpha_s / S[B_NCUR]), b = (float)(S[B_BETA] / S[B_NPREV]);
+    // after an exact breakdown (n_{j+1} = 0) the rhs's vectors are zero until the host check
+    // retires it: a = 0/0 would put NaN into the ring and the window's update
+    const float a = S[B_NCUR] > 0.0 ? (float)(alpha_s / S[B_NCUR]) : 0.f;
+    const float b = (float)(S[B_BETA] / S[B_NPREV]);
     const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     // four elements per thread and step (fields are whole 64-site tiles: n and off are
     // multiples of 768 elements), one 16-byte (BF16) or two (FP32) accesses per field
@@ -724,7 +730,7 @@ static int bwilson_lo(Batch& bt, int which, const SV* in, SV* out, int red, doub
 }
 
 static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
-  TimeScope ts(bt.ctx, T_WILSON, bt.wilson_bytes(576.0, 384.0));
+  TimeScope ts(bt.ctx, T_WILSON64, bt.wilson_bytes(576.0, 384.0));
   if (bt.single()) {
     dl_op* op = bt.items[0].op;
     const WilsonCfg cfg = wilson_cfg(op, DL_FP64, bt.nr);
@@ -906,7 +912,7 @@ struct GraphCache {
 // The batched solve over a list of operators.  B, X: all fields of the batch, field r at
 // h_off[r] (tiled FP64).  net: learned initial guess (single operator only).
 static int solve_batch(const std::vector<BItem>& items, const double2* B, double2* X, const dl_next_opts& o,
-                       dl_stats* st) {
+                       dl_stats* st, History* hist) {
   const double t0 = now_s();
   Batch bt(items);
   const int nr = bt.nr;
@@ -1036,8 +1042,18 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       std::fflush(stderr);
     }
   }
-  double inner_drop = o.inner_drop > 0.0 ? o.inner_drop : 1e-4;  // residual drop that ends a cycle
-  int rel_opt = o.reliable_every;
+  // Per-cycle residual drop and D-CG reliable-update interval; 0 in the options = the default
+  // for the storage and solver.  BF16 rounding limits what a MinRes cycle can reach, so BF16
+  // D-MinRes cycles end at 1e-2.  BF16 D-CG keeps its search direction through FP64 residual
+  // replacements every 8 iterations and runs 1e-3 cycles: on a near-critical 24^3x48 field that
+  // took 410 iterations per rhs (FP32: 392), against 1662 with 1e-2 cycles and updates every 50,
+  // while 1e-4 cycles stalled above their target (BF16 rounding) before the stagnation rule
+  // existed.  A batch that falls back from BF16 to FP32 takes the FP32 defaults for the values
+  // the caller left at 0 and keeps the ones it set.
+  const bool drop_default = o.inner_drop == 0.0, rel_default = o.reliable_every == 0;
+  const bool bf16_cg = o.storage == DL_BF16 && !mr;
+  double inner_drop = drop_default ? (o.storage == DL_BF16 ? (bf16_cg ? 1e-3 : 1e-2) : 1e-4) : o.inner_drop;
+  int rel_opt = rel_default ? (bf16_cg ? 8 : 50) : o.reliable_every;
   bool stalled_any = false;
   const int check = 8;                 // iterations between host checks (even)
   const Seg g = bt.seg;
@@ -1052,6 +1068,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       if (!bt.h_active[r]) continue;
       rel[r] = bt.get(r, B_NRM) / bnorm[r];
       if (!std::isfinite(rel[r])) fail(DL_E_NONFINITE, "non-finite residual");
+      if (hist) hist->add(r, (double)mvp[r], rel[r]);
       if (rel[r] <= tol[r] || mvp[r] >= o.max_mvp) bt.h_active[r] = 0;
     }
     bt.push_active();
@@ -1167,6 +1184,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
           for (int r = 0; r < nr; ++r) {
             if (!bt.h_active[r]) continue;
             const double eta = std::fabs(bt.get(r, B_ETA));
+            if (hist) hist->add(r, (double)mvp[r], eta / bnorm[r]);
             // with BF16 storage a cycle also ends when eta has not reached a new low (by 10%)
             // for kStall iterations (the rounding can hold it above the cycle's target)
             if (eta < 0.9 * mr_best[r]) {
@@ -1269,6 +1287,7 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
           for (int r = 0; r < nr; ++r) {
             if (!bt.h_active[r]) continue;
             const double rn = std::sqrt(bt.get(r, B_RR));
+            if (hist) hist->add(r, (double)mvp[r], rn / bnorm[r]);
             // with BF16 storage a cycle also ends when its residual has not reached a new low
             // (by 10%) for kStall iterations: the rounding can hold it above the cycle's target
             if (rn < 0.9 * best[r]) {
@@ -1306,9 +1325,9 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       if (bt.single()) (void)wilson_cfg(items[0].op, DL_FP32, nr);
       graphs.clear();  // captured blocks name the BF16 buffers
       bf16 = false;
-      // the BF16 defaults (1e-3 / 1e-2 drops, updates every 8) give way to the FP32 ones
-      if (inner_drop == 1e-3 || inner_drop == 1e-2) inner_drop = 1e-4;
-      if (rel_opt == 8) rel_opt = 50;
+      // defaulted settings give way to the FP32 defaults; values the caller set are kept
+      if (drop_default) inner_drop = 1e-4;
+      if (rel_default) rel_opt = 50;
       if (verbose()) {
         std::fprintf(stderr, "[deflan] batched: a BF16 cycle stalled, continuing with FP32 storage\n");
         std::fflush(stderr);
@@ -1339,14 +1358,14 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
 }
 
 int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
-                       const dl_next_opts& o, dl_stats* st) {
+                       const dl_next_opts& o, dl_stats* st, History* hist) {
   if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
     fail(DL_E_MISMATCH, "eigenvector handle was built for a different operator");
-  return solve_batch({BItem{op, eig, 0, nrhs, tol}}, B, X, o, st);
+  return solve_batch({BItem{op, eig, 0, nrhs, tol}}, B, X, o, st, hist);
 }
 
 int solve_next_multi(const std::vector<MultiItem>& items, const double2* B, double2* X, const dl_next_opts& o,
-                     dl_stats* st) {
+                     dl_stats* st, History* hist) {
   std::vector<BItem> bi;
   int r0 = 0;
   for (const auto& m : items) {
@@ -1355,7 +1374,7 @@ int solve_next_multi(const std::vector<MultiItem>& items, const double2* B, doub
     bi.push_back(BItem{m.op, m.eig, r0, m.nrhs, m.tol});
     r0 += m.nrhs;
   }
-  return solve_batch(bi, B, X, o, st);
+  return solve_batch(bi, B, X, o, st, hist);
 }
 
 }  // namespace dl

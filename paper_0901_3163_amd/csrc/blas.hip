@@ -183,3 +183,44 @@ void widen_f64(hipStream_t s, long n, const float2* a, double2* b) {
 }
 
 }  // namespace dl
+
+namespace dl {
+
+// splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) as the per-element mixer
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) k_field_hash(long n, const double2* __restrict__ a, uint64_t* part) {
+  uint64_t acc = 0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const double2 v = a[i];
+    const uint64_t re = (uint64_t)__double_as_longlong(v.x), im = (uint64_t)__double_as_longlong(v.y);
+    acc += mix64(re ^ mix64(2 * (uint64_t)i + 1)) + mix64(im ^ mix64(2 * (uint64_t)i + 2));
+  }
+  __shared__ uint64_t lds[256];
+  lds[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+}
+
+uint64_t field_hash(hipStream_t s, long n, const double2* a) {
+  constexpr int kParts = 1024;
+  DBuf<uint64_t> part(kParts);
+  hipLaunchKernelGGL(k_field_hash, dim3(kParts), dim3(256), 0, s, n, a, part.get());
+  DL_HIP(hipGetLastError());
+  std::vector<uint64_t> h(kParts);
+  DL_HIP(hipMemcpyAsync(h.data(), part.get(), kParts * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  DL_HIP(hipStreamSynchronize(s));
+  uint64_t t = 0;
+  for (uint64_t v : h) t += v;
+  return t;
+}
+
+}  // namespace dl

@@ -97,16 +97,23 @@ dl_first_opts first_defaults(const dl_first_opts* o) {
   d.eig_tol = 1e-12;
   d.past_conv_factor = 2.0;
   d.max_mvp = 1000000;
+  d.reorth = DL_REORTH_FULL;
+  d.reorth_period = 1;
   if (o) {
     if (o->eig_tol > 0) d.eig_tol = o->eig_tol;
     if (o->past_conv_factor > 0) d.past_conv_factor = o->past_conv_factor;
     if (o->max_mvp > 0) d.max_mvp = o->max_mvp;
+    need(o->reorth == DL_REORTH_FULL || o->reorth == DL_REORTH_KEPT, "reorth must be DL_REORTH_FULL or DL_REORTH_KEPT");
+    need(o->reorth_period >= 0, "reorth_period must be >= 0");
+    d.reorth = o->reorth;
+    if (o->reorth_period > 0) d.reorth_period = o->reorth_period;
   }
   return d;
 }
 
-// kind: the operator form (DL_MDAGM runs D-CG, DL_G5M D-MinRes); the BF16 defaults differ by solver
-dl_next_opts next_defaults(const dl_next_opts* o, int kind) {
+// inner_drop and reliable_every stay 0 when the caller leaves them at 0: the batched solver
+// resolves them by storage and solver (and knows which ones the caller set)
+dl_next_opts next_defaults(const dl_next_opts* o) {
   dl_next_opts d{};
   d.storage = DL_FP64;
   d.reliable_every = 0;  // resolved below by storage and solver
@@ -129,15 +136,6 @@ dl_next_opts next_defaults(const dl_next_opts* o, int kind) {
     d.minres_window = o->minres_window;
   }
   if (d.net_prec == 0) d.net_prec = DL_FP32;
-  // Per-cycle residual drop of the batched inner solve and the D-CG reliable-update interval.
-  // BF16 rounding limits what a MinRes cycle can reach, so BF16 D-MinRes cycles end at 1e-2.
-  // BF16 D-CG keeps its search direction through FP64 residual replacements every 8 iterations
-  // and runs 1e-3 cycles: on a near-critical 24^3x48 field that took 410 iterations per rhs
-  // (FP32: 392), against 1662 with 1e-2 cycles and updates every 50, while 1e-4 cycles stalled
-  // above their target (BF16 rounding) before the stagnation rule existed.
-  const bool bf16_cg = d.storage == DL_BF16 && kind == DL_MDAGM;
-  if (d.inner_drop == 0.0) d.inner_drop = d.storage == DL_BF16 ? (bf16_cg ? 1e-3 : 1e-2) : 1e-4;
-  if (d.reliable_every == 0) d.reliable_every = bf16_cg ? 8 : 50;
   return d;
 }
 
@@ -164,6 +162,31 @@ void weights_to_host(const float2* d, double* w, hipStream_t s) {
   }
 }
 
+// The caller's residual-history requests (input fields of dl_stats), taken before a solve
+// overwrites the entries, and given back with the points afterwards.
+struct HistoryReq {
+  std::vector<double*> ptr;
+  History h;
+  HistoryReq(const dl_stats* st, int n) : ptr(n, nullptr), h(n) {
+    if (!st) return;
+    for (int r = 0; r < n; ++r)
+      if (st[r].history && st[r].history_cap > 0) {
+        ptr[r] = st[r].history;
+        h.cap[r] = st[r].history_cap;
+      }
+  }
+  History* get() { return h.any() ? &h : nullptr; }
+  void write(dl_stats* st, int n) const {
+    if (!st) return;
+    for (int r = 0; r < n; ++r) {
+      st[r].history = ptr[r];
+      st[r].history_cap = ptr[r] ? h.cap[r] : 0;
+      st[r].history_len = ptr[r] ? (int)(h.pts[r].size() / 2) : 0;
+      if (ptr[r] && !h.pts[r].empty()) std::memcpy(ptr[r], h.pts[r].data(), h.pts[r].size() * sizeof(double));
+    }
+  }
+};
+
 void check_net_op(const dl_net* net, const dl_op* op) {
   need(net->ctx == op->ctx, "network and operator belong to different contexts");
 }
@@ -174,7 +197,7 @@ extern "C" {
 
 const char* dl_last_error(void) { return dl::last_error().c_str(); }
 
-int dl_version(void) { return 100; }
+int dl_version(void) { return 200; }
 
 int dl_ctx_create(int device, void* hip_stream, dl_ctx** out) {
   return guard([&] {
@@ -244,6 +267,7 @@ int dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total_
     else if (!std::strcmp(name, "tsk_dots")) id = T_TSK_DOTS;
     else if (!std::strcmp(name, "tsk_update")) id = T_TSK_UPDATE;
     else if (!std::strcmp(name, "small")) id = T_SMALL;
+    else if (!std::strcmp(name, "wilson64")) id = T_WILSON64;
     need(id >= 0, "unknown kernel family");
     ctx->timers.collect();
     *launches = ctx->timers.launches[id];
@@ -271,25 +295,21 @@ int dl_op_create(dl_ctx* ctx, const int dims[4], const double* links, int mem, d
       op->U.alloc(lat.nl);
       zero(s, lat.nl, op->U.get());
       const size_t bytes = (size_t)lat.V * kLinkC * sizeof(double2);
-      std::vector<double> sample;
       if (mem == DL_DEVICE) {
         pack_links(s, lat, reinterpret_cast<const double2*>(links), op->U.get());
-        sample.resize(std::min<size_t>(4096, (size_t)lat.V * kLinkC * 2));
-        DL_HIP(hipMemcpyAsync(sample.data(), links, sample.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       } else {
         DBuf<double2> stage((size_t)lat.V * kLinkC);
         DL_HIP(hipMemcpyAsync(stage.get(), links, bytes, hipMemcpyHostToDevice, s));
         pack_links(s, lat, stage.get(), op->U.get());
         DL_HIP(hipStreamSynchronize(s));
-        const size_t nd = (size_t)lat.V * kLinkC * 2;
-        for (size_t i = 0; i < nd; i += std::max<size_t>(1, nd / 4096)) sample.push_back(links[i]);
       }
-      DL_HIP(hipStreamSynchronize(s));
+      // every link as stored on the device, whatever memory it came from
+      const uint64_t lh = field_hash(s, lat.nl, op->U.get());
       uint64_t h = 1469598103934665603ull;
       h = fnv(h, dims, 4 * sizeof(int));
       h = fnv(h, &kappa, sizeof(double));
       h = fnv(h, &kind, sizeof(int));
-      h = fnv(h, sample.data(), sample.size() * sizeof(double));
+      h = fnv(h, &lh, sizeof(lh));
       op->fingerprint = h;
     } catch (...) {
       delete op;
@@ -308,6 +328,14 @@ void dl_op_destroy(dl_op* op) {
 }
 
 long dl_op_size(const dl_op* op) { return op ? 12 * op->lat.V : 0; }
+
+int dl_op_fingerprint(const dl_op* op, unsigned long long* out) {
+  return guard([&] {
+    need(op && out, "NULL argument");
+    *out = (unsigned long long)op->fingerprint;
+    return DL_OK;
+  });
+}
 
 int dl_apply(dl_op* op, int which, const double* in, double* out, int mem) {
   return guard([&] {
@@ -346,8 +374,10 @@ int dl_solve_first(dl_op* op, const double* b, double* x, int mem, int m, int k,
     DBuf<double2> xt(op->lat.nc);
     zero(op->ctx->stream, op->lat.nc, xt.get());
     dl_eig* e = nullptr;
-    const int rc = solve_first(op, bt.get(), xt.get(), m, k, tol, o, eig_out ? &e : nullptr, stats);
+    HistoryReq hr(stats, 1);
+    const int rc = solve_first(op, bt.get(), xt.get(), m, k, tol, o, eig_out ? &e : nullptr, stats, hr.get());
     fields_out(op, xt.get(), x, 1, mem);
+    hr.write(stats, 1);
     if (eig_out) *eig_out = e;
     return rc;
   });
@@ -362,12 +392,12 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     need(B && X, "NULL argument");
     need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
     need(tol > 0 && std::isfinite(tol), "tol must be positive");
-    const dl_next_opts o = next_defaults(opts, op->kind);
+    const dl_next_opts o = next_defaults(opts);
     need(o.storage == DL_FP64 || o.storage == DL_FP32 || o.storage == DL_BF16,
          "storage must be DL_FP64, DL_FP32 or DL_BF16");
     need(!(o.storage != DL_FP64 && !o.batched), "DL_FP32 and DL_BF16 storage run through the batched path (batched = 1)");
     need(!(o.batched && o.storage == DL_FP64), "the batched path stores Krylov vectors in DL_FP32 or DL_BF16");
-    need(o.inner_drop > 0.0 && o.inner_drop < 1.0, "inner_drop must be in (0, 1)");
+    need(o.inner_drop == 0.0 || (o.inner_drop > 0.0 && o.inner_drop < 1.0), "inner_drop must be in (0, 1)");
     need(!o.net || o.batched, "the learned initial guess runs on the batched path (batched = 1)");
     need(o.eig_storage == DL_FP64 || o.eig_storage == DL_FP32 || o.eig_storage == DL_BF16,
          "eig_storage must be DL_FP64, DL_FP32 or DL_BF16");
@@ -384,9 +414,11 @@ int dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B, doubl
     DBuf<double2> bt = fields_in(op, B, nrhs, mem);
     DBuf<double2> xt = o.x0_given ? fields_in(op, X, nrhs, mem) : DBuf<double2>((size_t)nrhs * op->lat.nc);
     if (!o.x0_given) zero(op->ctx->stream, (long)nrhs * op->lat.nc, xt.get());
-    const int rc = o.batched ? solve_next_batched(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats)
-                             : solve_next(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats);
+    HistoryReq hr(stats, nrhs);
+    const int rc = o.batched ? solve_next_batched(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats, hr.get())
+                             : solve_next(op, eig, nrhs, bt.get(), xt.get(), tol, o, stats, hr.get());
     fields_out(op, xt.get(), X, nrhs, mem);
+    hr.write(stats, nrhs);
     return rc;
   });
 }
@@ -440,15 +472,14 @@ int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int
     need(items != nullptr, "items is NULL");
     need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
     need(items[0].op != nullptr, "item op is NULL");
-    dl_next_opts o = next_defaults(opts, items[0].op->kind);
+    dl_next_opts o = next_defaults(opts);
     if (!opts) {
       o.storage = DL_FP32;
       o.batched = 1;
-      o.inner_drop = 1e-4;
     }
     need((o.storage == DL_FP32 || o.storage == DL_BF16) && o.batched,
          "the multi-lattice batch runs the batched path (DL_FP32 or DL_BF16, batched = 1)");
-    need(o.inner_drop > 0.0 && o.inner_drop < 1.0, "inner_drop must be in (0, 1)");
+    need(o.inner_drop == 0.0 || (o.inner_drop > 0.0 && o.inner_drop < 1.0), "inner_drop must be in (0, 1)");
     need(!o.net, "the learned initial guess takes one operator per batch (dl_solve_next)");
     need(o.minres_window <= 64, "minres_window must be at most 64");
     need(o.eig_storage == DL_FP64 || o.eig_storage == DL_FP32 || o.eig_storage == DL_BF16,
@@ -487,7 +518,8 @@ int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int
     long nst = 0;
     for (const auto& m : mi) nst += m.nrhs;
     st.resize(nst);
-    const int rc = solve_next_multi(mi, bt.get(), xt.get(), o, st.data());
+    HistoryReq hr(stats, (int)nst);
+    const int rc = solve_next_multi(mi, bt.get(), xt.get(), o, st.data(), hr.get());
     off = 0;
     long r = 0;
     for (size_t j = 0; j < mi.size(); ++j) {
@@ -499,6 +531,7 @@ int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int
       // stats in item order, nrhs entries per item (items with nrhs = 0 have none)
       for (size_t j = 0; j < mi.size(); ++j)
         for (int q = 0; q < mi[j].nrhs; ++q, ++r) stats[r] = st[r];
+      hr.write(stats, (int)nst);
     }
     return rc;
   });
@@ -752,6 +785,142 @@ int dl_eig_vectors(const dl_eig* eig, double* V, int mem) {
 }
 
 void dl_eig_destroy(dl_eig* eig) { delete eig; }
+
+namespace {
+
+// Handle file: a fixed header, then the host arrays, then the k eigenvectors in the caller's
+// interleaved layout.  All numbers little-endian as in memory (the file is read back on the
+// same kind of machine).
+constexpr char kEigMagic[8] = {'D', 'L', 'E', 'I', 'G', '0', '0', '1'};
+struct EigHeader {
+  char magic[8];
+  int32_t version, kind, k, dims[4], pad;
+  double kappa;
+  uint64_t fingerprint;
+  int64_t V, zr_n, lamr_n;
+};
+
+struct File {
+  FILE* f = nullptr;
+  File(const char* path, const char* mode) : f(std::fopen(path, mode)) {}
+  ~File() { if (f) std::fclose(f); }
+};
+
+void fwrite_all(FILE* f, const void* p, size_t bytes) {
+  if (bytes && std::fwrite(p, 1, bytes, f) != bytes) fail(DL_E_INVALID, "write to the handle file failed");
+}
+void fread_all(FILE* f, void* p, size_t bytes) {
+  if (bytes && std::fread(p, 1, bytes, f) != bytes) fail(DL_E_INVALID, "the handle file is truncated");
+}
+
+}  // namespace
+
+int dl_eig_save(const dl_eig* eig, const char* path) {
+  return guard([&] {
+    need(eig && path, "NULL argument");
+    use_device(eig->ctx);
+    hipStream_t s = eig->ctx->stream;
+    const Lattice& lat = eig->lat;
+    EigHeader hd{};
+    std::memcpy(hd.magic, kEigMagic, 8);
+    hd.version = 1;
+    hd.kind = eig->kind;
+    hd.k = eig->k;
+    for (int d = 0; d < 4; ++d) hd.dims[d] = lat.L[d];
+    hd.kappa = eig->kappa;
+    hd.fingerprint = eig->fingerprint;
+    hd.V = lat.V;
+    hd.zr_n = (int64_t)eig->Zr.n;
+    hd.lamr_n = (int64_t)eig->lamr.n;
+    std::vector<double> zr(eig->Zr.n), lamr(eig->lamr.n);
+    if (!zr.empty()) DL_HIP(hipMemcpyAsync(zr.data(), eig->Zr.get(), zr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!lamr.empty())
+      DL_HIP(hipMemcpyAsync(lamr.data(), eig->lamr.get(), lamr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    DL_HIP(hipStreamSynchronize(s));
+    File fh(path, "wb");
+    if (!fh.f) fail(DL_E_INVALID, std::string("cannot open ") + path + " for writing");
+    fwrite_all(fh.f, &hd, sizeof(hd));
+    fwrite_all(fh.f, eig->evals.data(), eig->k * sizeof(double));
+    fwrite_all(fh.f, eig->resid.data(), eig->k * sizeof(double));
+    fwrite_all(fh.f, zr.data(), zr.size() * sizeof(double));
+    fwrite_all(fh.f, lamr.data(), lamr.size() * sizeof(double));
+    // one vector at a time through a staging field
+    const size_t vbytes = (size_t)lat.V * kSpin * sizeof(double2);
+    DBuf<double2> stage((size_t)lat.V * kSpin);
+    std::vector<double2> host((size_t)lat.V * kSpin);
+    for (int i = 0; i < eig->k; ++i) {
+      unpack_spinor(s, lat, eig->Y.get() + (long)i * eig->nc, stage.get(), 1);
+      DL_HIP(hipMemcpyAsync(host.data(), stage.get(), vbytes, hipMemcpyDeviceToHost, s));
+      DL_HIP(hipStreamSynchronize(s));
+      fwrite_all(fh.f, host.data(), vbytes);
+    }
+    if (std::fflush(fh.f) != 0) fail(DL_E_INVALID, "write to the handle file failed");
+    return DL_OK;
+  });
+}
+
+int dl_eig_load(dl_op* op, const char* path, dl_eig** out) {
+  return guard([&] {
+    need(op && path && out, "NULL argument");
+    use_device(op->ctx);
+    hipStream_t s = op->ctx->stream;
+    const Lattice& lat = op->lat;
+    File fh(path, "rb");
+    if (!fh.f) fail(DL_E_INVALID, std::string("cannot open ") + path);
+    EigHeader hd{};
+    fread_all(fh.f, &hd, sizeof(hd));
+    need(std::memcmp(hd.magic, kEigMagic, 8) == 0 && hd.version == 1, "not an eigenvector handle file");
+    for (int d = 0; d < 4; ++d)
+      if (hd.dims[d] != lat.L[d]) fail(DL_E_MISMATCH, "the handle file was saved for another lattice");
+    if (hd.kind != op->kind || hd.kappa != op->kappa || hd.fingerprint != op->fingerprint)
+      fail(DL_E_MISMATCH, "the handle file was saved for another operator (kind, kappa or links)");
+    need(hd.k >= 0 && hd.k <= 512 && hd.V == lat.V, "corrupt handle header");
+    const int k = hd.k;
+    need(hd.zr_n == (k ? 4L * k * k : 0) && hd.lamr_n == (k ? 2L * k : 0), "corrupt handle header");
+    std::vector<double> evals(k), resid(k), zr(hd.zr_n), lamr(hd.lamr_n);
+    fread_all(fh.f, evals.data(), k * sizeof(double));
+    fread_all(fh.f, resid.data(), k * sizeof(double));
+    fread_all(fh.f, zr.data(), zr.size() * sizeof(double));
+    fread_all(fh.f, lamr.data(), lamr.size() * sizeof(double));
+    auto* e = new dl_eig();
+    try {
+      e->ctx = op->ctx;
+      e->lat = lat;
+      e->fingerprint = op->fingerprint;
+      e->kappa = op->kappa;
+      e->kind = op->kind;
+      e->k = k;
+      e->nc = lat.nc;
+      e->evals = evals;
+      e->resid = resid;
+      if (k > 0) {
+        e->Y.alloc((size_t)k * lat.nc);
+        zero(s, (long)k * lat.nc, e->Y.get());  // padding sites
+        const size_t vbytes = (size_t)lat.V * kSpin * sizeof(double2);
+        DBuf<double2> stage((size_t)lat.V * kSpin);
+        std::vector<double2> host((size_t)lat.V * kSpin);
+        for (int i = 0; i < k; ++i) {
+          fread_all(fh.f, host.data(), vbytes);
+          DL_HIP(hipMemcpyAsync(stage.get(), host.data(), vbytes, hipMemcpyHostToDevice, s));
+          pack_spinor(s, lat, stage.get(), e->Y.get() + (long)i * lat.nc, 1);
+          DL_HIP(hipStreamSynchronize(s));
+        }
+        e->Zr.alloc(zr.size());
+        e->lamr.alloc(lamr.size());
+        DL_HIP(hipMemcpyAsync(e->Zr.get(), zr.data(), zr.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        DL_HIP(hipMemcpyAsync(e->lamr.get(), lamr.data(), lamr.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        DL_HIP(hipStreamSynchronize(s));
+      }
+      char extra;
+      need(std::fread(&extra, 1, 1, fh.f) == 0, "the handle file has trailing data");
+    } catch (...) {
+      delete e;
+      throw;
+    }
+    *out = e;
+    return DL_OK;
+  });
+}
 
 int dl_eig_lower(dl_op* op, dl_eig* eig, int prec, long* mvp) {
   return guard([&] {

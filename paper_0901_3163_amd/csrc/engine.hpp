@@ -20,6 +20,7 @@ struct dl_eig {
   dl_ctx* ctx = nullptr;
   dl::Lattice lat{};
   uint64_t fingerprint = 0;
+  double kappa = 0.0;
   int kind = 0;
   int k = 0;
   long nc = 0;
@@ -39,6 +40,24 @@ struct dl_eig {
 namespace dl {
 
 bool verbose();  // DEFLAN_VERBOSE set: progress lines on stderr
+
+// Residual history requested by the caller (dl_stats.history): per right-hand side, the
+// (mvp, relres) points appended in order, at most cap[r] of them.
+struct History {
+  std::vector<int> cap;
+  std::vector<std::vector<double>> pts;
+  explicit History(int nrhs = 0) : cap(nrhs, 0), pts(nrhs) {}
+  bool want(int r) const { return r >= 0 && r < (int)cap.size() && cap[r] > 0; }
+  bool any() const {
+    for (int c : cap) if (c > 0) return true;
+    return false;
+  }
+  void add(int r, double mvp, double relres) {
+    if (!want(r) || (long)pts[r].size() >= 2L * cap[r]) return;
+    pts[r].push_back(mvp);
+    pts[r].push_back(relres);
+  }
+};
 
 // Scratch owned by one solve: device scalars, reduction partials, small work.
 struct Scratch {
@@ -62,12 +81,13 @@ int apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red 
 WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs);
 WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us);
 
+// hist (may be nullptr): residual history of the solve's right-hand sides.
 int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double tol, const dl_first_opts& o,
-                dl_eig** eig_out, dl_stats* st);
+                dl_eig** eig_out, dl_stats* st, History* hist = nullptr);
 int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
-               const dl_next_opts& o, dl_stats* st);
+               const dl_next_opts& o, dl_stats* st, History* hist = nullptr);
 int solve_next_batched(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
-                       const dl_next_opts& o, dl_stats* st);
+                       const dl_next_opts& o, dl_stats* st, History* hist = nullptr);
 // Several operators (lattices) in one batch: item i's fields are contiguous after item i-1's.
 struct MultiItem {
   dl_op* op;
@@ -76,7 +96,7 @@ struct MultiItem {
   double tol;
 };
 int solve_next_multi(const std::vector<MultiItem>& items, const double2* B, double2* X, const dl_next_opts& o,
-                     dl_stats* st);
+                     dl_stats* st, History* hist = nullptr);
 dl_eig* eig_build(dl_op* op, int k, DBuf<double2>&& Y, long* mvp);
 // Build the lowered copies of eig for prec (DL_FP32 or DL_BF16); k MVPs for H32 (once: a second
 // call with the same prec does nothing, DL_FP64 drops the copies).  Returns MVPs used.

@@ -90,7 +90,8 @@ struct DBuf {
 };
 
 // ---- kernel timing --------------------------------------------------------
-enum TimerId { T_WILSON = 0, T_TSK_DOTS, T_TSK_UPDATE, T_SMALL, T_COUNT };
+// T_WILSON: stencils with FP32 or BF16 spinors; T_WILSON64: FP64 stencils.
+enum TimerId { T_WILSON = 0, T_TSK_DOTS, T_TSK_UPDATE, T_SMALL, T_WILSON64, T_COUNT };
 
 struct Timers {
   bool enabled = false;
@@ -200,6 +201,10 @@ void zero(hipStream_t s, long n, double2* a);
 void round_f32(hipStream_t s, long n, const double2* a, float2* b);  // b = (float) a
 void widen_f64(hipStream_t s, long n, const float2* a, double2* b);  // b = (double) a
 void round_bf16(hipStream_t s, long n, const double2* a, bf2* b);    // b = bf16(float(a)), nearest even
+// Position-dependent 64-bit hash of n complex numbers (bit patterns): the wrap-around sum of a
+// mixed (index, bits) word per element, so it is independent of the summation order and any
+// single changed element changes it (up to 64-bit collisions).  Synchronises the stream.
+uint64_t field_hash(hipStream_t s, long n, const double2* a);
 void widen_bf16(hipStream_t s, long n, const bf2* a, double2* b);    // b = (double) a
 
 }  // namespace dl

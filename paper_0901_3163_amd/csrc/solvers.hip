@@ -188,6 +188,15 @@ k_fin_lanczos(const double* part, int np, double* Tb, int m, int j, const double
   }
 }
 
+// One residual-history point: out = (mvp, scale * sqrt(sc[idx])) or (mvp, scale * |sc[idx]|).
+__global__ void k_hist_push(const double* sc, int idx, int squared, double scale, double mvp, double* out) {
+  if (threadIdx.x == 0) {
+    const double v = sc[idx];
+    out[0] = mvp;
+    out[1] = scale * (squared ? sqrt(v) : fabs(v));
+  }
+}
+
 // ---- streaming kernels ------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_scale(long n, const double* sc, int idx, const double2* __restrict__ in, double2* __restrict__ out) {
@@ -279,7 +288,7 @@ static int grid_for(long n) {
 int apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red, double* part) {
   const WilsonCfg cfg = wilson_cfg(op, DL_FP64, 1);
   // algorithmic bytes: input spinor, links and output spinor moved once (FP64: 960 B/site)
-  TimeScope ts(op->ctx, T_WILSON, 960.0 * (double)op->lat.V);
+  TimeScope ts(op->ctx, T_WILSON64, 960.0 * (double)op->lat.V);
   return wilson_f64(op->ctx->stream, op->lat, op->U.get(), op->kappa, which, in, out, red, part, cfg);
 }
 
@@ -340,6 +349,20 @@ static double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Per-iteration residual history of one rhs of the FP64 later-rhs path, written on the device
+// (no host synchronisation per point) and copied out when the rhs is done.
+struct DevHist {
+  DBuf<double> d;
+  int cap = 0, n = 0;
+  long mvp0 = 0;  // MVPs of the rhs before the current inner run
+  void push(hipStream_t s, const double* sc, int idx, bool squared, double scale, long mvp) {
+    if (n >= cap) return;
+    hipLaunchKernelGGL(k_hist_push, dim3(1), dim3(64), 0, s, sc, idx, (int)squared, scale, (double)mvp,
+                       d.get() + 2L * n);
+    ++n;
+  }
+};
+
 // ---- Krylov inner solvers -------------------------------------------------------
 struct InnerResult {
   long iters = 0, mvp = 0;
@@ -348,7 +371,7 @@ struct InnerResult {
 
 // MinRes on gamma5 M from x: iterate until |eta|/||b|| <= tol (recurrence), FP64.
 static InnerResult minres_run(dl_op* op, const double2* b, double2* x, double bnorm, double tol, long max_mvp,
-                              Scratch& S, DBuf<double2>* w6, int check_every) {
+                              Scratch& S, DBuf<double2>* w6, int check_every, DevHist* dh = nullptr) {
   hipStream_t s = op->ctx->stream;
   const long n = op->lat.nc;
   const int G = grid_for(n);
@@ -370,6 +393,7 @@ static InnerResult minres_run(dl_op* op, const double2* b, double2* x, double bn
   double h[S_COUNT];
   read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
   const double beta1 = h[S_NRM];
+  if (dh) dh->push(s, S.sc.get(), (int)S_NRM, false, 1.0 / bnorm, dh->mvp0 + res.mvp);
   if (!(beta1 / bnorm > tol)) {
     res.converged = true;
     return res;
@@ -390,6 +414,7 @@ static InnerResult minres_run(dl_op* op, const double2* b, double2* x, double bn
     std::swap(w6[0], w6[1]);  // v <- v_next, vp <- old v
     v = w6[0].get(); vp = w6[1].get(); d1 = w6[3].get(); d2 = w6[4].get();
     res.iters += 1;
+    if (dh) dh->push(s, S.sc.get(), (int)M_ETA, false, 1.0 / bnorm, dh->mvp0 + res.mvp);
     if (res.iters % check_every == 0 || res.mvp >= max_mvp) {
       read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
       if (h[S_FLAG] == 2.0) { res.converged = true; break; }
@@ -402,7 +427,7 @@ static InnerResult minres_run(dl_op* op, const double2* b, double2* x, double bn
 
 // CG on the normal equations (CGLS) from x, tracking r = b - M x.
 static InnerResult cgls_run(dl_op* op, const double2* b, double2* x, double bnorm, double tol, long max_mvp,
-                            Scratch& S, DBuf<double2>* w6, int check_every) {
+                            Scratch& S, DBuf<double2>* w6, int check_every, DevHist* dh = nullptr) {
   hipStream_t s = op->ctx->stream;
   const long n = op->lat.nc;
   const int G = grid_for(n);
@@ -416,6 +441,7 @@ static InnerResult cgls_run(dl_op* op, const double2* b, double2* x, double bnor
   hipLaunchKernelGGL(k_fin_store, dim3(1), dim3(kBlock), 0, s, S.part.get(), nbw, S.sc.get(), (int)S_SS);
   copy(s, n, sv, p);
   res.mvp += 2;
+  if (dh) dh->push(s, S.sc.get(), (int)S_RN2, true, 1.0 / bnorm, dh->mvp0 + res.mvp);
   double h[S_COUNT];
   read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
   if (!(std::sqrt(h[S_RN2]) / bnorm > tol)) {
@@ -437,6 +463,7 @@ static InnerResult cgls_run(dl_op* op, const double2* b, double2* x, double bnor
     DL_HIP(hipGetLastError());
     res.mvp += 2;
     res.iters += 1;
+    if (dh) dh->push(s, S.sc.get(), (int)S_RN2, true, 1.0 / bnorm, dh->mvp0 + res.mvp);
     if (res.iters % check_every == 0 || res.mvp >= max_mvp) {
       read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
       if (h[S_FLAG] != 0.0) {
@@ -454,7 +481,7 @@ static InnerResult cgls_run(dl_op* op, const double2* b, double2* x, double bnor
 // CG on gamma5 M x = gamma5 b from x (Hermitian, indefinite), tracking r = gamma5 (b - M x),
 // whose norm is ||b - M x||.  The paper's counter-example to using CG on gamma5 M (Section 3).
 static InnerResult cg_g5_run(dl_op* op, const double2* b, double2* x, double bnorm, double tol, long max_mvp,
-                             Scratch& S, DBuf<double2>* w6, int check_every) {
+                             Scratch& S, DBuf<double2>* w6, int check_every, DevHist* dh = nullptr) {
   hipStream_t s = op->ctx->stream;
   const long n = op->lat.nc;
   const int G = grid_for(n);
@@ -467,6 +494,7 @@ static InnerResult cg_g5_run(dl_op* op, const double2* b, double2* x, double bno
   hipLaunchKernelGGL(k_fin_store, dim3(1), dim3(kBlock), 0, s, S.part.get(), nb, S.sc.get(), (int)S_RN2);
   gamma5_f64(s, op->lat, q, r);
   copy(s, n, r, p);
+  if (dh) dh->push(s, S.sc.get(), (int)S_RN2, true, 1.0 / bnorm, dh->mvp0 + res.mvp);
   double h[S_COUNT];
   read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
   if (!(std::sqrt(h[S_RN2]) / bnorm > tol)) {
@@ -486,6 +514,7 @@ static InnerResult cg_g5_run(dl_op* op, const double2* b, double2* x, double bno
     DL_HIP(hipGetLastError());
     res.mvp += 1;
     res.iters += 1;
+    if (dh) dh->push(s, S.sc.get(), (int)S_RN2, true, 1.0 / bnorm, dh->mvp0 + res.mvp);
     if (res.iters % check_every == 0 || res.mvp >= max_mvp) {
       read_scalars(op->ctx, S.sc.get(), S_COUNT, h);
       if (h[S_FLAG] != 0.0) {
@@ -520,7 +549,7 @@ static void project(dl_op* op, const dl_eig* eig, const double2* r, double2* x, 
 }
 
 int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2* X, double tol,
-               const dl_next_opts& o, dl_stats* st) {
+               const dl_next_opts& o, dl_stats* st, History* hist) {
   hipStream_t s = op->ctx->stream;
   const long n = op->lat.nc;
   if (eig && (eig->fingerprint != op->fingerprint || eig->kind != op->kind))
@@ -580,21 +609,36 @@ int solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double2* B, double2
     long iters = 0;
     bool conv = false;
     double relres = 1.0;
+    DevHist dh;
+    DevHist* dhp = nullptr;
+    if (hist && hist->want(r)) {
+      dh.cap = hist->cap[r];
+      dh.d.alloc(2 * (size_t)dh.cap);
+      dhp = &dh;
+    }
     for (int attempt = 0; attempt < 6; ++attempt) {
-      InnerResult ir = op->kind != DL_G5M ? cgls_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check)
-                       : o.method == DL_METHOD_CG ? cg_g5_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check)
-                                                  : minres_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check);
+      dh.mvp0 = mvp;
+      InnerResult ir = op->kind != DL_G5M ? cgls_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check, dhp)
+                       : o.method == DL_METHOD_CG ? cg_g5_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check, dhp)
+                                                  : minres_run(op, b, x, bnorm, tol, o.max_mvp - mvp, S, w6, check, dhp);
       iters += ir.iters;
       mvp += ir.mvp;
       // true residual in FP64
       enqueue_true_residual(op, b, x, w6[0].get(), w6[1].get(), S, (int)S_RN2);
       mvp += 1;
+      if (dhp) dh.push(s, S.sc.get(), (int)S_RN2, true, 1.0 / bnorm, mvp);
       double h;
       read_scalars(op->ctx, S.sc.get() + S_RN2, 1, &h);
       relres = std::sqrt(h) / bnorm;
       if (!std::isfinite(relres)) fail(DL_E_NONFINITE, "non-finite residual");
       if (relres <= tol) { conv = true; break; }
       if (mvp >= o.max_mvp) break;
+    }
+    if (dhp && dh.n > 0) {
+      std::vector<double> hp(2 * (size_t)dh.n);
+      DL_HIP(hipMemcpyAsync(hp.data(), dh.d.get(), hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      DL_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < dh.n; ++i) hist->add(r, hp[2 * i], hp[2 * i + 1]);
     }
     one.status = conv ? DL_OK : DL_NOT_CONVERGED;
     one.iters = iters;
@@ -621,6 +665,7 @@ dl_eig* eig_build(dl_op* op, int k, DBuf<double2>&& Y, long* mvp) {
   e->ctx = op->ctx;
   e->lat = op->lat;
   e->fingerprint = op->fingerprint;
+  e->kappa = op->kappa;
   e->kind = op->kind;
   e->k = k;
   e->nc = n;
@@ -714,7 +759,7 @@ long eig_lower(dl_op* op, dl_eig* e, int prec) {
 
 // ---- first right-hand side: Lan-DR / MinRes-DR --------------------------------------
 int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double tol, const dl_first_opts& o,
-                dl_eig** eig_out, dl_stats* st) {
+                dl_eig** eig_out, dl_stats* st, History* hist) {
   const double t0 = now_s();
   dl_ctx* ctx = op->ctx;
   hipStream_t s = ctx->stream;
@@ -748,7 +793,14 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
   // small problem buffers
   DBuf<double> Tb((size_t)(m + 1) * m), cvec(m + 1), dvec(m), Gk((size_t)(m + 1) * (k + 1) + 1);
   DBuf<double> theta(k + 1), rho(k + 1), hth(k + 1), Smat((size_t)k * k + 1), info(8);
-  DBuf<double> c1(2 * (size_t)(m + 1)), c2(2 * (size_t)(m + 1));
+  DBuf<double> c1(2 * (size_t)(m + 1)), c2(2 * (size_t)(m + 1)), c3(4 * (size_t)(m + 1));
+  // the best cycle-end iterate: after the linear system has met tol the cycles go on for the
+  // eigenvectors, and at the FP64 residual floor their corrections move the residual by small
+  // factors either way
+  DBuf<double2> xbest(n);
+  double best = HUGE_VAL;
+  const bool kept_reorth = o.reorth == DL_REORTH_KEPT;
+  const int period = std::max(1, o.reorth_period);
   DBuf<double> work(std::max(landr_work(m), minresdr_work(m)));
   {
     std::vector<double> z((size_t)(m + 1) * m, 0.0);
@@ -786,16 +838,28 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
     int mm = m;
     for (int j = j0; j < m; ++j) {
       mvp += apply_A(op, V(j), w.get(), tmp.get());
-      for (int pass = 0; pass < 2; ++pass) {
-        double* cb = pass == 0 ? c1.get() : c2.get();
-        int nb;
-        {
-          TimeScope ts(ctx, T_TSK_DOTS);
-          nb = tsk_dots(s, n, j + 1, Vb.get(), n, slot_d.get(), w.get(), S.part.get());
+      // Classical Gram-Schmidt twice against logical vectors [v0, v0 + nv); the coefficients land
+      // at cb[v0..] (k_fin_lanczos takes alpha_j from entry j of c1 + c2).
+      auto cgs2 = [&](int v0, int nv, double* ca, double* cb2) {
+        for (int pass = 0; pass < 2; ++pass) {
+          double* cb = (pass == 0 ? ca : cb2) + 2 * v0;
+          int nb;
+          {
+            TimeScope ts(ctx, T_TSK_DOTS);
+            nb = tsk_dots(s, n, nv, Vb.get(), n, slot_d.get() + v0, w.get(), S.part.get());
+          }
+          sum_partials(s, S.part.get(), nb, 2 * nv, cb);
+          TimeScope ts(ctx, T_TSK_UPDATE);
+          tsk_update(s, n, nv, Vb.get(), n, slot_d.get() + v0, reinterpret_cast<const double2*>(cb), -1.0, w.get());
         }
-        sum_partials(s, S.part.get(), nb, 2 * (j + 1), cb);
-        TimeScope ts(ctx, T_TSK_UPDATE);
-        tsk_update(s, n, j + 1, Vb.get(), n, slot_d.get(), reinterpret_cast<const double2*>(cb), -1.0, w.get());
+      };
+      if (!kept_reorth || j == j0 || j == 0) {
+        cgs2(0, j + 1, c1.get(), c2.get());  // the whole basis (the arrow column after a restart)
+      } else {
+        // the paper's policy: the three-term recurrence's two vectors, and every `period` steps
+        // the vectors kept at the last restart (coefficients discarded: zero in exact arithmetic)
+        cgs2(j - 1, 2, c1.get(), c2.get());
+        if (j0 > 0 && (j - j0) % period == 0) cgs2(0, j0, c3.get(), c3.get() + 2 * (m + 1));
       }
       const int nb = norm2_partials(s, n, w.get(), S.part.get());
       hipLaunchKernelGGL(k_fin_lanczos, dim3(1), dim3(kBlock), 0, s, S.part.get(), nb, Tb.get(), m, j, c1.get(),
@@ -840,6 +904,11 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
     read_scalars(ctx, S.sc.get(), S_COUNT, h);
     relres = std::sqrt(h[S_RN2]) / bnorm;
     if (!std::isfinite(relres)) fail(DL_E_NONFINITE, "non-finite residual");
+    if (hist) hist->add(0, (double)mvp, relres);
+    if (relres < best) {
+      best = relres;
+      copy(s, n, x, xbest.get());
+    }
     if (k > 0) DL_HIP(hipMemcpy(h_rho.data(), rho.get(), k * sizeof(double), hipMemcpyDeviceToHost));
     DL_HIP(hipMemcpy(h_info.data(), info.get(), 8 * sizeof(double), hipMemcpyDeviceToHost));
     anorm = std::max(anorm, h_info[0]);
@@ -906,6 +975,11 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
   } else if (eig_out) {
     *eig_out = eig_build(op, 0, DBuf<double2>(), nullptr);
   }
+  if (best < relres) {  // a later cycle ended above an earlier one: return the best iterate
+    copy(s, n, xbest.get(), x);
+    relres = best;
+  }
+  DL_HIP(hipStreamSynchronize(s));
   out.status = (relres <= tol) ? DL_OK : DL_NOT_CONVERGED;
   out.stop_rule = rule;
   out.cycles = cycles;

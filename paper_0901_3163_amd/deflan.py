@@ -25,6 +25,7 @@ DL_FP64, DL_FP32, DL_BF16 = 0, 1, 2
 DL_HOST, DL_DEVICE = 0, 1
 DL_METHOD_DEFAULT, DL_METHOD_CG = 0, 1
 DL_APPLY_M, DL_APPLY_MDAG, DL_APPLY_G5M, DL_APPLY_MDAGM = 0, 1, 2, 3
+DL_REORTH_FULL, DL_REORTH_KEPT = 0, 1
 STOP_RULES = {0: "linear", 1: "eigen", 2: "mvp_factor", 3: "max_mvp", 4: "breakdown", -1: "none"}
 
 
@@ -35,7 +36,8 @@ class DeflanError(RuntimeError):
 
 
 class dl_first_opts(C.Structure):
-    _fields_ = [("eig_tol", C.c_double), ("past_conv_factor", C.c_double), ("max_mvp", C.c_long)]
+    _fields_ = [("eig_tol", C.c_double), ("past_conv_factor", C.c_double), ("max_mvp", C.c_long),
+                ("reorth", C.c_int), ("reorth_period", C.c_int)]
 
 
 class dl_next_opts(C.Structure):
@@ -53,12 +55,36 @@ class dl_batch_item(C.Structure):
 class dl_stats(C.Structure):
     _fields_ = [("status", C.c_int), ("stop_rule", C.c_int), ("cycles", C.c_int), ("guess", C.c_int),
                 ("mvp", C.c_long), ("mvp_lin", C.c_long), ("iters", C.c_long),
-                ("relres", C.c_double), ("time_s", C.c_double)]
+                ("relres", C.c_double), ("time_s", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("history", "history_cap", "history_len")}
         d["stop_rule"] = STOP_RULES.get(self.stop_rule, str(self.stop_rule))
         return d
+
+
+def _stats(n, history):
+    """n dl_stats entries; history > 0: each gets a caller buffer of that many (mvp, relres) pairs."""
+    st = (dl_stats * max(n, 1))()
+    bufs = []
+    if history:
+        for i in range(n):
+            b = np.zeros((int(history), 2))
+            bufs.append(b)
+            st[i].history = b.ctypes.data_as(C.POINTER(C.c_double))
+            st[i].history_cap = int(history)
+    return st, bufs
+
+
+def _stats_dicts(st, bufs, n):
+    out = []
+    for i in range(n):
+        d = st[i].as_dict()
+        if bufs:
+            d["history"] = bufs[i][: st[i].history_len].copy()
+        out.append(d)
+    return out
 
 
 def _load():
@@ -77,6 +103,9 @@ def _load():
         "dl_op_create": (I, [P, C.POINTER(I), P, I, D, I, C.POINTER(P)]),
         "dl_op_destroy": (None, [P]),
         "dl_op_size": (L, [P]),
+        "dl_op_fingerprint": (I, [P, C.POINTER(C.c_ulonglong)]),
+        "dl_eig_save": (I, [P, C.c_char_p]),
+        "dl_eig_load": (I, [P, C.c_char_p, C.POINTER(P)]),
         "dl_apply": (I, [P, I, P, P, I]),
         "dl_solve_first": (I, [P, P, P, I, I, I, D, C.POINTER(dl_first_opts), C.POINTER(P), C.POINTER(dl_stats)]),
         "dl_solve_next": (I, [P, P, I, P, P, I, D, C.POINTER(dl_next_opts), C.POINTER(dl_stats)]),
@@ -120,7 +149,7 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
             "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower",
-            "dl_net_apply_prec")
+            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load")
 
 
 def _check(rc):
@@ -229,6 +258,10 @@ class Eig:
         _check(lib.dl_eig_lower(self.op.h, self.h, int(prec), C.byref(used)))
         return used.value
 
+    def save(self, path):
+        """Write the handle to a file (dl_eig_save)."""
+        _check(lib.dl_eig_save(self.h, os.fspath(path).encode()))
+
     def vectors(self):
         V = np.zeros((self.k, self.op.V, 4, 3), dtype=np.complex128)
         if self.k:
@@ -282,23 +315,36 @@ class Operator:
         _check(lib.dl_apply_batched(self.h, int(which), int(prec), int(Psi.shape[0]), pi, po, mem))
         return out
 
+    def fingerprint(self):
+        f = C.c_ulonglong()
+        _check(lib.dl_op_fingerprint(self.h, C.byref(f)))
+        return f.value
+
+    def eig_load(self, path):
+        """An eigenvector handle read from a file written by Eig.save (dl_eig_load)."""
+        h = C.c_void_p()
+        _check(lib.dl_eig_load(self.h, os.fspath(path).encode(), C.byref(h)))
+        return Eig(h, self)
+
     def solve_first(self, b, m: int, k: int, tol: float, eig_tol=None, past_conv_factor=None, max_mvp=None,
-                    want_eig=True):
+                    want_eig=True, reorth=DL_REORTH_FULL, reorth_period=0, history=0):
+        """history > 0: the stats dict also holds 'history', an array of (mvp, relres) rows."""
         b = _c128(b)
         x = _empty_like(b)
-        o = dl_first_opts(eig_tol or 0.0, past_conv_factor or 0.0, int(max_mvp or 0))
-        st = dl_stats()
+        o = dl_first_opts(eig_tol or 0.0, past_conv_factor or 0.0, int(max_mvp or 0), int(reorth),
+                          int(reorth_period))
+        st, bufs = _stats(1, history)
         eh = C.c_void_p()
         pb, mem = _ptr(b)
         px, _ = _ptr(x)
         rc = _check(lib.dl_solve_first(self.h, pb, px, mem, int(m), int(k), float(tol), C.byref(o),
-                                       C.byref(eh) if want_eig else None, C.byref(st)))
+                                       C.byref(eh) if want_eig else None, st))
         eig = Eig(eh, self) if want_eig else None
-        return x, eig, dict(st.as_dict(), rc=rc)
+        return x, eig, dict(_stats_dicts(st, bufs, 1)[0], rc=rc)
 
     def solve_next(self, B, eig, tol: float, storage=DL_FP64, batched=0, x0=None, max_mvp=None,
                    reliable_every=None, net=None, graph=False, inner_drop=None, eig_storage=DL_FP64,
-                   net_prec=DL_FP32, method=0, minres_window=0):
+                   net_prec=DL_FP32, method=0, minres_window=0, history=0):
         B = _c128(B)
         nrhs = B.shape[0]
         X = _empty_like(B) if x0 is None else _c128(x0).copy()
@@ -306,12 +352,12 @@ class Operator:
                          int(max_mvp or 0), net.h if net is not None else None, 1 if graph else 0,
                          float(inner_drop or 0.0), int(eig_storage), int(net_prec), int(method),
                          int(minres_window))
-        st = (dl_stats * max(nrhs, 1))()
+        st, bufs = _stats(nrhs, history)
         pB, mem = _ptr(B)
         pX, _ = _ptr(X)
         rc = _check(lib.dl_solve_next(self.h, eig.h if eig is not None else None, nrhs, pB, pX, mem, float(tol),
                                       C.byref(o), st))
-        return X, [st[i].as_dict() for i in range(nrhs)], rc
+        return X, _stats_dicts(st, bufs, nrhs), rc
 
     def eig_create(self, Vecs):
         Vecs = _c128(Vecs)
@@ -421,7 +467,7 @@ def num_weights() -> int:
 
 
 def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s=None, graph=False,
-                     storage=DL_FP32, inner_drop=None, eig_storage=DL_FP64, minres_window=0):
+                     storage=DL_FP32, inner_drop=None, eig_storage=DL_FP64, minres_window=0, history=0):
     """Later right-hand sides of several operators in one batched solve.
 
     items: sequence of (op, eig or None, B [nrhs][V][4][3], tol); all B numpy (host) or all
@@ -444,11 +490,12 @@ def solve_next_multi(ctx: Context, items, reliable_every=None, max_mvp=None, x0s
                      1 if graph else 0, float(inner_drop or 0.0), int(eig_storage), DL_FP32, 0,
                      int(minres_window))
     ntot = sum(int(B.shape[0]) for B in keep)
-    st = (dl_stats * max(ntot, 1))()
+    st, bufs = _stats(ntot, history)
     rc = _check(lib.dl_solve_next_multi(ctx.h, len(items), its, mem if mem is not None else DL_HOST, C.byref(o), st))
+    flat = _stats_dicts(st, bufs, ntot)
     out, r = [], 0
     for B in keep:
-        out.append([st[r + j].as_dict() for j in range(int(B.shape[0]))])
+        out.append(flat[r:r + int(B.shape[0])])
         r += int(B.shape[0])
     return Xs, out, rc
 

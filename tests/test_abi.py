@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     assert sorted(deflan.EXPORTED) == declared_functions()
-    assert deflan.lib.dl_version() >= 100
+    assert deflan.lib.dl_version() >= 200
     assert deflan.lib.dl_last_error() == b""
 
 
@@ -42,6 +42,9 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert rc == deflan.DL_E_INVALID
     rc = deflan.lib.dl_solve_next(None, None, 0, None, None, 0, 1e-10, None, None)
     assert rc == deflan.DL_E_INVALID  # op is NULL
+    assert deflan.lib.dl_eig_save(None, b"/nonexistent/x") == deflan.DL_E_INVALID
+    assert deflan.lib.dl_eig_load(None, b"/nonexistent/x", None) == deflan.DL_E_INVALID
+    assert deflan.lib.dl_op_fingerprint(None, None) == deflan.DL_E_INVALID
 
 
 def test_binding_structs_match_the_header(tmp_path):
