@@ -171,6 +171,10 @@ def _ptr(a):
     if torch is not None and isinstance(a, torch.Tensor):
         if not a.is_contiguous():
             raise ValueError("tensor must be contiguous")
+        if a.is_cuda:
+            # the library works on its own stream: torch's pending work on the tensor (a fill, a
+            # copy) must be done before the library reads or writes it
+            torch.cuda.current_stream(a.device).synchronize()
         return C.c_void_p(a.data_ptr()), (DL_DEVICE if a.is_cuda else DL_HOST)
     raise TypeError(f"unsupported array type {type(a)}")
 
