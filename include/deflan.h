@@ -398,6 +398,15 @@ int  dl_net_train(dl_net* net, dl_op* op, int n, const double* B, const double* 
  * Then, if `subtract`, w <- w - V c in place.  All pointers DL_HOST or DL_DEVICE. */
 int  dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w,
                     double* c, int subtract, int mem);
+/* The same projection for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): V, w and c are DEVICE
+ * pointers on ctx's device (layouts as dl_tsk_project), and the call allocates nothing -- the
+ * reduction partials live in a fixed array of the library that every GPU it runs on holds for
+ * the life of the process (8 MiB).  Limit: 2 * nv * ceil(n / 2048) <= 1048576 (every nv <= 512
+ * up to n = 2^21, nv <= 134 at n = 7962624); larger sizes return DL_E_INVALID.  The array is
+ * shared by every call on that GPU: calls that overlap on one GPU (several threads or streams
+ * at once) race and give wrong results.  Results equal dl_tsk_project's bit for bit. */
+int  dl_tsk_project_noalloc(dl_ctx* ctx, long n, int nv, const double* V, double* w, double* c, int subtract);
 /* Several columns at once (the batched deflation projection): C[r][j] = <V_j, W_r> for nv
  * vectors V ([nv][n] complex) and nw <= 16 columns W ([nw][n]); C: [nw][nv] complex.  If X
  * ([nw][n]) is not NULL, then X_r += sum_j C[r][j] V_j.  V streams once for all columns. */

@@ -218,6 +218,7 @@ int dl_ctx_create(int device, void* hip_stream, dl_ctx** out) {
       void* pin = nullptr;
       DL_HIP(hipHostMalloc(&pin, 4096 * sizeof(double), hipHostMallocDefault));
       c->pinned = static_cast<double*>(pin);
+      noalloc_init(device);  // device address of the no-allocation scratch array
     } catch (...) {
       if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
       delete c;
@@ -971,6 +972,18 @@ int dl_tsk_project(dl_ctx* ctx, long n, int nv, const double* V, double* w, doub
       if (subtract) DL_HIP(hipMemcpyAsync(w, wp, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, s));
     }
     DL_HIP(hipStreamSynchronize(s));
+    return DL_OK;
+  });
+}
+
+int dl_tsk_project_noalloc(dl_ctx* ctx, long n, int nv, const double* V, double* w, double* c, int subtract) {
+  return guard([&] {
+    need(ctx && V && w && c, "NULL argument");
+    need(n > 0 && nv > 0 && nv <= 512, "need n > 0 and 0 < nv <= 512");
+    use_device(ctx);
+    tsk_project_noalloc(ctx, n, nv, reinterpret_cast<const double2*>(V), reinterpret_cast<double2*>(w),
+                        reinterpret_cast<double2*>(c), subtract);
+    DL_HIP(hipStreamSynchronize(ctx->stream));
     return DL_OK;
   });
 }

@@ -205,6 +205,9 @@ void round_bf16(hipStream_t s, long n, const double2* a, bf2* b);    // b = bf16
 // mixed (index, bits) word per element, so it is independent of the summation order and any
 // single changed element changes it (up to 64-bit collisions).  Synchronises the stream.
 uint64_t field_hash(hipStream_t s, long n, const double2* a);
+
+// ---- the no-allocation projection (noalloc.hip) ------------------------------------
+void noalloc_init(int device);  // once per device, with the device current (context creation)
 void widen_bf16(hipStream_t s, long n, const bf2* a, double2* b);    // b = (double) a
 
 }  // namespace dl

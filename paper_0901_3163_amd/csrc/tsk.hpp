@@ -42,4 +42,8 @@ int tsk_dots_lowp(hipStream_t s, long n, int nv, const bf2* base, long ld, const
                   const int* active, double* part);
 int tsk_lowp_nblocks(long n, int prec);
 
+// c = V^H w (and w -= V c if subtract) with the partials in the library's fixed per-device
+// array; device pointers only; no allocation (noalloc.hip).
+int tsk_project_noalloc(dl_ctx* ctx, long n, int nv, const double2* V, double2* w, double2* c, int subtract);
+
 }  // namespace dl

@@ -119,6 +119,7 @@ def _load():
         "dl_eig_vectors": (I, [P, P, I]),
         "dl_eig_destroy": (None, [P]),
         "dl_tsk_project": (I, [P, L, I, P, P, P, I, I]),
+        "dl_tsk_project_noalloc": (I, [P, L, I, P, P, P, I]),
         "dl_tsk_combine": (I, [P, L, I, P, P, I, P, I]),
         "dl_tsk_project_multi": (I, [P, L, I, P, I, P, P, P, I]),
         "dl_tsk_project_lowp": (I, [P, I, L, I, P, I, P, P, P, I]),
@@ -149,7 +150,7 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
             "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower",
-            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load")
+            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load", "dl_tsk_project_noalloc")
 
 
 def _check(rc):
@@ -514,6 +515,22 @@ def dl_tsk_project(ctx: Context, V, w, subtract: bool = False):
     pw, _ = _ptr(w)
     pc, _ = _ptr(c)
     _check(lib.dl_tsk_project(ctx.h, int(V.shape[1]), int(V.shape[0]), pV, pw, pc, 1 if subtract else 0, mem))
+    return c, w
+
+
+def dl_tsk_project_noalloc(ctx: Context, V, w, c, subtract: bool = False):
+    """dl_tsk_project with no device allocation: V [nv][n], w [n] and c [nv] are complex128
+    device tensors owned by the caller; c receives V^H w and, if subtract, w <- w - V c in place."""
+    ptrs = []
+    for a in (V, w, c):
+        p, mem = _ptr(a)
+        if mem != DL_DEVICE:
+            raise ValueError("dl_tsk_project_noalloc takes device tensors only")
+        ptrs.append(p)
+    if V.dim() != 2 or w.shape != (V.shape[1],) or c.shape != (V.shape[0],):
+        raise ValueError("shapes must be V [nv][n], w [n], c [nv]")
+    _check(lib.dl_tsk_project_noalloc(ctx.h, int(V.shape[1]), int(V.shape[0]), ptrs[0], ptrs[1], ptrs[2],
+                                      1 if subtract else 0))
     return c, w
 
 
