@@ -157,15 +157,24 @@ def layer_backward_data(U, W, g_out, dims):
     return g
 
 
-def loss_and_grad(U, w, b, x, dims, M, Mdag):
+def loss_and_grad(U, w, b, x, dims, M, Mdag, Y=None, H=None):
     """L = ||M (net(b) - x)||^2 / ||b||^2 and its real gradient w.r.t. the weights.
 
-    M, Mdag: callables on [V, 4, 3] spinors.
+    M, Mdag: callables on [V, 4, 3] spinors.  With a basis Y ([12 V, k], orthonormal columns)
+    and H = Y^H M^dag M Y, the error d = net(b) - x is first replaced by what the D-CG start
+    (guess, then the Galerkin projection over Y, Section 2) leaves of it,
+    d' = d - Y H^-1 Y^H M^dag M d.  That map is the M^dag M-orthogonal projector Q onto the
+    complement of span Y, so Q^H A Q = A Q (A = M^dag M) and the gradient of ||M Q d||^2 with
+    respect to d is A Q d = M^dag (M d'): the backward pass below is the same in both cases.
     """
     Ws = split_weights(w)
     y, c = forward(U, w, b, dims, keep=True)
     bn2 = np.real(np.vdot(b, b))
-    r = M(y - x)
+    d = y - x
+    if Y is not None and Y.shape[1] > 0:
+        g = Y.conj().T @ Mdag(M(d)).ravel()
+        d = d - (Y @ np.linalg.solve(H, g)).reshape(d.shape)
+    r = M(d)
     L = float(np.real(np.vdot(r, r)) / bn2)
     g_y = 2.0 * Mdag(r) / bn2
     g3 = c["s"] * g_y

@@ -184,3 +184,66 @@ def test_forward_with_rounded_middle_layer():
     yb = ptc.forward_lowp(U, w, b, DIMS, lowp.round_bf16)
     rel = np.linalg.norm(yb - y) / np.linalg.norm(y)
     assert 1e-5 < rel < 2e-2
+
+
+def _proj_setup(k):
+    U = su3_links(DIMS, 20)
+    w = ptc.init_weights(21, scale=1.0)
+    b = gaussian_spinor(DIMS, 22)
+    x = gaussian_spinor(DIMS, 23) * 0.3
+    op = dirac.WilsonOperator(U, DIMS, 0.12)
+    M = lambda v: op.M(v.ravel()).reshape(v.shape)
+    Mdag = lambda v: op.Mdag(v.ravel()).reshape(v.shape)
+    Md = dirac.dense(op.M, op.n)
+    lam, Z = np.linalg.eigh(Md.conj().T @ Md)
+    Y = Z[:, :k]
+    H = Y.conj().T @ (Md.conj().T @ (Md @ Y))
+    return U, w, b, x, M, Mdag, Md, lam, Y, H
+
+
+def test_projected_loss_closed_form_over_exact_eigenvectors():
+    """Over exact eigenvectors y_i of M^dag M (eigenvalues sigma_i^2) the projection removes
+    sigma_i^2 |y_i^H d|^2 from ||M d||^2 (the A-orthogonal projection's Pythagoras), and over the
+    whole eigenbasis nothing is left."""
+    U, w, b, x, M, Mdag, Md, lam, Y, H = _proj_setup(40)
+    d = (ptc.forward(U, w, b, DIMS) - x).ravel()
+    bn2 = np.real(np.vdot(b, b))
+    want = (np.linalg.norm(Md @ d) ** 2 - np.sum(lam[:40] * np.abs(Y.conj().T @ d) ** 2)) / bn2
+    L, _ = ptc.loss_and_grad(U, w, b, x, DIMS, M, Mdag, Y=Y, H=H)
+    assert abs(L - want) <= 1e-12 * abs(want)
+    L0, _ = ptc.loss_and_grad(U, w, b, x, DIMS, M, Mdag)
+    assert L < L0
+    full = np.linalg.eigh(Md.conj().T @ Md)[1]
+    Hf = full.conj().T @ (Md.conj().T @ (Md @ full))
+    Lf, Gf = ptc.loss_and_grad(U, w, b, x, DIMS, M, Mdag, Y=full, H=Hf)
+    assert Lf < 1e-20 and np.max(np.abs(Gf)) < 1e-8
+
+
+@pytest.mark.parametrize("layer", [0, 2, None])
+def test_projected_gradient_matches_central_differences(layer):
+    """The backward pass of the projected loss (seeded with M^dag M d') against central
+    differences of the projected loss over a basis that is not an eigenbasis (random orthonormal)."""
+    U, w, b, x, M, Mdag, Md, lam, _, _ = _proj_setup(1)
+    rng = np.random.default_rng(25)
+    Y, _ = np.linalg.qr(rng.standard_normal((Md.shape[0], 30)) + 1j * rng.standard_normal((Md.shape[0], 30)))
+    A = Md.conj().T @ Md
+    H = Y.conj().T @ A @ Y
+    L, G = ptc.loss_and_grad(U, w, b, x, DIMS, M, Mdag, Y=Y, H=H)
+    d = rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape)
+    if layer is not None:
+        sizes = [9 * ptc.WIDTHS[l + 1] * ptc.WIDTHS[l] for l in range(3)]
+        lo = sum(sizes[:layer])
+        mask = np.zeros(w.shape, bool)
+        mask[lo:lo + sizes[layer]] = True
+        d[~mask] = 0
+    eps = 1e-6
+    P = np.eye(A.shape[0]) - Y @ np.linalg.solve(H, Y.conj().T @ A)  # dense projector, built apart
+
+    def loss(wv):
+        e = P @ (ptc.forward(U, wv, b, DIMS) - x).ravel()
+        return np.linalg.norm(Md @ e) ** 2 / np.real(np.vdot(b, b))
+
+    assert abs(loss(w) - L) <= 1e-12 * L
+    fd = (loss(w + eps * d) - loss(w - eps * d)) / (2 * eps)
+    an = np.sum(np.real(G) * np.real(d) + np.imag(G) * np.imag(d))
+    assert abs(fd - an) <= 1e-7 * max(abs(fd), 1e-3 * L)
