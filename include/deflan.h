@@ -387,6 +387,15 @@ int  dl_net_apply_prec(dl_net* net, dl_op* op, int prec, int nrhs, const double*
  * grad (host complex128, may be NULL) = dloss/dRe W + i dloss/dIm W.  b_j = 0 is invalid. */
 int  dl_net_loss_grad(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem,
                       double* loss, double* grad);
+/* Train on the error the D-CG start leaves (eig != NULL) or on the raw error (eig = NULL, the
+ * default).  With eig, every later dl_net_loss_grad / dl_net_train on eig's operator replaces
+ * d = net(b_j) - x_j by d' = d - Y H^-1 Y^H M^dag M d (Y the eigenvectors of eig, H = Y^H M^dag M Y):
+ * the error left after the Galerkin projection that follows the guess (Section 2), in the norm
+ * CG minimises, instead of the raw error, much of which the projection removes anyway.  eig must
+ * be a DL_MDAGM handle of this context, must outlive those calls, and must belong to the operator
+ * they are given (DL_E_MISMATCH otherwise); call again with the next field's handle when training
+ * moves to another gauge field. */
+int  dl_net_set_projection(dl_net* net, const dl_eig* eig);
 /* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the same loss; step s uses
  * the pairs [g*batch, (g+1)*batch) with g = s mod (n / batch).  losses ([steps], host, may
  * be NULL) receives each step's minibatch loss before the update.  1 <= batch <= n. */

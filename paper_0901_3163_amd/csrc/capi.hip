@@ -696,6 +696,16 @@ int dl_net_apply_prec(dl_net* net, dl_op* op, int prec, int nrhs, const double* 
   return net_apply_prec(net, op, prec, nrhs, B, Y, mem);
 }
 
+int dl_net_set_projection(dl_net* net, const dl_eig* eig) {
+  return guard([&] {
+    need(net != nullptr, "net is NULL");
+    need(!eig || eig->ctx == net->ctx, "eigenvector handle and network belong to different contexts");
+    need(!eig || eig->kind == DL_MDAGM, "the projected training loss is the D-CG one (M^dag M eigenvectors)");
+    net->proj = eig;
+    return DL_OK;
+  });
+}
+
 int dl_net_loss_grad(dl_net* net, dl_op* op, int n, const double* B, const double* X, int mem, double* loss,
                      double* grad) {
   return guard([&] {

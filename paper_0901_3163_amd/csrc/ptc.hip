@@ -16,6 +16,8 @@
 // weight gradient G_W[h][o][i] = sum_x sum_c G_out[o](x)_c conj((T_h in[i])(x)_c)
 // is accumulated per 64-site chunk from LDS in FP64 and reduced in a fixed order.
 #include "ptc.hpp"
+#include "small.hpp"
+#include "tsk.hpp"
 #include "cplx.hpp"
 
 #include <algorithm>
@@ -632,6 +634,59 @@ void net_apply(dl_net* net, dl_op* op, int nitems, const double2* B, double2* Y6
   DL_HIP(hipGetLastError());
 }
 
+// d' = d - Y H^-1 Y^H (M^dag M d) for the error fields d (FP32, in acts.g4): the part of the
+// guess's error that the D-CG start (net(b), then the Galerkin projection over Y) leaves.  The
+// loss ||M d'||^2 then has gradient M^dag M d' with respect to d (the projection is orthogonal
+// in the M^dag M inner product), so the backward pass below is unchanged.
+__global__ void k_negate(long n, double2* a) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    a[i] = make_double2(-a[i].x, -a[i].y);
+}
+
+static void project_error(dl_net* net, dl_op* op, int nitems) {
+  const dl_eig* e = net->proj;
+  if (e->fingerprint != op->fingerprint || e->kind != op->kind)
+    fail(DL_E_MISMATCH, "the training projection's eigenvectors belong to another operator");
+  if (op->kind != DL_MDAGM) fail(DL_E_INVALID, "the projected training loss is the D-CG one (M^dag M operators)");
+  hipStream_t s = net->ctx->stream;
+  const Lattice& lat = op->lat;
+  const long n = lat.nc, tot = (long)nitems * n;
+  NetActs& a = net->acts;
+  const float2* U = op_links32_public(op);
+  const WilsonCfg cfg = wilson_cfg(op, DL_FP32, nitems);
+  // A d (FP32 stencils) in a.g16a, widened; d widened
+  wilson_batched<float>(s, lat, U, op->kappa, 0, a.g4.get(), a.r.get(), n, nitems, 0, nullptr, nullptr, nullptr, cfg);
+  wilson_batched<float>(s, lat, U, op->kappa, 1, a.r.get(), a.g16a.get(), n, nitems, 0, nullptr, nullptr, nullptr,
+                        cfg);
+  DBuf<double2> ad((size_t)tot), d64((size_t)tot);
+  widen_f64(s, tot, a.g16a.get(), ad.get());
+  widen_f64(s, tot, a.g4.get(), d64.get());
+  const int k = e->k;
+  constexpr int kCols = 16, kRows = 64;
+  DBuf<double> part((size_t)2 * kRows * kCols * tsk_multi_nblocks(n) + 64);
+  DBuf<double2> cbuf(2 * (size_t)nitems * k);
+  for (int c0 = 0; c0 < nitems; c0 += kCols) {
+    const int nw = std::min(kCols, nitems - c0);
+    for (int j0 = 0; j0 < k; j0 += kRows) {
+      const int nv = std::min(kRows, k - j0);
+      const int np = tsk_dots_multi(s, n, nv, e->Y.get() + (long)j0 * n, n, ad.get() + (long)c0 * n, n, nw, nullptr,
+                                    part.get());
+      for (int r = 0; r < nw; ++r)
+        sum_partials(s, part.get() + (size_t)2 * r * nv * np, np, 2 * nv,
+                     reinterpret_cast<double*>(cbuf.get() + (long)(c0 + r) * k + j0));
+    }
+  }
+  double2* D = cbuf.get() + (long)nitems * k;
+  proj_solve(s, k, nitems, e->Zr.get(), e->lamr.get(), cbuf.get(), D);
+  hipLaunchKernelGGL(k_negate, dim3(64), dim3(256), 0, s, (long)nitems * k, D);
+  for (int c0 = 0; c0 < nitems; c0 += kCols) {
+    const int nw = std::min(kCols, nitems - c0);
+    tsk_update_multi(s, n, k, e->Y.get(), n, D + (long)c0 * k, nw, nullptr, d64.get() + (long)c0 * n, n);
+  }
+  round_f32(s, tot, d64.get(), a.g4.get());
+  DL_HIP(hipGetLastError());
+}
+
 double net_loss_grad(dl_net* net, dl_op* op, int nitems, const double2* B, const double2* X, bool grad) {
   hipStream_t s = net->ctx->stream;
   const Lattice& lat = op->lat;
@@ -642,6 +697,7 @@ double net_loss_grad(dl_net* net, dl_op* op, int nitems, const double2* B, const
   forward(net, op, nitems, B, a.y.get(), grad);
   // d = net(b) - x; r = M d; loss = mean ||r||^2 / ||b||^2
   hipLaunchKernelGGL(k_sub_f32_f64, dim3(kStreamBlocks, nitems), dim3(256), 0, s, a.y.get(), X, a.g4.get(), n);
+  if (net->proj && net->proj->k > 0) project_error(net, op, nitems);
   wilson_batched<float>(s, lat, U, op->kappa, 0, a.g4.get(), a.r.get(), n, nitems, 0, nullptr, nullptr, nullptr,
                         wilson_cfg(op, DL_FP32, nitems));
   hipLaunchKernelGGL(k_norm2_items_f32, dim3(kStreamBlocks, nitems), dim3(kBlock), 0, s, a.r.get(), n, a.part.get());

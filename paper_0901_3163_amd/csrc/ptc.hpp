@@ -33,6 +33,7 @@ struct dl_net {
   long step = 0;           // Adam steps taken
   dl::DBuf<unsigned> frag16; // BF16 matrix-core operands of the 16 -> 16 layer (built per inference)
   dl::NetActs acts;
+  const dl_eig* proj = nullptr;  // training loss over the error left after this Galerkin projection
 };
 
 namespace dl {
@@ -41,6 +42,8 @@ namespace dl {
 // layer's channel mixing with BF16 operands on the matrix cores (FP32 accumulation).
 void net_apply(dl_net* net, dl_op* op, int nitems, const double2* B, double2* Y64, bool bf16 = false);
 // Mean over items of ||M (net(b) - x)||^2 / ||b||^2; with grad, net->G holds its real gradient.
+// With net->proj set (eigenvectors Y of op's M^dag M, H = Y^H M^dag M Y), the error d = net(b) - x
+// is first replaced by what the D-CG start leaves of it, d' = d - Y H^-1 Y^H M^dag M d.
 double net_loss_grad(dl_net* net, dl_op* op, int nitems, const double2* B, const double2* X, bool grad);
 // One Adam step on net->W from net->G (bias-corrected, beta1 0.9, beta2 0.999, eps 1e-8).
 void net_adam_step(dl_net* net, float lr);

@@ -134,6 +134,7 @@ def _load():
         "dl_net_apply_prec": (I, [P, P, I, I, P, P, I]),
         "dl_net_loss_grad": (I, [P, P, I, P, P, I, C.POINTER(D), P]),
         "dl_net_train": (I, [P, P, I, P, P, I, I, I, D, P]),
+        "dl_net_set_projection": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -150,7 +151,7 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
             "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower",
-            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load", "dl_tsk_project_noalloc")
+            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load", "dl_tsk_project_noalloc", "dl_net_set_projection")
 
 
 def _check(rc):
@@ -444,6 +445,10 @@ class Net:
         _check(lib.dl_net_loss_grad(self.h, op.h, int(B.shape[0]), pB, pX, mem, C.byref(L),
                                     g.ctypes.data_as(C.c_void_p) if grad else None))
         return L.value, g
+
+    def set_projection(self, eig):
+        """Train on the error left after the Galerkin projection over eig (None: the raw error)."""
+        _check(lib.dl_net_set_projection(self.h, eig.h if eig is not None else None))
 
     def train(self, op: "Operator", B, X, batch: int, steps: int, lr: float):
         """Adam steps on the pairs (B, X); returns the per-step minibatch losses."""

@@ -187,7 +187,9 @@ def test_training_lowers_loss_and_guess_helps_solve(gpu_ctx, c1_config):
         assert stn[i]["relres"] <= 1e-10 and r <= 1.0001e-10
         assert _rel(Xn[i], Xh[i]) < 1e-6
         assert stn[i]["guess"] == 1 and stp[i]["guess"] == 0
-    assert sum(s["iters"] for s in stn) <= 1.05 * sum(s["iters"] for s in stp)
+    # the learned start saves iterations on pairs it was not trained on
+    assert sum(s["iters"] for s in stn) < sum(s["iters"] for s in stp), ([s["iters"] for s in stn],
+                                                                        [s["iters"] for s in stp])
     # BF16 inference of the guess: the same solutions to tol, the learned start still kept
     Xb, stb, rc = op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net,
                                 net_prec=deflan.DL_BF16)
@@ -196,9 +198,85 @@ def test_training_lowers_loss_and_guess_helps_solve(gpu_ctx, c1_config):
         r = np.linalg.norm(Bh[i].ravel() - ora.M(Xb[i].ravel())) / np.linalg.norm(Bh[i])
         assert stb[i]["relres"] <= 1e-10 and r <= 1.0001e-10
         assert stb[i]["guess"] == 1
-    assert sum(s["iters"] for s in stb) <= 1.05 * sum(s["iters"] for s in stp)
+    assert sum(s["iters"] for s in stb) < sum(s["iters"] for s in stp)
     with pytest.raises(deflan.DeflanError):
         op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net, net_prec=7)
+    eig.close()
+    net.close()
+    op.close()
+
+
+def test_projected_loss_and_gradient_match_oracle(gpu_ctx, c1_config):
+    """The D-CG training loss over the error left after the Galerkin projection (dl_net_set_projection)
+    against the oracle's projected loss and gradient, on the near-critical 4^4 field with the 20
+    lowest dense eigenvectors of M^dag M as the basis (computed by the oracle side and handed to
+    the library as a handle)."""
+    from paper_0901_3163_amd import deflan
+    c1 = c1_config
+    dims, U, kappa = c1["dims"], c1["links"], c1["kappa"]
+    ora, M, Mdag = _ops(dims, U, kappa)
+    Md = dirac.dense(ora.M, ora.n)
+    A = Md.conj().T @ Md
+    Y = np.linalg.eigh(A)[1][:, :20]
+    H = Y.conj().T @ A @ Y
+    w = ptc.init_weights(51, scale=1.0)
+    B = np.stack([gaussian_spinor(dims, 52 + i) for i in range(2)])
+    X = np.stack([0.4 * gaussian_spinor(dims, 60 + i) for i in range(2)])
+    res = [ptc.loss_and_grad(U, w, B[i], X[i], dims, M, Mdag, Y=Y, H=H) for i in range(2)]
+    L_orc, G_orc = float(np.mean([r[0] for r in res])), np.mean([r[1] for r in res], axis=0)
+    L_raw = float(np.mean([ptc.loss_and_grad(U, w, B[i], X[i], dims, M, Mdag)[0] for i in range(2)]))
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_MDAGM)
+    eig = op.eig_create(Y.T.reshape(20, ora.V, 4, 3).copy())
+    net = deflan.Net(gpu_ctx, w)
+    net.set_projection(eig)
+    L, G = net.loss_grad(op, B, X)
+    assert L < L_raw
+    assert abs(L - L_orc) <= 1e-4 * L_orc, (L, L_orc)
+    assert _rel(G, G_orc) < 1e-3
+    net.set_projection(None)
+    L2, _ = net.loss_grad(op, B, X, grad=False)
+    assert abs(L2 - L_raw) <= 1e-5 * L_raw
+    # a handle of another operator is refused when the loss is formed
+    op2 = deflan.Operator(gpu_ctx, dims, U, kappa * 0.99, deflan.DL_MDAGM)
+    net.set_projection(eig)
+    with pytest.raises(deflan.DeflanError) as ei:
+        net.loss_grad(op2, B, X)
+    assert ei.value.code == deflan.DL_E_MISMATCH
+    net.set_projection(None)
+    op2.close()
+    eig.close()
+    net.close()
+    op.close()
+
+
+def test_projected_training_gains_iterations_in_dcg(gpu_ctx, c1_config):
+    """D-CG (M^dag M): trained on 8 pairs with the projected loss over the Lan-DR eigenvectors,
+    the guess gives held-out right-hand sides a start that needs strictly fewer CG iterations
+    than the projection alone (and every solution reaches tol)."""
+    from paper_0901_3163_amd import deflan
+    c1 = c1_config
+    dims, U, kappa = c1["dims"], c1["links"], c1["kappa"]
+    ora, B, X = _c1_pairs(c1, range(500, 508))
+    _, Bh, Xh = _c1_pairs(c1, range(600, 606))
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_MDAGM)
+    _, eig, _ = op.solve_first(gaussian_spinor(dims, 100), 60, 20, 1e-10)
+    net = deflan.Net(gpu_ctx, ptc.init_weights(7))
+    net.set_projection(eig)
+    L0, _ = net.loss_grad(op, Bh, Xh, grad=False)
+    losses = net.train(op, B, X, batch=4, steps=150, lr=3e-3)
+    assert np.all(np.isfinite(losses))
+    L1, _ = net.loss_grad(op, Bh, Xh, grad=False)
+    assert L1 < 0.5 * L0, (L0, L1)
+    Xp, stp, rc = op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1)
+    assert rc == deflan.DL_OK
+    Xn, stn, rc = op.solve_next(Bh, eig, 1e-10, storage=deflan.DL_FP32, batched=1, net=net)
+    assert rc == deflan.DL_OK
+    for i in range(len(Bh)):
+        r = np.linalg.norm(Bh[i].ravel() - ora.M(Xn[i].ravel())) / np.linalg.norm(Bh[i])
+        assert stn[i]["relres"] <= 1e-10 and r <= 1.0001e-10
+    it_n, it_p = [s["iters"] for s in stn], [s["iters"] for s in stp]
+    assert sum(it_n) < sum(it_p), (it_n, it_p)
+    net.set_projection(None)
     eig.close()
     net.close()
     op.close()
