@@ -1,24 +1,26 @@
 """Benchmark: later right-hand sides per second to rel. residual 1e-10, plus Wilson Dslash HBM GB/s.
 
-Workload (one GPU): the 16^3 x 32 near-critical Wilson lattice (links
-U = exp(0.5 i X), seed 0; kappa from the oracle's kappa search, min|lambda(gamma5 M)|
-~ 1e-4).  Setup, untimed and reported separately: MinRes-DR(120,60) on gamma5 M
-for a Gaussian first right-hand side (seed 200), and the training of the
-learned-guess network on 24 point sources at other sites of the same field.
-One timed step: D-MinRes for the 12 spin-colour point sources e_{site 0, spin s,
-colour c} on the fast path (Krylov vectors and stencil spinors in BF16 -- or FP32
-with --storage fp32 -- FP32 arithmetic and links, all 12 rhs together, FP64 true
-residuals, projection and solution, learned initial guess), every one verified by
-its FP64 true residual <= 1e-10.  Inputs and outputs stay in HBM (torch complex128
-device tensors passed as device pointers).  The ablation (each storage with and
-without the guess) and the plain FP64 one-rhs-at-a-time D-MinRes are timed after it.
+Workload (one GPU), the learned-guess held-out set: 16^3 x 32 Wilson lattices with links
+U = exp(0.5 i X), one kappa tuned on links seed 10 to min|lambda(gamma5 M)| = 1e-3; training
+fields 10-17, held-out fields 20-23.  Setup, untimed and reported separately: Lan-DR(m,k) on
+M^dag M for a Gaussian first right-hand side of every field (eigenvectors lowered to FP32),
+256 Gaussian (b, x) pairs per training field solved to tol by the batched path, and the
+network trained on them in FP32 on the GPU with the loss on the error the D-CG projection
+leaves.  One timed step: D-CG for the 4 held-out fields x 64 Gaussian right-hand sides (each
+field's 64 in one batch) on the fast path: BF16 Krylov vectors and stencil spinors, FP32
+arithmetic and links, FP64 reliable updates, true residuals and solutions, the Galerkin
+projection over the field's FP32-rounded eigenvectors and the learned guess, every rhs verified
+by its FP64 true residual <= 1e-10.  Inputs and outputs stay in HBM (torch complex128 device
+tensors passed as device pointers).  After it: an ablation (storage, eigenvector precision,
+network) and the baseline, plain FP64 D-CG one rhs at a time over the same eigenvectors and rhs.
 
-value = 12 * steps / timed seconds (RHS/s).  roofline: the batched stencil, its
-average launch duration taken with HIP events on the library's stream around every
-launch inside the timed region, algorithmic bytes per launch = 288 B/site (FP32
-links once) + 96 (BF16) or 192 (FP32) B/site per active rhs (input and output
-spinor).  cpu_baseline: the oracle's D-MinRes on the host cores for a bounded
-sample of the same workload.  --multi: the uneven multi-lattice batch instead.
+value = 256 * steps / timed seconds (RHS/s).  roofline: the batched BF16 stencil, its average
+launch duration taken with HIP events on the library's stream around every launch inside the
+timed region; algorithmic bytes per launch = 288 B/site (FP32 links once) + 96 B/site per active
+rhs (BF16 input and output spinor).  cpu_baseline: the oracle's D-CG on the host cores for a
+bounded sample of the same workload.  c2: the plain-method configuration (16^3 x 32 at
+min|lambda| = 1e-4, MinRes-DR then batched D-MinRes on 12 point sources) as extra keys.
+Study modes (--multi, --precision, --ksweep, --learned, --window-sweep) print their own line.
 """
 from __future__ import annotations
 
@@ -60,9 +62,9 @@ def wilson_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(dims, storage):
+def traffic_from_profiles(dims, storage, nrhs=12):
     """HBM bytes per Wilson launch from the committed rocprofv3 counter summary, if current."""
-    p = os.path.join(ROOT, "profiles", f"wilson_{storage}_nrhs12_16x16x16x32_traffic.json")
+    p = os.path.join(ROOT, "profiles", f"wilson_{storage}_nrhs{nrhs}_{'x'.join(map(str, dims))}_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -92,20 +94,35 @@ def dslash_sweep(ctx, deflan, sizes, reps):
         op = deflan.Operator(ctx, dims, U, 0.13, deflan.DL_G5M)
         del U
         torch.cuda.empty_cache()
-        for prec, pname in ((deflan.DL_FP64, "fp64"), (deflan.DL_FP32, "fp32")):
+        for prec, pname in ((deflan.DL_FP64, "fp64"), (deflan.DL_FP32, "fp32"), (deflan.DL_BF16, "bf16")):
             for nrhs in (1, 12):
-                variant, order, _ = op.tune_wilson(prec, nrhs, reps=5)  # the project's autotuner
-                op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, 2)  # warm-up
-                ms, by = op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, reps)
-                gbs = by / (ms * 1e-3) / 1e9
                 key = f"{'x'.join(map(str, dims))}/{pname}/nrhs{nrhs}"
-                out[key] = dict(bytes_per_launch=by, avg_us=round(ms * 1e3, 1), GBps=round(gbs, 1),
-                                frac=round(gbs / HBM_PEAK_GBS, 4), working_set_MB=round(by / 1e6, 1),
-                                cache_resident=by < 256e6, tuned_variant=variant, tuned_order=order)
-                log(f"dslash {key}: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s")
+                out[key] = dslash_point(op, deflan, prec, nrhs, reps)
         op.close()
         torch.cuda.empty_cache()
     return out
+
+
+def dslash_point(op, deflan, prec, nrhs, reps):
+    """One stencil configuration: tuned launch shape, event-timed average over reps launches."""
+    variant, order, _ = op.tune_wilson(prec, nrhs, reps=5)  # the project's autotuner
+    op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, 2)  # warm-up
+    ms, by = op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, reps)
+    gbs = by / (ms * 1e-3) / 1e9
+    log(f"dslash {'x'.join(map(str, op.dims))} prec {prec} nrhs {nrhs}: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s")
+    return dict(bytes_per_launch=by, avg_us=round(ms * 1e3, 1), GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                working_set_MB=round(by / 1e6, 1), cache_resident=by < 256e6, tuned_variant=variant,
+                tuned_order=order)
+
+
+def copy_ceiling(ctx, nbytes=1 << 30, reps=20):
+    """The library's streaming copy kernel over 1 GiB (read + write): the practical HBM ceiling."""
+    ctx.bench_copy(nbytes, 2)
+    ms = ctx.bench_copy(nbytes, reps)
+    gbs = 2.0 * nbytes / (ms * 1e-3) / 1e9
+    log(f"copy kernel: {gbs:.0f} GB/s over {nbytes >> 20} MiB")
+    return dict(bytes_per_launch=2 * nbytes, avg_us=round(ms * 1e3, 1), GBps=round(gbs, 1),
+                frac=round(gbs / HBM_PEAK_GBS, 4))
 
 
 def cpu_baseline(dims, kappa, iters_per_rhs, k):
@@ -673,6 +690,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--pairs", type=int, default=256, help="training pairs per training field")
+    ap.add_argument("--test-rhs", type=int, default=64, help="right-hand sides per held-out field")
+    ap.add_argument("--plain-rhs", type=int, default=8, help="rhs per held-out field of the plain FP64 baseline")
+    ap.add_argument("--epochs", type=int, default=2, help="passes of the network training over the fields")
+    ap.add_argument("--reorth", choices=("full", "kept"), default="full",
+                    help="re-orthogonalisation of the first-rhs Lan-DR runs")
+    ap.add_argument("--no-c2", action="store_true", help="skip the plain-method (C2) extra keys")
+    ap.add_argument("--c2-steps", type=int, default=3, help="timed steps of the C2 extra keys")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain FP64 baseline")
     ap.add_argument("--m", type=int, default=120)
     ap.add_argument("--k", type=int, default=60)
@@ -683,7 +708,7 @@ def main():
     ap.add_argument("--kernel-only", action="store_true", help="run only the dominant kernel + a copy (profiling)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--train-rhs", type=int, default=24, help="training pairs of the learned guess (0: no net)")
-    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-steps", type=int, default=100, help="Adam steps per field and pass")
     ap.add_argument("--train-batch", type=int, default=6)
     ap.add_argument("--train-lr", type=float, default=3e-3)
     ap.add_argument("--net-seed", type=int, default=7)
@@ -736,11 +761,277 @@ def main():
     if args.window_sweep:
         return window_sweep(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
-    import torch
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    from lattice_inputs import gaussian_spinor, su3_links
-    from paper_0901_3163_amd import deflan
+    return c5_headline(args)
 
+
+def cpu_baseline_dcg(dims, kappa, seed, b_host, iters_per_rhs, k):
+    """Oracle D-CG on the host cores for a bounded sample: the Galerkin projection over k seeded
+    orthonormal vectors and 60 CGLS iterations on one right-hand side of the held-out workload
+    (numpy vectors, the OpenMP C Wilson matrix), scaled to the GPU's iterations per rhs."""
+    from lattice_inputs import su3_links
+    from oracle import cwilson, deflated, krylov
+    cores = len(os.sched_getaffinity(0))
+    op = cwilson.CWilson(su3_links(dims, seed), dims, kappa)
+    n = op.n
+    rng = np.random.default_rng(7)
+    Y, _ = np.linalg.qr(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    b = np.ascontiguousarray(b_host.ravel())
+    t0 = time.time()
+    H = deflated.projection_matrix(op.MdagM, Y)  # once per handle, not per rhs
+    t_h = time.time() - t0
+    nit = 60
+    t0 = time.time()
+    x0 = deflated.galerkin_projection(Y, H, op.Mdag(b))
+    t_proj = time.time() - t0
+    t0 = time.time()
+    krylov.cgls(op.M, op.Mdag, b, x0=x0, tol=0.0, maxiter=nit)
+    t_it = (time.time() - t0) / nit
+    per_rhs = t_proj + iters_per_rhs * t_it
+    return dict(value=round(1.0 / per_rhs, 5), unit="RHS/s", cores=cores, kind="oracle",
+                sample=(f"oracle D-CG (numpy vectors, OpenMP C Wilson matrix) on {'x'.join(map(str, dims))}, held-out "
+                        f"field {seed}: Galerkin projection of M^dag b over {k} seeded orthonormal vectors "
+                        f"({t_proj:.2f}s) + {nit} CGLS iterations ({t_it * 1e3:.1f} ms/iter) on one right-hand side "
+                        f"of the workload; per-rhs time = projection + {iters_per_rhs:.0f} iterations (the plain FP64 "
+                        f"GPU run's mean per rhs); H = Y^H A Y setup ({t_h:.1f}s) excluded like the GPU's"),
+                seconds_per_rhs=round(per_rhs, 3))
+
+
+def c5_headline(args):
+    """The learned-guess configuration, on which the metric is quoted: 16^3x32 Wilson, one kappa
+    (tuned on links seed 10 to min|lambda(gamma5 M)| = 1e-3) for training fields 10-17 and
+    held-out fields 20-23.  Setup (untimed, reported): per field Lan-DR(m,k) on M^dag M for a
+    Gaussian first rhs (eigenvectors lowered to FP32); per training field 256 Gaussian (b, x) pairs
+    solved to tol by the batched path; the network trained on them in FP32 on the GPU (Adam), with
+    the loss on the error the D-CG projection leaves.  One timed step: D-CG for the 4 held-out
+    fields x 64 Gaussian rhs, each field's 64 rhs in one batch: BF16 Krylov vectors and stencil
+    spinors (FP32 arithmetic and links), FP64 true residuals and solutions, the Galerkin projection
+    over the field's FP32-rounded eigenvectors, and the learned guess (BF16 inference of its middle
+    layer); every rhs verified by its FP64 true residual <= tol.  Baseline: plain FP64 D-CG one rhs
+    at a time over the same FP64 eigenvectors and right-hand sides."""
+    import torch
+    from lattice_inputs import gaussian_spinor, gaussian_spinors_device, net_weights, su3_links
+    from paper_0901_3163_amd import deflan
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    e = kappa_for("16x16x16x32/seed10")
+    dims, kappa, tol = tuple(e["dims"]), e["kappa"], args.tol
+    V = int(np.prod(dims))
+    m, k = args.m, args.k
+    reorth = deflan.DL_REORTH_KEPT if args.reorth == "kept" else deflan.DL_REORTH_FULL
+    npair, ntest, bs = args.pairs, args.test_rhs, 64
+    ctx = deflan.Context(0)
+    BF, F32, F64 = deflan.DL_BF16, deflan.DL_FP32, deflan.DL_FP64
+
+    def field(seed):
+        U = torch.from_numpy(su3_links(dims, seed, e["eps"])).cuda()
+        op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_MDAGM)
+        del U
+        t0 = time.time()
+        b1 = torch.from_numpy(gaussian_spinor(dims, 1000 + seed)).cuda()
+        _, eig, st1 = op.solve_first(b1, m, k, tol, reorth=reorth)
+        eig.lower(F32)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        log(f"field {seed}: Lan-DR({m},{k}) {st1['mvp']} MVPs ({st1['mvp_lin']} to tol), {dt:.1f}s, "
+            f"rule {st1['stop_rule']}")
+        return op, eig, dict(seed=seed, mvp=st1["mvp"], mvp_lin=st1["mvp_lin"], seconds=round(dt, 2),
+                             relres=st1["relres"], stop_rule=st1["stop_rule"])
+
+    def solve(op, eig, B, **kw):
+        X = torch.empty_like(B)
+        its, kept, ok = [], [], True
+        for i in range(0, B.shape[0], bs):
+            Xi, sts, rc = op.solve_next(B[i:i + bs], eig, tol, batched=1, **kw)
+            X[i:i + bs] = Xi
+            its += [s["iters"] for s in sts]
+            kept += [s["guess"] for s in sts]
+            ok &= rc == deflan.DL_OK and all(s["relres"] <= tol for s in sts)
+        return X, its, kept, ok
+
+    # ---- setup: training fields, pairs, network ----
+    t_setup = time.time()
+    train, first = [], []
+    t_pairs = 0.0
+    pair_iters = []
+    for seed in range(10, 18):
+        op, eig, info = field(seed)
+        first.append(info)
+        B = gaussian_spinors_device(dims, 20000 + 1000 * seed, npair)
+        t0 = time.time()
+        X, its, _, ok = solve(op, eig, B, storage=BF, eig_storage=F32)
+        torch.cuda.synchronize()
+        t_pairs += time.time() - t0
+        pair_iters += its
+        assert ok, f"training pairs of field {seed} did not reach tol"
+        train.append((op, eig, B, X))
+        log(f"field {seed}: {npair} training pairs in {time.time() - t0:.1f}s, {np.mean(its):.0f} iterations per rhs")
+    net = deflan.Net(ctx, net_weights(args.net_seed))
+    t0 = time.time()
+    losses = []
+    for ep in range(args.epochs):
+        for op, eig, B, X in train:
+            net.set_projection(eig)
+            losses += list(net.train(op, B, X, batch=args.train_batch, steps=args.train_steps, lr=args.train_lr))
+    net.set_projection(None)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"network: {len(losses)} Adam steps in {t_train:.1f}s, loss {losses[0]:.4f} -> {np.mean(losses[-20:]):.4f}")
+    for op, eig, B, X in train:
+        eig.close()
+        op.close()
+    del train, B, X
+    torch.cuda.empty_cache()
+    held = []
+    for seed in range(20, 24):
+        op, eig, info = field(seed)
+        first.append(info)
+        # stencil launch shapes of every configuration timed below, tuned here (untimed)
+        for prec, nr in ((BF, ntest), (F32, ntest), (F64, ntest), (F64, 1)):
+            op.tune_wilson(prec, nr, reps=3)
+        held.append((op, eig, gaussian_spinors_device(dims, 40000 + 1000 * seed, ntest), seed))
+    setup_s = time.time() - t_setup
+
+    fast_kw = dict(storage=BF, eig_storage=F32, net=net, net_prec=BF)
+
+    def step(**kw):
+        its, kept, ok = [], [], True
+        for op, eig, B, _ in held:
+            _, it, kp, o = solve(op, eig, B, **kw)
+            its += it
+            kept += kp
+            ok &= o
+        return its, kept, ok
+
+    for w in range(args.warmup):
+        its, _, _ = step(**fast_kw)
+        log(f"warmup {w}: {np.mean(its):.1f} iterations per rhs")
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.time()
+    all_ok, iters, kept = True, [], []
+    for s_ in range(args.steps):
+        its, kp, ok = step(**fast_kw)
+        all_ok &= ok
+        iters += its
+        kept += kp
+        log(f"step {s_}: {np.mean(its):.1f} iterations per rhs, all converged {ok}")
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    n_w, ms_w, by_w = ctx.kernel_time("wilson")
+    ctx.timing(False)
+    nrhs_step = len(held) * ntest
+    value = nrhs_step * args.steps / dt
+    log(f"fast path: {value:.2f} RHS/s")
+
+    # ---- ablation: each factor on one pass over the held-out set ----
+    ablation = {}
+    for name, kw in (("bf16+proj_fp32", dict(storage=BF, eig_storage=F32)),
+                     ("bf16+proj_fp64", dict(storage=BF, eig_storage=F64)),
+                     ("fp32+proj_fp32", dict(storage=F32, eig_storage=F32)),
+                     ("fp32+proj_fp32+net", dict(storage=F32, eig_storage=F32, net=net, net_prec=F32)),
+                     ("bf16+proj_fp32+net_fp32", dict(storage=BF, eig_storage=F32, net=net, net_prec=F32))):
+        torch.cuda.synchronize()
+        t1 = time.time()
+        its, kp, ok = step(**kw)
+        torch.cuda.synchronize()
+        d1 = time.time() - t1
+        ablation[name] = dict(value=round(nrhs_step / d1, 3), unit="RHS/s", iters_per_rhs=float(np.mean(its)),
+                              all_rhs_converged=bool(ok), guess_kept=float(np.mean(kp)) if "net" in kw else None)
+        log(f"ablation {name}: {nrhs_step / d1:.2f} RHS/s, {np.mean(its):.1f} iterations per rhs")
+    proj_only = ablation["bf16+proj_fp32"]
+
+    # ---- baseline: plain FP64 D-CG, one rhs at a time, same eigenvectors (FP64) and rhs ----
+    log("plain FP64 D-CG baseline")
+    op0, eig0, B0, _ = held[0]
+    op0.solve_next(B0[:1], eig0, tol)  # warm-up
+    torch.cuda.synchronize()
+    t1 = time.time()
+    its64, ok64, n64 = [], True, 0
+    for op, eig, B, _ in held:
+        _, sts, rc = op.solve_next(B[:args.plain_rhs], eig, tol)
+        its64 += [s_["iters"] for s_ in sts]
+        ok64 &= rc == deflan.DL_OK and all(s_["relres"] <= tol for s_ in sts)
+        n64 += args.plain_rhs
+    torch.cuda.synchronize()
+    d64 = time.time() - t1
+    plain_value = n64 / d64
+    log(f"plain FP64 D-CG {plain_value:.2f} RHS/s; fast path {value / plain_value:.2f}x")
+
+    achieved = by_w / (ms_w * 1e-3) / 1e9 if ms_w > 0 else 0.0
+    bpl = by_w / max(n_w, 1)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(dims, "bf16", ntest),
+                    kernel=("Wilson stencil (M and M^dag of D-CG), BF16 spinors, FP32 links and arithmetic, batched "
+                            f"over the {ntest} rhs of a held-out field (tuned launch shape)"),
+                    launches=n_w, avg_us=round(ms_w / max(n_w, 1) * 1e3, 2), bytes_per_launch=round(bpl),
+                    note=(f"algorithmic bytes per launch: links once (288 B/site FP32) + input and output spinor "
+                          f"per active rhs (96 B/site BF16); {round(bpl / 1e6)} MB on average per launch "
+                          f"({V * (288 + 96 * ntest) / 1e6:.0f} MB with all {ntest} rhs active), above the 256 MB "
+                          "Infinity Cache"))
+    result = dict(metric=METRIC, value=round(value, 3), unit="RHS/s", n_gpus=1, steps=args.steps,
+                  warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 2), higher_is_better=True,
+                  scaling="weak", vs_baseline=None, dtype="bf16/f32+f64",
+                  data="synthetic (seeded SU(3) gauge fields and Gaussian right-hand sides)",
+                  config=dict(workload=(f"learned-guess held-out set: 16^3x32 Wilson, kappa {kappa:.7f} tuned on "
+                                        f"links seed 10 (min|lambda(gamma5 M)| {e['min_abs_eig']:.2e}), network "
+                                        f"trained on {8 * npair} (b, x) pairs from D-CG on fields 10-17, tested on "
+                                        f"held-out fields 20-23 x {ntest} Gaussian rhs; Lan-DR({m},{k}) on M^dag M "
+                                        f"per field, then D-CG from net(b) + projection, tol {tol:g}"),
+                              lattice=list(dims), kappa=kappa, training_fields=list(range(10, 18)),
+                              held_out_fields=list(range(20, 24)), rhs_per_field=ntest, m=m, k=k,
+                              reorth=args.reorth,
+                              path=("batched D-CG (CG on M^dag M x = M^dag b), the 64 rhs of a field in one batch: "
+                                    "BF16 Krylov vectors and Wilson apply (FP32 arithmetic and links), FP64 "
+                                    "reliable updates and true residuals, FP64 solution, Galerkin projection over "
+                                    "the FP32-rounded eigenvectors (FP64 arithmetic), learned initial guess (BF16 "
+                                    "matrix-core inference of the 16->16 layer; net(b) + projection, kept per rhs "
+                                    "when its residual is smaller)")),
+                  all_rhs_converged=bool(all_ok), iters_per_rhs=float(np.mean(iters)),
+                  guess_kept_per_rhs=float(np.mean(kept)),
+                  learned_guess=dict(training_pairs=8 * npair, pair_seconds=round(t_pairs, 2),
+                                     pair_iters_per_rhs=float(np.mean(pair_iters)), epochs=args.epochs,
+                                     steps_per_field=args.train_steps, batch=args.train_batch, lr=args.train_lr,
+                                     adam_steps=len(losses), train_seconds=round(t_train, 2),
+                                     loss_first=round(float(losses[0]), 5),
+                                     loss_last20=round(float(np.mean(losses[-20:])), 5),
+                                     loss="mean ||M d'||^2 / ||b||^2, d' = the error of net(b) left after the D-CG "
+                                          "Galerkin projection over the field's eigenvectors",
+                                     iters_saved_per_rhs=round(proj_only["iters_per_rhs"] - float(np.mean(iters)), 2),
+                                     rhs_per_s_vs_projection_only=round(value / proj_only["value"], 4)),
+                  ablation=ablation,
+                  plain_fp64=dict(value=round(plain_value, 3), unit="RHS/s", rhs=n64,
+                                  all_rhs_converged=bool(ok64), iters_per_rhs=float(np.mean(its64)),
+                                  path=f"D-CG FP64, one rhs after another (first {args.plain_rhs} rhs of each "
+                                       "held-out field)"),
+                  speedup_vs_plain_fp64=round(value / plain_value, 3),
+                  first_rhs=first, setup_seconds=round(setup_s, 1),
+                  roofline=roofline)
+    if not args.no_sweep:
+        result["dslash_sweep"] = dslash_sweep(ctx, deflan, [(24, 24, 24, 48), (32, 32, 32, 64)], reps=20)
+        result["dslash_sweep"]["16x16x16x32/bf16/nrhs64"] = dslash_point(held[0][0], deflan, deflan.DL_BF16, ntest, 20)
+        result["copy_ceiling"] = copy_ceiling(ctx)
+    if not args.no_c2:
+        result["c2"] = c2_workload(args, ctx, deflan)
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        op_h, _, B_h, seed_h = held[0]
+        result["cpu_baseline"] = cpu_baseline_dcg(dims, kappa, seed_h, B_h[0].cpu().numpy(),
+                                                  result["plain_fp64"]["iters_per_rhs"], k)
+    for op, eig, B, _ in held:
+        eig.close()
+        op.close()
+    net.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def c2_workload(args, ctx, deflan):
+    """The plain-method configuration (16^3x32 near-critical, min|lambda| ~ 1e-4, seed 0):
+    MinRes-DR(m,k) on gamma5 M for a Gaussian first rhs, then the 12 spin-colour point sources
+    by the batched BF16 D-MinRes (with a network trained on 24 point sources of the same field)
+    and by plain FP64 D-MinRes one rhs at a time.  Returns a dict (extra keys of the benchmark
+    line)."""
+    import torch
+    from lattice_inputs import gaussian_spinor, su3_links
     try:
         e = kappa_for("16x16x16x32")
     except KeyError:
@@ -750,8 +1041,7 @@ def main():
     if kappa is None:
         sys.exit("no kappa stored for 16x16x16x32: run `python -m oracle.kappa large`")
     V = int(np.prod(dims))
-    ctx = deflan.Context(0)
-    log(f"workload 16^3x32 kappa={kappa:.7f}: building operator")
+    log(f"C2 workload 16^3x32 kappa={kappa:.7f}: building operator")
     U = torch.from_numpy(su3_links(dims, e["seed"], e["eps"])).cuda()
     op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_G5M)
     b1 = torch.from_numpy(gaussian_spinor(dims, 200)).cuda()
@@ -791,7 +1081,7 @@ def main():
     def plain():
         return op.solve_next(B, eig, args.tol)
 
-    for w in range(args.warmup):
+    for w in range(1):
         X, sts, rc = fast()
         log(f"warmup {w} (batched FP32{' + learned guess' if net else ''}): iters {[s['iters'] for s in sts]}")
     torch.cuda.synchronize()
@@ -799,7 +1089,7 @@ def main():
     t0 = time.time()
     all_ok = True
     iters, kept = [], []
-    for s in range(args.steps):
+    for s in range(args.c2_steps):
         X, sts, rc = fast()
         all_ok &= all(st["relres"] <= args.tol for st in sts)
         iters += [st["iters"] for st in sts]
@@ -809,7 +1099,7 @@ def main():
     dt = time.time() - t0
     n_w, ms_w, by_w = ctx.kernel_time("wilson")
     ctx.timing(False)
-    value = nrhs * args.steps / dt
+    value = nrhs * args.c2_steps / dt
     # ablation: the batched path with each storage, with and without the learned guess
     ablation = {}
     if net is not None:
@@ -861,10 +1151,8 @@ def main():
     plain_value = nrhs * args.plain_steps / dt64
     ok64 = all(st["relres"] <= args.tol for st in st64)
     log(f"fast {value:.2f} RHS/s, plain FP64 {plain_value:.2f} RHS/s")
-    result = dict(metric=METRIC, value=round(value, 3), unit="RHS/s", n_gpus=1, steps=args.steps,
-                  warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 2), higher_is_better=True,
-                  scaling="weak", vs_baseline=None, dtype=("f32+f64" if args.storage == "fp32" else "bf16/f32+f64"),
-                  data="synthetic",
+    result = dict(value=round(value, 3), unit="RHS/s", steps=args.c2_steps,
+                  ms_per_step=round(dt / args.c2_steps * 1e3, 2),
                   config=dict(workload=f"16^3x32 Wilson near-critical (kappa {kappa:.6f}), MinRes-DR({args.m},"
                                        f"{args.k}) on gamma5 M then D-MinRes on 12 point sources, tol "
                                        f"{args.tol:g}", lattice=list(dims), kappa=kappa, nrhs=nrhs,
@@ -891,20 +1179,11 @@ def main():
                                  relres=st1["relres"], stop_rule=st1["stop_rule"],
                                  mvp_overhead=round(st1["mvp"] / max(st1["mvp_lin"], 1), 3)),
                   roofline=roofline)
-    if not args.no_sweep:
-        result["dslash_sweep"] = dslash_sweep(ctx, deflan, [(24, 24, 24, 48), (32, 32, 32, 64)], reps=20)
-    if not args.no_proj_sweep:
-        result["projection_sweep"] = projection_sweep(ctx, deflan, [(dims, args.k), ((24, 24, 24, 48), 100)], reps=5)
-    if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(dims, kappa, result["plain_fp64"]["iters_per_rhs"], args.k)
     if net is not None:
         net.close()
     eig.close()
     op.close()
-    ctx.close()
-    print(json.dumps(result), flush=True)
-
+    return result
 
 if __name__ == "__main__":
     main()

@@ -284,6 +284,12 @@ int  dl_solve_next(dl_op* op, const dl_eig* eig, int nrhs, const double* B,
  * once).  Allocates and frees its own fields. */
 int  dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* avg_ms, double* bytes);
 
+/* Measurement: average duration (ms) of the library's streaming copy kernel moving `bytes`
+ * bytes (rounded down to 16-byte elements) between two device buffers, over `reps`
+ * event-timed launches (each moves 2 * bytes through HBM: one read, one write): the practical
+ * bandwidth ceiling the stencil is compared with.  Allocates and frees its own buffers. */
+int  dl_bench_copy(dl_ctx* ctx, long bytes, int reps, double* avg_ms);
+
 /* Autotuner: time every launch shape of the Wilson stencil (threads per block,
  * occupancy hint, block order) for this operator's lattice in precision `prec`
  * with `nrhs` right-hand sides (reps event-timed launches each), keep the

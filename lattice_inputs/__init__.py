@@ -71,6 +71,17 @@ def gaussian_spinor(dims, seed: int) -> np.ndarray:
     return re + 1j * im
 
 
+def gaussian_spinors_device(dims, seed: int, n: int, device="cuda"):
+    """n complex Gaussian spinor fields [n][V][4][3] (re, im ~ N(0,1)), complex128, drawn on a
+    torch device by torch's seeded generator: the bulk right-hand sides of the benchmark (thousands
+    of fields, where host draws would dominate the run)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    x = torch.randn((n, volume(dims), 4, 3, 2), generator=g, device=device, dtype=torch.float64)
+    return torch.view_as_complex(x)
+
+
 def point_source(dims, site: int, spin: int, colour: int) -> np.ndarray:
     """Unit spin-colour point source e_{site, spin, colour}, complex128 [V][4][3]."""
     b = np.zeros((volume(dims), 4, 3), dtype=np.complex128)

@@ -602,6 +602,32 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
   });
 }
 
+int dl_bench_copy(dl_ctx* ctx, long bytes, int reps, double* avg_ms) {
+  return guard([&] {
+    need(ctx && avg_ms, "NULL argument");
+    need(bytes >= 16 && reps >= 1, "need bytes >= 16 and reps >= 1");
+    use_device(ctx);
+    hipStream_t s = ctx->stream;
+    const long n = bytes / 16;
+    DBuf<double2> a(n), b(n);
+    zero(s, n, a.get());
+    copy(s, n, a.get(), b.get());
+    hipEvent_t e0, e1;
+    DL_HIP(hipEventCreate(&e0));
+    DL_HIP(hipEventCreate(&e1));
+    DL_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) copy(s, n, a.get(), b.get());
+    DL_HIP(hipEventRecord(e1, s));
+    DL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    DL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / reps;
+    return DL_OK;
+  });
+}
+
 int dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* order, double* best_us) {
   return guard([&] {
     need(op != nullptr, "op is NULL");

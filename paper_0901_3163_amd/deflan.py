@@ -111,6 +111,7 @@ def _load():
         "dl_solve_next": (I, [P, P, I, P, P, I, D, C.POINTER(dl_next_opts), C.POINTER(dl_stats)]),
         "dl_eig_create": (I, [P, I, P, I, C.POINTER(P)]),
         "dl_bench_wilson": (I, [P, I, I, I, I, C.POINTER(D), C.POINTER(D)]),
+        "dl_bench_copy": (I, [P, L, I, C.POINTER(D)]),
         "dl_apply_batched": (I, [P, I, I, I, P, P, I]),
         "dl_solve_next_multi": (I, [P, I, C.POINTER(dl_batch_item), I, C.POINTER(dl_next_opts),
                                     C.POINTER(dl_stats)]),
@@ -151,7 +152,7 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
             "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower",
-            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load", "dl_tsk_project_noalloc", "dl_net_set_projection")
+            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load", "dl_tsk_project_noalloc", "dl_net_set_projection", "dl_bench_copy")
 
 
 def _check(rc):
@@ -216,6 +217,12 @@ class Context:
         n, ms, by = C.c_long(), C.c_double(), C.c_double()
         _check(lib.dl_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
+
+    def bench_copy(self, nbytes: int, reps: int = 20):
+        """Milliseconds per launch of the library's copy kernel over nbytes (read once, written once)."""
+        ms = C.c_double()
+        _check(lib.dl_bench_copy(self.h, int(nbytes), int(reps), C.byref(ms)))
+        return ms.value
 
     def close(self):
         if getattr(self, "h", None):
