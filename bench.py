@@ -559,29 +559,29 @@ def multi_lattice(args):
 
 
 def kernel_only(args):
-    """The dominant kernel alone, for rocprofv3 counter runs: the gamma5 M stencil (--storage
-    spinors) on the 16^3x32 lattice for 12 right-hand sides at once (reps launches), then a device copy of
-    1 GiB (reps launches) whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    """The dominant kernel alone, for rocprofv3 counter runs: the stencil of the headline path
+    (M, BF16 spinors -- or --storage fp32 -- FP32 links) on held-out field 20 of the learned-guess
+    workload (16^3x32) for its 64 right-hand sides at once (reps launches, tuned shape), then the
+    library's copy kernel over 1 GiB (reps launches), whose FETCH_SIZE / WRITE_SIZE calibrate the
+    counters."""
     import torch
+    from lattice_inputs import su3_links
     from paper_0901_3163_amd import deflan
-    e = kappa_for("16x16x16x32")
+    e = kappa_for("16x16x16x32/seed10")
     dims = tuple(e["dims"])
+    nrhs = args.test_rhs
     ctx = deflan.Context(0)
-    op = deflan.Operator(ctx, dims, torch.from_numpy(tiled_links(dims)).cuda(), e["kappa"], deflan.DL_G5M)
+    op = deflan.Operator(ctx, dims, torch.from_numpy(su3_links(dims, 20, e["eps"])).cuda(), e["kappa"],
+                         deflan.DL_MDAGM)
     prec = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.storage]
-    ms, by = op.bench_wilson(deflan.DL_APPLY_G5M, prec, 12, args.reps)
-    log(f"wilson {args.storage} nrhs12: {ms * 1e3:.1f} us/launch, algorithmic {by / 1e6:.1f} MB/launch")
-    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
-    y = torch.empty_like(x)
-    x.fill_(1.0)
-    for _ in range(args.reps):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    log("copy: 1 GiB read + 1 GiB written per launch")
-    print(json.dumps(dict(kernel=f"Wilson stencil gamma5 M, {args.storage} spinors", dims=list(dims), nrhs=12,
-                          reps=args.reps,
-                          avg_us=round(ms * 1e3, 2), algorithmic_bytes=by, copy_bytes=1 << 30,
-                          source_hash=wilson_source_hash())))
+    op.tune_wilson(prec, nrhs, reps=3)
+    ms, by = op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, args.reps)
+    log(f"wilson {args.storage} nrhs{nrhs}: {ms * 1e3:.1f} us/launch, algorithmic {by / 1e6:.1f} MB/launch")
+    cms = ctx.bench_copy(1 << 30, args.reps)
+    log(f"copy: 1 GiB read + 1 GiB written per launch, {cms * 1e3:.1f} us")
+    print(json.dumps(dict(kernel=f"Wilson stencil M, {args.storage} spinors", dims=list(dims), nrhs=nrhs,
+                          reps=args.reps, avg_us=round(ms * 1e3, 2), algorithmic_bytes=by,
+                          copy_bytes=1 << 30, copy_avg_us=round(cms * 1e3, 2), source_hash=wilson_source_hash())))
     op.close()
     ctx.close()
 

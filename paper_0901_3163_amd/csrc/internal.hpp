@@ -150,7 +150,9 @@ void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, d
 // (8, 8), (2, 8); 11-14 = the marching form with each slice's spinors staged in LDS (11: with
 // the x, y links too, FP32 only; T = 8, 8, 16, 8; 14 issues each hop's loads one hop ahead); order = block order (0: rhs fastest, XCD-contiguous; 1: sites
 // fastest, XCD-contiguous; 2: rhs fastest, hardware order).  Chosen by the autotuner.
-constexpr int kWilsonVariants = 15;
+// 15-17 = one thread per site for 2 or 4 rhs of a group (256 threads; 2 rhs with 128 threads), each
+// hop's link loaded once for the group.
+constexpr int kWilsonVariants = 18;
 constexpr int kWilsonOrders = 3;
 struct WilsonCfg {
   int variant = 0;

@@ -795,13 +795,132 @@ k_wilson_tml(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
   }
 }
 
+// Several right-hand sides per thread: a thread owns one site and RT consecutive rhs of a
+// group; each hop's link is loaded once into registers and applied to the RT neighbour
+// spinors, so links and neighbour offsets are read and computed once per site for the group
+// (the one-rhs-per-block forms read each site's links once per rhs, from L2 at best) and the
+// RT spinor loads of a hop are independent and in flight together.  Logical block = (site
+// block, rhs group), order as k_wilson.  Same arithmetic and hop order as k_wilson per rhs.
+template <class R, class SV, int WHICH, int RED, int NT, int RT>
+__global__ void __launch_bounds__(NT)
+k_wilson_mr(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
+            SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
+            int Lt, long V, long Vpad, int nbs, int ngroups, int order, const double* __restrict__ scale,
+            const int* __restrict__ active, double* __restrict__ part) {
+  using C = typename CT<R>::type;
+  const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int rg = order == 1 ? lb / nbs : lb % ngroups;
+  const int sb = order == 1 ? lb % nbs : lb / ngroups;
+  const int r0 = rg * RT;
+  bool on[RT];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < RT; ++j) {
+    on[j] = r0 + j < nrhs && (!active || active[r0 + j]);
+    any |= on[j];
+  }
+  if (!any) return;
+  const int site = sb * NT + (int)threadIdx.x;
+  double red[RT];
+#pragma unroll
+  for (int j = 0; j < RT; ++j) red[j] = 0.0;
+  if (site >= V && site < Vpad) {
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+      if (on[j]) {
+        SV* op = out + (r0 + j) * fstride + sp_base(site);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sst(op + c * kTile, CT<R>::make(0, 0));
+      }
+  }
+  if (site < V) {
+    const int x = site % Lx;
+    const int y = (site / Lx) % Ly;
+    const int z = (site / (Lx * Ly)) % Lz;
+    const int t = site / (Lx * Ly * Lz);
+    const int sy = Lx, sz = Lx * Ly, st = Lx * Ly * Lz;
+    const int fx = x == Lx - 1 ? 1 - Lx : 1, bx = x == 0 ? Lx - 1 : -1;
+    const int fy = y == Ly - 1 ? (1 - Ly) * sy : sy, by = y == 0 ? (Ly - 1) * sy : -sy;
+    const int fz = z == Lz - 1 ? (1 - Lz) * sz : sz, bz = z == 0 ? (Lz - 1) * sz : -sz;
+    const int ft = t == Lt - 1 ? (1 - Lt) * st : st, bt = t == 0 ? (Lt - 1) * st : -st;
+    C acc[RT][12];
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[j][c] = CT<R>::make(0, 0);
+    constexpr int SF = (WHICH == 1) ? 1 : -1;
+#pragma unroll 1
+    for (int hh = 0; hh < 8; ++hh) {
+      const int mu = hh >> 1;
+      const bool fwd = (hh & 1) == 0;
+      const int d = fwd ? (mu == 0 ? fx : mu == 1 ? fy : mu == 2 ? fz : ft)
+                        : (mu == 0 ? bx : mu == 1 ? by : mu == 2 ? bz : bt);
+      const int nb = site + d;
+      C u[9];
+      const C* up = U + lk_base(fwd ? site : nb, mu);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = up[e * kTile];
+      const SV* pb = in + sp_base(nb);
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        if (!on[j]) continue;
+        C p[12], h[6], g[6];
+        const SV* pp = pb + (r0 + j) * fstride;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = sld(pp + c * kTile);
+        if (fwd) {
+          project_mu<SF>(mu, p, h);
+          mul_half<false>(u, h, g);
+          reconstruct_mu<SF>(mu, acc[j], g);
+        } else {
+          project_mu<-SF>(mu, p, h);
+          mul_half<true>(u, h, g);
+          reconstruct_mu<-SF>(mu, acc[j], g);
+        }
+      }
+    }
+    const R mk = (R)(-kappa);
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+      if (!on[j]) continue;
+      const R sc = scale ? (R)scale[r0 + j] : (R)1;
+      const SV* ip = in + (r0 + j) * fstride + sp_base(site);
+      SV* op = out + (r0 + j) * fstride + sp_base(site);
+      R sred = 0;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const C p = sld(ip + c * kTile);
+        C r = CT<R>::make(fma(mk, acc[j][c].x, p.x) * sc, fma(mk, acc[j][c].y, p.y) * sc);
+        if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
+        sst(op + c * kTile, r);
+        if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
+        if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
+      }
+      if (RED == 1) red[j] = (double)sred;
+      if (RED == 2) red[j] = (double)sred * sc;
+    }
+  }
+  if (RED != 0) {
+    __shared__ double lds[NT / 64];
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+      if (!on[j]) continue;  // uniform over the block
+      const double s = block_sum<NT>(red[j], lds);
+      if (threadIdx.x == 0) part[(long)(r0 + j) * nbs + sb] = s;
+      __syncthreads();  // lds is reused by the next rhs's sum
+    }
+  }
+}
+
 // Launch-shape variants.  0-3: k_wilson with (threads per block, occupancy hint)
 // {(256,2), (128,2), (512,1), (256,1)}; 4-6: k_wilson_tm, 256 threads per block, time
 // chunks of T = 4, 8, 16 slices; 7-10: k_wilson_tml with 64 sites per block and
 // (rhs per block, T) = (4, 8), (4, 16), (8, 8), (2, 8).
-static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64, 256, 256, 256, 256};
-static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8, 8, 8, 16, 8};
-static constexpr int kVariantRB[kWilsonVariants] = {0, 0, 0, 0, 0, 0, 0, 4, 4, 8, 2, 0, 0, 0, 0};
+// 15-17: k_wilson_mr with (threads per block, rhs per thread) = (256, 2), (256, 4), (128, 2).
+static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64, 256, 256, 256, 256,
+                                                    256, 256, 128};
+static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8, 8, 8, 16, 8, 0, 0, 0};
+static constexpr int kVariantRT[kWilsonVariants] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 2};
 
 static int tm_nb3(const Lattice& lat, int v) {
   return (lat.L[0] * lat.L[1] * lat.L[2] + kVariantNT[v] - 1) / kVariantNT[v];
@@ -849,6 +968,17 @@ static void launch_tml(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, do
                      tm_nb3(lat, v), nbs, ngroups, order, scale, active, part);
 }
 
+template <class R, class SV, int WHICH, int RED, int NT, int RT>
+static void launch_mr(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const SV* in, SV* out,
+                      long fstride, int nrhs, int order, const double* scale, const int* active, double* part,
+                      int nbs) {
+  const int* L = lat.L;
+  const int ngroups = (nrhs + RT - 1) / RT;
+  hipLaunchKernelGGL((k_wilson_mr<R, SV, WHICH, RED, NT, RT>), dim3(nbs * ngroups), dim3(NT), 0, s, U, in, out,
+                     fstride, nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, nbs, ngroups, order,
+                     scale, active, part);
+}
+
 template <class R, class SV, int WHICH, int RED>
 static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa,
                            const SV* in, SV* out, long fstride, int nrhs, int order,
@@ -886,6 +1016,15 @@ static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const
       launch_tmp<R, SV, WHICH, RED, 256, false, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active,
                                                       part, nbs, variant);
       break;
+    case 15:
+      launch_mr<R, SV, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs);
+      break;
+    case 16:
+      launch_mr<R, SV, WHICH, RED, 256, 4>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs);
+      break;
+    case 17:
+      launch_mr<R, SV, WHICH, RED, 128, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs);
+      break;
     default: launch_one<R, SV, WHICH, RED, 256, 2>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active, part, nbs); break;
   }
 }
@@ -910,7 +1049,7 @@ int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double
   const int v = cfg.variant % kWilsonVariants;
   const int nbs = wilson_nbs(lat, cfg);
   if (red && nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
-  if ((long)nbs * nrhs > 2147483647L) fail(DL_E_INVALID, "grid too large");
+  if ((long)nbs * ((nrhs + kVariantRT[v] - 1) / kVariantRT[v]) > 2147483647L) fail(DL_E_INVALID, "grid too large");
   const int o = cfg.order;
 #define DL_W(WH, RD) launch_variant<R, SV, WH, RD>(v, s, lat, U, kappa, in, out, fstride, nrhs, o, scale, active, part, nbs)
   if (which == 0) { if (red == 0) DL_W(0, 0); else if (red == 1) DL_W(0, 1); else DL_W(0, 2); }

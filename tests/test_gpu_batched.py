@@ -115,7 +115,7 @@ def test_batched_bf16_storage(gpu_ctx, c1_config, kind, graph):
     op.close()
 
 
-@pytest.mark.parametrize("variant", [0, 5, 7, 9])
+@pytest.mark.parametrize("variant", [0, 5, 7, 9, 15, 16])
 def test_batched_solver_in_each_stencil_family(gpu_ctx, c1_config, variant, monkeypatch):
     """The batched FP32 D-MinRes with the stencil forced to one launch shape of each family
     (per site, time-marching, marching with LDS links for 4 and 8 rhs): active masks, fused

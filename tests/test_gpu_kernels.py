@@ -129,7 +129,7 @@ def test_tsk_project_and_combine(gpu_ctx, n, nv):
     assert _rel(Y, G.T @ V) < 1e-13
 
 
-N_VARIANTS = 15  # stencil launch shapes: 0-3 per site, 4-6 time-marching, 7-10 LDS links, 11-14 LDS slice
+N_VARIANTS = 18  # launch shapes: 0-3 per site, 4-6 time-marching, 7-10 LDS links, 11-14 LDS slice, 15-17 rhs per thread
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 16), (16, 16, 16, 32)])
