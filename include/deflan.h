@@ -59,6 +59,18 @@ extern "C" {
  * ||b - M x|| / ||b||, the paper's "residual norm for convergence of M^-1". */
 #define DL_MDAGM 0
 #define DL_G5M   1
+/* Flag OR'ed into the kind of dl_op_create: the even-odd (Schur complement) form of the same
+ * system (not in the paper; the usual production form, one step below the stencil).  With
+ * sites split by parity p(x) = (x + y + z + t) mod 2 (every extent even), M x = b is the
+ * even-site system Mhat x_e = bhat_e, Mhat = 1 - kappa^2 D_eo D_oe, bhat_e = b_e + kappa D_eo b_o,
+ * then x_o = b_o + kappa D_oe x_e (dl_eo_prepare, dl_eo_reconstruct).  Such an operator acts on
+ * even half fields, [V/2][4][3] complex128 holding the even sites in increasing site order
+ * (half index = site / 2): dl_apply applies Mhat, Mhat^dag, gamma5 Mhat, Mhat^dag Mhat, and the
+ * solvers, eigenvector handles and dl_op_size (12 V / 2) work on that system, the Hermitian forms
+ * being Mhat^dag Mhat (Lan-DR, D-CG) and gamma5 Mhat (MinRes-DR, D-MinRes; gamma5 Mhat is
+ * Hermitian since Mhat^dag = gamma5 Mhat gamma5), and tol is relative to ||bhat_e||.  Not for
+ * the network or the multi-lattice batch (DL_E_INVALID). */
+#define DL_EVEN_ODD 16
 
 #define DL_FP64 0
 #define DL_FP32 1
@@ -235,7 +247,7 @@ int  dl_kernel_time(dl_ctx* ctx, const char* name, long* launches, double* total
 
 /* ---- operator ----------------------------------------------------------- */
 /* Create the operator A of the paper for links U, hopping parameter kappa and
- * Hermitian form `kind` (DL_MDAGM or DL_G5M).  The links are converted once to
+ * Hermitian form `kind` (DL_MDAGM or DL_G5M, optionally | DL_EVEN_ODD).  The links are converted once to
  * the device's site-major tiled layout (FP64, plus FP32/BF16 copies on first
  * use).  Errors: DL_E_INVALID for dims < 2, kappa not finite, unknown kind. */
 int  dl_op_create(dl_ctx* ctx, const int dims[4], const double* links, int mem,
@@ -243,6 +255,12 @@ int  dl_op_create(dl_ctx* ctx, const int dims[4], const double* links, int mem,
 void dl_op_destroy(dl_op* op);
 /* Number of complex entries N = 12 V of one spinor. */
 long dl_op_size(const dl_op* op);
+/* Even-odd operators (DL_EVEN_ODD): bhat ([V/2][4][3]) = b_e + kappa D_eo b_o for a whole-lattice
+ * right-hand side b ([V][4][3]), and the whole-lattice solution x from the even-site solution
+ * xe: x_e = xe, x_o = b_o + kappa D_oe xe (FP64).  All pointers DL_HOST or all DL_DEVICE;
+ * DL_E_INVALID for an operator without DL_EVEN_ODD. */
+int  dl_eo_prepare(dl_op* op, const double* b, double* bhat, int mem);
+int  dl_eo_reconstruct(dl_op* op, const double* b, const double* xe, double* x, int mem);
 /* The operator's fingerprint: a hash of dims, kappa, kind and every link as stored on the
  * device (so the same links give the same value whether they came from host or device
  * memory, and a change of any one link changes it).  Eigenvector handles carry the

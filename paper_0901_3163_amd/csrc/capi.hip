@@ -47,9 +47,8 @@ void need(bool ok, const char* msg) {
 
 void use_device(dl_ctx* ctx) { DL_HIP(hipSetDevice(ctx->device)); }
 
-// nfield fields in the caller's layout -> tiled device fields at t (pads zeroed).
-void fields_in_to(dl_op* op, const double* p, int nfield, int mem, double2* t) {
-  const Lattice& lat = op->lat;
+// nfield fields in the caller's layout on lattice `lat` -> tiled device fields at t (pads zeroed).
+void fields_in_lat(dl_op* op, const Lattice& lat, const double* p, int nfield, int mem, double2* t) {
   hipStream_t s = op->ctx->stream;
   zero(s, (long)nfield * lat.nc, t);
   const size_t bytes = (size_t)nfield * lat.V * kSpin * sizeof(double2);
@@ -63,14 +62,17 @@ void fields_in_to(dl_op* op, const double* p, int nfield, int mem, double2* t) {
   }
 }
 
+void fields_in_to(dl_op* op, const double* p, int nfield, int mem, double2* t) {
+  fields_in_lat(op, op->lat, p, nfield, mem, t);
+}
+
 DBuf<double2> fields_in(dl_op* op, const double* p, int nfield, int mem) {
   DBuf<double2> t((size_t)nfield * op->lat.nc);
   fields_in_to(op, p, nfield, mem, t.get());
   return t;
 }
 
-void fields_out(dl_op* op, const double2* t, double* p, int nfield, int mem) {
-  const Lattice& lat = op->lat;
+void fields_out_lat(dl_op* op, const Lattice& lat, const double2* t, double* p, int nfield, int mem) {
   hipStream_t s = op->ctx->stream;
   const size_t bytes = (size_t)nfield * lat.V * kSpin * sizeof(double2);
   if (mem == DL_DEVICE) {
@@ -81,6 +83,10 @@ void fields_out(dl_op* op, const double2* t, double* p, int nfield, int mem) {
     DL_HIP(hipMemcpyAsync(p, stage.get(), bytes, hipMemcpyDeviceToHost, s));
   }
   DL_HIP(hipStreamSynchronize(s));
+}
+
+void fields_out(dl_op* op, const double2* t, double* p, int nfield, int mem) {
+  fields_out_lat(op, op->lat, t, p, nfield, mem);
 }
 
 uint64_t fnv(uint64_t h, const void* data, size_t n) {
@@ -189,6 +195,7 @@ struct HistoryReq {
 
 void check_net_op(const dl_net* net, const dl_op* op) {
   need(net->ctx == op->ctx, "network and operator belong to different contexts");
+  need(!op->lat.eo, "the network works on whole-lattice fields (not on an even-odd operator)");
 }
 
 }  // namespace
@@ -234,6 +241,7 @@ void dl_ctx_destroy(dl_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->timers.collect();
+  eo_release(ctx->stream);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   dl::dmem_trim(ctx->device);
@@ -282,16 +290,18 @@ int dl_op_create(dl_ctx* ctx, const int dims[4], const double* links, int mem, d
   return guard([&] {
     need(ctx && dims && links && out, "NULL argument");
     need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
-    need(kind == DL_MDAGM || kind == DL_G5M, "kind must be DL_MDAGM or DL_G5M");
+    const int base = kind & ~DL_EVEN_ODD;
+    const bool eo = (kind & DL_EVEN_ODD) != 0;
+    need(base == DL_MDAGM || base == DL_G5M, "kind must be DL_MDAGM or DL_G5M, optionally with DL_EVEN_ODD");
     need(std::isfinite(kappa), "kappa must be finite");
     use_device(ctx);
     auto* op = new dl_op();
     try {
       op->ctx = ctx;
-      op->lat = make_lattice(dims);
+      op->lat = eo ? make_lattice_eo(dims) : make_lattice(dims);
       op->kappa = kappa;
-      op->kind = kind;
-      const Lattice& lat = op->lat;
+      op->kind = base;
+      const Lattice lat = make_lattice(dims);  // the links cover the whole lattice
       hipStream_t s = ctx->stream;
       op->U.alloc(lat.nl);
       zero(s, lat.nl, op->U.get());
@@ -329,6 +339,45 @@ void dl_op_destroy(dl_op* op) {
 }
 
 long dl_op_size(const dl_op* op) { return op ? 12 * op->lat.V : 0; }
+
+int dl_eo_prepare(dl_op* op, const double* b, double* bhat, int mem) {
+  return guard([&] {
+    need(op && b && bhat, "NULL argument");
+    need(op->lat.eo, "dl_eo_prepare needs an operator created with DL_EVEN_ODD");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    use_device(op->ctx);
+    hipStream_t s = op->ctx->stream;
+    const Lattice full = make_lattice(op->lat.L);
+    DBuf<double2> bt(full.nc), be(op->lat.nc), bo(op->lat.nc), bh(op->lat.nc);
+    fields_in_lat(op, full, b, 1, mem, bt.get());
+    eo_split(s, full, bt.get(), be.get(), 0, 1);
+    eo_split(s, full, bt.get(), bo.get(), 1, 1);
+    eo_hop_f64(s, op->lat, op->U.get(), op->kappa, 0, bo.get(), be.get(), bh.get());  // b_e + kappa D_eo b_o
+    fields_out(op, bh.get(), bhat, 1, mem);
+    return DL_OK;
+  });
+}
+
+int dl_eo_reconstruct(dl_op* op, const double* b, const double* xe, double* x, int mem) {
+  return guard([&] {
+    need(op && b && xe && x, "NULL argument");
+    need(op->lat.eo, "dl_eo_reconstruct needs an operator created with DL_EVEN_ODD");
+    need(mem == DL_HOST || mem == DL_DEVICE, "mem must be DL_HOST or DL_DEVICE");
+    use_device(op->ctx);
+    hipStream_t s = op->ctx->stream;
+    const Lattice full = make_lattice(op->lat.L);
+    DBuf<double2> bt(full.nc), bo(op->lat.nc), xo(op->lat.nc), xt(full.nc);
+    DBuf<double2> xet = fields_in(op, xe, 1, mem);
+    fields_in_lat(op, full, b, 1, mem, bt.get());
+    eo_split(s, full, bt.get(), bo.get(), 1, 1);
+    eo_hop_f64(s, op->lat, op->U.get(), op->kappa, 1, xet.get(), bo.get(), xo.get());  // b_o + kappa D_oe x_e
+    zero(s, full.nc, xt.get());
+    eo_merge(s, full, xet.get(), xt.get(), 0, 1);
+    eo_merge(s, full, xo.get(), xt.get(), 1, 1);
+    fields_out_lat(op, full, xt.get(), x, 1, mem);
+    return DL_OK;
+  });
+}
 
 int dl_op_fingerprint(const dl_op* op, unsigned long long* out) {
   return guard([&] {
@@ -494,6 +543,7 @@ int dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int
       const dl_batch_item& it = items[i];
       need(it.op != nullptr, "item op is NULL");
       need(it.op->ctx == ctx, "every operator of the batch must belong to ctx");
+      need(!it.op->lat.eo, "the multi-lattice batch takes whole-lattice operators (no DL_EVEN_ODD)");
       need(it.nrhs >= 0, "item nrhs must be >= 0");
       need(it.tol > 0 && std::isfinite(it.tol), "item tol must be positive");
       if (kind < 0) kind = it.op->kind;
@@ -596,6 +646,13 @@ int dl_bench_wilson(dl_op* op, int which, int prec, int nrhs, int reps, double* 
     DL_HIP(hipEventElapsedTime(&ms, a, b));
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    if (lat.eo) {
+      // Mhat: both half stages read every link once; per rhs the input half field twice, the odd
+      // intermediate (arithmetic precision) written and read once, the output written once
+      const double linkb = prec == DL_FP64 ? 576.0 : 288.0, tmpb = prec == DL_FP64 ? 192.0 : 96.0;
+      const double spb = prec == DL_FP64 ? 192.0 : prec == DL_FP32 ? 96.0 : 48.0;
+      bb = 2.0 * (2.0 * lat.V) * linkb + (double)nrhs * lat.V * (3.0 * spb + 2.0 * tmpb);
+    }
     *avg_ms = ms / reps;
     if (bytes) *bytes = bb;
     return DL_OK;

@@ -51,13 +51,17 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 
 struct Lattice {
   int L[4];        // Lx, Ly, Lz, Lt
-  long V;          // sites
+  long V;          // sites of a field (eo: the sites of one parity, half the lattice)
   long ntiles;     // ceil(V / 64)
   long nc;         // complex elements of a padded spinor field = ntiles * 64 * 12
-  long nl;         // complex elements of padded links = ntiles * 64 * 36
+  long nl;         // complex elements of the padded links of the whole lattice
+  int eo = 0;      // 1: fields hold the even sites only (the even-odd Schur operator)
 };
 
 Lattice make_lattice(const int dims[4]);
+// The even half of the lattice of dims (every extent even): fields of V/2 sites in increasing
+// full-site order, half index = full site / 2 (tiled like a full field); links stay full.
+Lattice make_lattice_eo(const int dims[4]);
 
 // ---- device memory --------------------------------------------------------
 void* dmalloc(size_t bytes);  // cached per device (freed blocks are reused by size)
@@ -163,6 +167,17 @@ struct WilsonCfg {
 int wilson_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, int which,
                const double2* in, double2* out, int red, double* part, WilsonCfg cfg = WilsonCfg());
 void gamma5_f64(hipStream_t s, const Lattice& lat, const double2* in, double2* out);
+// Even-odd operator (lat.eo): op = Mhat = 1 - kappa^2 D_eo D_oe on the even half fields (which 0),
+// Mhat^dag (1), gamma5 Mhat (2), through an odd intermediate field in the arithmetic precision
+// held in a per-stream scratch buffer (eo_reserve grows it ahead of graph capture).
+void eo_reserve(hipStream_t s, size_t bytes);
+void eo_release(hipStream_t s);
+// Full fields (tiled, whole lattice `full`) <-> half fields (tiled, lat.eo) of parity par.
+void eo_split(hipStream_t s, const Lattice& full, const double2* in, double2* half, int par, int nfield);
+void eo_merge(hipStream_t s, const Lattice& full, const double2* half, double2* out, int par, int nfield);
+// out_{par} = kappa_fac * D_{par, 1-par} in_{1-par} + add_{par} (FP64 half fields; add may be NULL).
+void eo_hop_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa_fac, int par, const double2* in,
+                const double2* add, double2* out);
 // Batched Wilson apply in FP64 (R = double) or FP32 (R = float): nrhs fields at stride fstride.
 // Partials (red != 0) are column-major [nrhs][wilson_nbs(lat)].  Returns wilson_nbs(lat) or 0.
 int wilson_nbs(const Lattice& lat, const WilsonCfg& cfg);

@@ -147,6 +147,17 @@ Lattice make_lattice(const int dims[4]) {
   return lat;
 }
 
+Lattice make_lattice_eo(const int dims[4]) {
+  Lattice lat = make_lattice(dims);
+  for (int i = 0; i < 4; ++i)
+    if (dims[i] % 2) fail(DL_E_INVALID, "the even-odd operator needs every lattice extent even");
+  lat.eo = 1;
+  lat.V /= 2;
+  lat.ntiles = (lat.V + kTile - 1) / kTile;
+  lat.nc = lat.ntiles * kTile * kSpin;  // nl (the whole lattice's links) is kept
+  return lat;
+}
+
 hipEvent_t Timers::take() {
   if (!pool.empty()) {
     hipEvent_t e = pool.back();

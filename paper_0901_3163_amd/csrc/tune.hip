@@ -113,6 +113,11 @@ double time_cfg(dl_op* op, const cplx_t<R>* U, const SV* in, SV* out, int nrhs, 
 
 WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) {
   op->wcfg.erase(prec * 100000 + nrhs);
+  if (op->lat.eo) {  // the even-odd operator has one launch shape
+    eo_reserve(op->ctx->stream, (size_t)nrhs * op->lat.nc * (prec == DL_FP64 ? 16 : 8));
+    if (best_us) *best_us = 0.0;
+    return WilsonCfg{};
+  }
   const Lattice& lat = op->lat;
   const long n = (long)nrhs * lat.nc;
   hipEvent_t a, b;
@@ -160,6 +165,11 @@ WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) 
 }
 
 WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs) {
+  if (op->lat.eo) {
+    // one launch shape; its odd intermediate is sized here, before any graph capture
+    eo_reserve(op->ctx->stream, (size_t)nrhs * op->lat.nc * (prec == DL_FP64 ? 16 : 8));
+    return WilsonCfg{};
+  }
   // DEFLAN_WILSON_VARIANT=v or v,o forces a launch shape (checked on every call)
   if (const char* e = std::getenv("DEFLAN_WILSON_VARIANT")) {
     int v = -1, o = 0;

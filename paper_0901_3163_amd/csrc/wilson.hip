@@ -29,6 +29,8 @@
 #include "cplx.hpp"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 namespace dl {
 
@@ -1029,7 +1031,239 @@ static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const
   }
 }
 
+// ---- even-odd (Schur complement) operator ---------------------------------------------
+// Half fields hold the sites of one parity p(x) = (x + y + z + t) mod 2 in increasing full-site
+// order; with every extent even the half index of a site is site / 2.  One thread per output
+// half site; logical block = (site block, rhs), rhs fastest.
+
+template <class C>
+__device__ __forceinline__ C czero() {
+  C z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+
+// full coordinates of half site h of parity par
+__device__ __forceinline__ void eo_coords(int h, int par, int Lx, int Ly, int Lz, int& x, int& y, int& z, int& t) {
+  const int lxh = Lx >> 1;
+  const int xh = h % lxh, r = h / lxh;
+  y = r % Ly;
+  z = (r / Ly) % Lz;
+  t = r / (Ly * Lz);
+  x = 2 * xh + ((par + y + z + t) & 1);
+}
+
+// acc = D_{par, 1-par} applied at half site h (input: half field of the other parity, in storage SV)
+template <int SF, class C, class SV>
+__device__ __forceinline__ void eo_hops(const C* __restrict__ U, const SV* __restrict__ in, int h, int par, int Lx,
+                                        int Ly, int Lz, int Lt, C acc[12]) {
+  int x, y, z, t;
+  eo_coords(h, par, Lx, Ly, Lz, x, y, z, t);
+  const int sy = Lx, sz = Lx * Ly, st = Lx * Ly * Lz;
+  const int site = x + sy * y + sz * z + st * t;
+  const int fx = x == Lx - 1 ? 1 - Lx : 1, bx = x == 0 ? Lx - 1 : -1;
+  const int fy = y == Ly - 1 ? (1 - Ly) * sy : sy, by = y == 0 ? (Ly - 1) * sy : -sy;
+  const int fz = z == Lz - 1 ? (1 - Lz) * sz : sz, bz = z == 0 ? (Lz - 1) * sz : -sz;
+  const int ft = t == Lt - 1 ? (1 - Lt) * st : st, bt = t == 0 ? (Lt - 1) * st : -st;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = czero<C>();
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const int df = mu == 0 ? fx : mu == 1 ? fy : mu == 2 ? fz : ft;
+    const int db = mu == 0 ? bx : mu == 1 ? by : mu == 2 ? bz : bt;
+    hop<SF, false>(U, in, mu, (site + df) >> 1, site, acc);
+    hop<-SF, true>(U, in, mu, (site + db) >> 1, site + db, acc);
+  }
+}
+
+// Stage 1: tmp (arithmetic precision) = D_{1-par0, par0} in for the rhs of the launch.
+template <class R, class SV, int WHICH>
+__global__ void __launch_bounds__(256)
+k_eo_hop1(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in, typename CT<R>::type* __restrict__ tmp,
+          long fstride, int nrhs, int Lx, int Ly, int Lz, int Lt, long V, long Vpad, int par,
+          const int* __restrict__ active) {
+  using C = typename CT<R>::type;
+  const int rhs = (int)blockIdx.x % nrhs, sb = (int)blockIdx.x / nrhs;
+  if (active && !active[rhs]) return;
+  const int h = sb * 256 + (int)threadIdx.x;
+  C* op = tmp + rhs * fstride;
+  if (h >= V && h < Vpad) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) op[sp_base(h) + c * kTile] = czero<C>();
+  }
+  if (h >= V) return;
+  constexpr int SF = (WHICH == 1) ? 1 : -1;
+  C acc[12];
+  eo_hops<SF>(U, in + rhs * fstride, h, par, Lx, Ly, Lz, Lt, acc);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) op[sp_base(h) + c * kTile] = acc[c];
+}
+
+// Stage 2: out = scale * (in - kappa^2 D_{par, 1-par} tmp) (gamma5 on the result for WHICH 2), with
+// the fused reduction of the result (RED 1: ||out||^2, RED 2: Re<in, out>) per block.
+template <class R, class SV, int WHICH, int RED>
+__global__ void __launch_bounds__(256)
+k_eo_schur(const typename CT<R>::type* __restrict__ U, const typename CT<R>::type* __restrict__ tmp,
+           const SV* __restrict__ in, SV* __restrict__ out, long fstride, int nrhs, double kappa2, int Lx, int Ly,
+           int Lz, int Lt, long V, long Vpad, int par, int nbs, const double* __restrict__ scale,
+           const int* __restrict__ active, double* __restrict__ part) {
+  using C = typename CT<R>::type;
+  const int rhs = (int)blockIdx.x % nrhs, sb = (int)blockIdx.x / nrhs;
+  if (active && !active[rhs]) return;
+  const int h = sb * 256 + (int)threadIdx.x;
+  SV* op = out + rhs * fstride;
+  double red = 0.0;
+  if (h >= V && h < Vpad) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sst(op + sp_base(h) + c * kTile, CT<R>::make(0, 0));
+  }
+  if (h < V) {
+    constexpr int SF = (WHICH == 1) ? 1 : -1;
+    C acc[12];
+    eo_hops<SF>(U, tmp + rhs * fstride, h, par, Lx, Ly, Lz, Lt, acc);
+    const R sc = scale ? (R)scale[rhs] : (R)1;
+    const R mk = (R)(-kappa2);
+    const SV* ip = in + rhs * fstride + sp_base(h);
+    R sred = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const C p = sld(ip + c * kTile);
+      C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
+      if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
+      sst(op + sp_base(h) + c * kTile, r);
+      if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
+      if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
+    }
+    if (RED == 1) red = (double)sred;
+    if (RED == 2) red = (double)sred * sc;
+  }
+  if (RED != 0) {
+    __shared__ double lds[256 / 64];
+    const double s = block_sum<256>(red, lds);
+    if (threadIdx.x == 0) part[(long)rhs * nbs + sb] = s;
+  }
+}
+
+namespace {
+std::mutex g_eo_mu;
+std::map<hipStream_t, DBuf<char>> g_eo_scratch;
+}  // namespace
+
+void eo_reserve(hipStream_t s, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_eo_mu);
+  DBuf<char>& b = g_eo_scratch[s];
+  if (b.n < bytes) b.alloc(bytes);
+}
+
+void eo_release(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_eo_mu);
+  g_eo_scratch.erase(s);
+}
+
+static void* eo_buffer(hipStream_t s, size_t bytes) {
+  eo_reserve(s, bytes);
+  std::lock_guard<std::mutex> lk(g_eo_mu);
+  return g_eo_scratch[s].get();
+}
+
+template <class R, class SV>
+static int wilson_eo(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which, const SV* in,
+                     SV* out, long fstride, int nrhs, int red, const double* scale, const int* active, double* part) {
+  using C = cplx_t<R>;
+  const int nbs = (int)((lat.V + 255) / 256);
+  if (red && nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
+  C* tmp = static_cast<C*>(eo_buffer(s, (size_t)nrhs * fstride * sizeof(C)));
+  const int* L = lat.L;
+  const long Vpad = lat.ntiles * kTile;
+  const dim3 grid((unsigned)((long)nbs * nrhs)), block(256);
+  // stage 1: odd intermediate D_oe in (par 1 output); stage 2: even result
+#define DL_EO1(WH) hipLaunchKernelGGL((k_eo_hop1<R, SV, WH>), grid, block, 0, s, U, in, tmp, fstride, nrhs, L[0], L[1], \
+                                      L[2], L[3], lat.V, Vpad, 1, active)
+#define DL_EO2(WH, RD) hipLaunchKernelGGL((k_eo_schur<R, SV, WH, RD>), grid, block, 0, s, U, tmp, in, out, fstride, \
+                                          nrhs, kappa * kappa, L[0], L[1], L[2], L[3], lat.V, Vpad, 0, nbs, scale, \
+                                          active, part)
+  if (which == 1) DL_EO1(1); else DL_EO1(0);
+  if (which == 0) { if (red == 0) DL_EO2(0, 0); else if (red == 1) DL_EO2(0, 1); else DL_EO2(0, 2); }
+  else if (which == 1) { if (red == 0) DL_EO2(1, 0); else if (red == 1) DL_EO2(1, 1); else DL_EO2(1, 2); }
+  else { if (red == 0) DL_EO2(2, 0); else if (red == 1) DL_EO2(2, 1); else DL_EO2(2, 2); }
+#undef DL_EO1
+#undef DL_EO2
+  DL_HIP(hipGetLastError());
+  return red ? nbs : 0;
+}
+
+__global__ void k_eo_split(const double2* __restrict__ in, double2* __restrict__ half, long nc_full, long nc_half,
+                           long Vh, int par, int Lx, int Ly, int Lz) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long f = blockIdx.y;
+  if (i >= Vh * kSpin) return;
+  const int h = (int)(i / kSpin), c = (int)(i % kSpin);
+  int x, y, z, t;
+  eo_coords(h, par, Lx, Ly, Lz, x, y, z, t);
+  const int site = x + Lx * (y + Ly * (z + Lz * t));
+  half[f * nc_half + sp_base(h) + c * kTile] = in[f * nc_full + sp_base(site) + c * kTile];
+}
+
+__global__ void k_eo_merge(const double2* __restrict__ half, double2* __restrict__ out, long nc_full, long nc_half,
+                           long Vh, int par, int Lx, int Ly, int Lz) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long f = blockIdx.y;
+  if (i >= Vh * kSpin) return;
+  const int h = (int)(i / kSpin), c = (int)(i % kSpin);
+  int x, y, z, t;
+  eo_coords(h, par, Lx, Ly, Lz, x, y, z, t);
+  const int site = x + Lx * (y + Ly * (z + Lz * t));
+  out[f * nc_full + sp_base(site) + c * kTile] = half[f * nc_half + sp_base(h) + c * kTile];
+}
+
+// out = fac * D_{par, 1-par} in + add (FP64, one field)
+__global__ void __launch_bounds__(256)
+k_eo_hop_f64(const double2* __restrict__ U, const double2* __restrict__ in, const double2* __restrict__ add,
+             double2* __restrict__ out, double fac, int Lx, int Ly, int Lz, int Lt, long V, long Vpad, int par) {
+  const int h = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (h >= V && h < Vpad) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[sp_base(h) + c * kTile] = make_double2(0.0, 0.0);
+  }
+  if (h >= V) return;
+  double2 acc[12];
+  eo_hops<-1>(U, in, h, par, Lx, Ly, Lz, Lt, acc);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double2 a = add ? add[sp_base(h) + c * kTile] : make_double2(0.0, 0.0);
+    out[sp_base(h) + c * kTile] = make_double2(fma(fac, acc[c].x, a.x), fma(fac, acc[c].y, a.y));
+  }
+}
+
+void eo_split(hipStream_t s, const Lattice& full, const double2* in, double2* half, int par, int nfield) {
+  if (nfield <= 0) return;
+  const Lattice hl = make_lattice_eo(full.L);
+  const long n = hl.V * kSpin;
+  hipLaunchKernelGGL(k_eo_split, dim3((unsigned)((n + 255) / 256), nfield), dim3(256), 0, s, in, half, full.nc,
+                     hl.nc, hl.V, par, full.L[0], full.L[1], full.L[2]);
+  DL_HIP(hipGetLastError());
+}
+
+void eo_merge(hipStream_t s, const Lattice& full, const double2* half, double2* out, int par, int nfield) {
+  if (nfield <= 0) return;
+  const Lattice hl = make_lattice_eo(full.L);
+  const long n = hl.V * kSpin;
+  hipLaunchKernelGGL(k_eo_merge, dim3((unsigned)((n + 255) / 256), nfield), dim3(256), 0, s, half, out, full.nc,
+                     hl.nc, hl.V, par, full.L[0], full.L[1], full.L[2]);
+  DL_HIP(hipGetLastError());
+}
+
+void eo_hop_f64(hipStream_t s, const Lattice& lat, const double2* U, double fac, int par, const double2* in,
+                const double2* add, double2* out) {
+  const int* L = lat.L;
+  hipLaunchKernelGGL(k_eo_hop_f64, dim3((unsigned)((lat.V + 255) / 256)), dim3(256), 0, s, U, in, add, out, fac, L[0],
+                     L[1], L[2], L[3], lat.V, lat.ntiles * kTile, par);
+  DL_HIP(hipGetLastError());
+}
+
 int wilson_nbs(const Lattice& lat, const WilsonCfg& cfg) {
+  if (lat.eo) return (int)((lat.V + 255) / 256);
   const int v = cfg.variant % kWilsonVariants;
   if (kVariantT[v] > 0) return tm_nb3(lat, v) * tm_chunks(lat, v);
   const int nt = kVariantNT[v];
@@ -1046,6 +1280,7 @@ template <class R, class SV>
 int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, int which,
                    const SV* in, SV* out, long fstride, int nrhs, int red, const double* scale,
                    const int* active, double* part, WilsonCfg cfg) {
+  if (lat.eo) return wilson_eo<R, SV>(s, lat, U, kappa, which, in, out, fstride, nrhs, red, scale, active, part);
   const int v = cfg.variant % kWilsonVariants;
   const int nbs = wilson_nbs(lat, cfg);
   if (red && nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libdeflan.so")
 DL_OK, DL_NOT_CONVERGED = 0, 1
 DL_E_INVALID, DL_E_HIP, DL_E_NOMEM, DL_E_BREAKDOWN, DL_E_NONFINITE, DL_E_MISMATCH = -1, -2, -3, -4, -5, -6
 DL_MDAGM, DL_G5M = 0, 1
+DL_EVEN_ODD = 16
 DL_FP64, DL_FP32, DL_BF16 = 0, 1, 2
 DL_HOST, DL_DEVICE = 0, 1
 DL_METHOD_DEFAULT, DL_METHOD_CG = 0, 1
@@ -104,6 +105,8 @@ def _load():
         "dl_op_destroy": (None, [P]),
         "dl_op_size": (L, [P]),
         "dl_op_fingerprint": (I, [P, C.POINTER(C.c_ulonglong)]),
+        "dl_eo_prepare": (I, [P, P, P, I]),
+        "dl_eo_reconstruct": (I, [P, P, P, P, I]),
         "dl_eig_save": (I, [P, C.c_char_p]),
         "dl_eig_load": (I, [P, C.c_char_p, C.POINTER(P)]),
         "dl_apply": (I, [P, I, P, P, I]),
@@ -152,7 +155,8 @@ EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "d
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
             "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower",
-            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load", "dl_tsk_project_noalloc", "dl_net_set_projection", "dl_bench_copy")
+            "dl_net_apply_prec", "dl_op_fingerprint", "dl_eig_save", "dl_eig_load", "dl_tsk_project_noalloc", "dl_net_set_projection", "dl_bench_copy", "dl_eo_prepare",
+            "dl_eo_reconstruct")
 
 
 def _check(rc):
@@ -300,7 +304,9 @@ class Operator:
     def __init__(self, ctx: Context, dims, links, kappa: float, kind: int):
         self.ctx = ctx
         self.dims = tuple(int(d) for d in dims)
-        self.V = int(np.prod(self.dims))
+        self.eo = bool(int(kind) & DL_EVEN_ODD)
+        self.V_full = int(np.prod(self.dims))
+        self.V = self.V_full // 2 if self.eo else self.V_full  # sites of the fields it acts on
         links = _c128(links)
         p, mem = _ptr(links)
         d = (C.c_int * 4)(*self.dims)
@@ -308,7 +314,7 @@ class Operator:
         _check(lib.dl_op_create(ctx.h, d, p, mem, float(kappa), int(kind), C.byref(h)))
         self.h = h
         ctx._children.add(self)
-        self.kind = kind
+        self.kind = int(kind) & ~DL_EVEN_ODD
         self.kappa = kappa
 
     def apply(self, which: int, psi):
@@ -327,6 +333,25 @@ class Operator:
         po, _ = _ptr(out)
         _check(lib.dl_apply_batched(self.h, int(which), int(prec), int(Psi.shape[0]), pi, po, mem))
         return out
+
+    def eo_prepare(self, b):
+        """bhat = b_e + kappa D_eo b_o (even half field) for a whole-lattice b (DL_EVEN_ODD operators)."""
+        b = _c128(b)
+        bh = _empty_like(b, (self.V,) + tuple(b.shape[1:]))
+        pb, mem = _ptr(b)
+        ph, _ = _ptr(bh)
+        _check(lib.dl_eo_prepare(self.h, pb, ph, mem))
+        return bh
+
+    def eo_reconstruct(self, b, xe):
+        """The whole-lattice solution from the even-site one (DL_EVEN_ODD operators)."""
+        b, xe = _c128(b), _c128(xe)
+        x = _empty_like(b)
+        pb, mem = _ptr(b)
+        pxe, _ = _ptr(xe)
+        px, _ = _ptr(x)
+        _check(lib.dl_eo_reconstruct(self.h, pb, pxe, px, mem))
+        return x
 
     def fingerprint(self):
         f = C.c_ulonglong()
