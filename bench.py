@@ -646,6 +646,87 @@ def net_only(args):
     ctx.close()
 
 
+def evenodd_study(args):
+    """The even-odd (Schur complement) form against the whole-lattice system on held-out field 20
+    of the learned-guess workload (16^3x32, kappa tuned on field 10): Lan-DR(m,k) for a Gaussian
+    first rhs, then D-CG for 64 Gaussian rhs by plain FP64 (8 of them, one at a time) and by the
+    batched BF16 path (all 64 together, FP32-rounded eigenvectors).  The even-odd runs include
+    preparing bhat and reconstructing the whole solution; every solution is judged by its
+    whole-lattice FP64 residual.  Prints one JSON line."""
+    import torch
+    from lattice_inputs import gaussian_spinor, gaussian_spinors_device, su3_links
+    from paper_0901_3163_amd import deflan
+    os.environ.setdefault("DEFLAN_VERBOSE", "1")
+    e = kappa_for("16x16x16x32/seed10")
+    dims, kappa, tol = tuple(e["dims"]), e["kappa"], args.tol
+    ctx = deflan.Context(0)
+    U = torch.from_numpy(su3_links(dims, 20, e["eps"])).cuda()
+    full = deflan.Operator(ctx, dims, U, kappa, deflan.DL_MDAGM)
+    half = deflan.Operator(ctx, dims, U, kappa, deflan.DL_MDAGM | deflan.DL_EVEN_ODD)
+    b1 = torch.from_numpy(gaussian_spinor(dims, 1020)).cuda()
+    B = gaussian_spinors_device(dims, 60000, args.test_rhs)
+    nb = torch.linalg.vector_norm(B.reshape(B.shape[0], -1), dim=1)
+    out = dict(workload=(f"16^3x32 Wilson, held-out field 20 (kappa {kappa:.7f}), Lan-DR({args.m},{args.k}) on "
+                         f"M^dag M then D-CG for {args.test_rhs} Gaussian rhs, tol {tol:g} on the whole-lattice "
+                         "residual"), runs={})
+
+    def whole_relres(X):
+        nr = X.shape[0]
+        R = B[:nr] - full.apply_batched(deflan.DL_APPLY_M, deflan.DL_FP64, X)
+        return (torch.linalg.vector_norm(R.reshape(nr, -1), dim=1) / nb[:nr]).cpu().numpy()
+
+    for name, op in (("whole", full), ("even_odd", half)):
+        t0 = time.time()
+        if op is half:
+            bh = op.eo_prepare(b1)
+            tol1 = tol * float(torch.linalg.vector_norm(b1)) / float(torch.linalg.vector_norm(bh))
+            _, eig, st1 = op.solve_first(bh, args.m, args.k, tol1)
+        else:
+            _, eig, st1 = op.solve_first(b1, args.m, args.k, tol)
+        eig.lower(deflan.DL_FP32)
+        torch.cuda.synchronize()
+        t_first = time.time() - t0
+        res = dict(first_rhs=dict(mvp=st1["mvp"], mvp_lin=st1["mvp_lin"], seconds=round(t_first, 2),
+                                  stop_rule=st1["stop_rule"]))
+        log(f"evenodd {name}: first rhs {st1['mvp']} MVPs, {t_first:.1f}s")
+        op.tune_wilson(deflan.DL_BF16, args.test_rhs, reps=3)
+        for path, kw, nr in (("plain_fp64", dict(), args.plain_rhs),
+                             ("batched_bf16", dict(storage=deflan.DL_BF16, batched=1, eig_storage=deflan.DL_FP32),
+                              args.test_rhs)):
+            Bs = B[:nr]
+            for rep in range(2):  # the first pass warms up (launch shapes, buffers)
+                torch.cuda.synchronize()
+                t0 = time.time()
+                if op is half:
+                    Bh = torch.stack([op.eo_prepare(Bs[i]) for i in range(nr)])
+                    nbh = torch.linalg.vector_norm(Bh.reshape(nr, -1), dim=1)
+                    # the even system's tol that gives the whole-lattice tol (||r|| is the same)
+                    tole = tol * float((nb[:nr] / nbh).min())
+                    Xe, sts, rc = op.solve_next(Bh, eig, tole, **kw)
+                    X = torch.stack([op.eo_reconstruct(Bs[i], Xe[i]) for i in range(nr)])
+                else:
+                    X, sts, rc = op.solve_next(Bs, eig, tol, **kw)
+                torch.cuda.synchronize()
+                dt = time.time() - t0
+            rr = whole_relres(X)
+            res[path] = dict(value=round(nr / dt, 3), unit="RHS/s", rhs=nr, iters_per_rhs=float(np.mean([s_["iters"] for s_ in sts])),
+                             mvp_per_rhs=float(np.mean([s_["mvp"] for s_ in sts])),
+                             max_whole_relres=float(rr.max()), all_converged=bool(rc == 0 and rr.max() <= tol * 1.0001))
+            log(f"evenodd {name} {path}: {nr / dt:.2f} RHS/s, {res[path]['iters_per_rhs']:.0f} iterations per rhs, "
+                f"whole-lattice relres {rr.max():.2e}")
+        ms, by = op.bench_wilson(deflan.DL_APPLY_M, deflan.DL_BF16, args.test_rhs, 10)
+        res["stencil_bf16_nrhs64"] = dict(avg_us=round(ms * 1e3, 1), bytes_per_launch=by,
+                                         GBps=round(by / (ms * 1e-3) / 1e9, 1))
+        out["runs"][name] = res
+        eig.close()
+    w, h = out["runs"]["whole"], out["runs"]["even_odd"]
+    out["speedup_even_odd"] = {p_: round(h[p_]["value"] / w[p_]["value"], 3) for p_ in ("plain_fp64", "batched_bf16")}
+    print(json.dumps(out), flush=True)
+    half.close()
+    full.close()
+    ctx.close()
+
+
 def window_sweep(args):
     """The batched D-MinRes of the benchmark workload in its fused short-recurrence form
     (minres_window < 0) and windowed with W = 8, 16, 32, 64: BF16 storage with the
@@ -734,6 +815,8 @@ def main():
                     help="the learned-guess study across training and held-out fields instead (own JSON line)")
     ap.add_argument("--window-sweep", action="store_true",
                     help="the D-MinRes window sweep on the benchmark workload instead (own JSON line)")
+    ap.add_argument("--evenodd", action="store_true",
+                    help="the even-odd (Schur) form against the whole lattice on a held-out field instead")
     ap.add_argument("--learned-pairs", type=int, default=256)
     ap.add_argument("--learned-test", type=int, default=64)
     ap.add_argument("--learned-epochs", type=int, default=2)
@@ -760,6 +843,8 @@ def main():
         return ksweep_study(args)
     if args.window_sweep:
         return window_sweep(args)
+    if args.evenodd:
+        return evenodd_study(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
     return c5_headline(args)
 
