@@ -828,6 +828,7 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
     write_scalars(ctx, S.sc.get(), S_COUNT, h);
   }
   int j0 = 0, cycles = 0;
+  double t_line = t0;  // time of the last progress line
   long mvp_lin = -1;
   double anorm = 0.0, relres = 1.0;
   int rule = -1;
@@ -869,6 +870,13 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
       if (anorm == 0.0 || (j - j0) % 16 == 15 || j == m - 1) {
         double h[S_COUNT];
         read_scalars(ctx, S.sc.get(), S_COUNT, h);
+        // a long cycle (large m, large lattice) reports its own progress as well
+        if (verbose() && now_s() - t_line >= 20.0) {
+          std::fprintf(stderr, "[deflan] %s cycle %d: Lanczos step %d of %d, mvp %ld (%.1fs)\n", lan ? "Lan-DR" : "MinRes-DR",
+                       cycles + 1, j + 1, m, mvp, now_s() - t0);
+          std::fflush(stderr);
+          t_line = now_s();
+        }
         if (h[S_FLAG] == 1.0) fail(DL_E_NONFINITE, "non-finite value in the Lanczos process");
         if (h[S_FLAG] == 2.0) {
           // breakdown: V(0..brk) spans an invariant subspace; finish with an exact solve
@@ -918,6 +926,7 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
       std::fprintf(stderr, "[deflan] %s cycle %d: mvp %ld relres %.3e max eig-resid %.3e (%.1fs)\n",
                    lan ? "Lan-DR" : "MinRes-DR", cycles, mvp, relres, rmax, now_s() - t0);
       std::fflush(stderr);
+      t_line = now_s();
     }
     if (breakdown) { rule = DL_STOP_BREAKDOWN; break; }
     // ---- stopping rule ----
