@@ -317,6 +317,27 @@ int  dl_bench_copy(dl_ctx* ctx, long bytes, int reps, double* avg_ms);
  * variant / order / best_us (may be NULL) receive the choice and its time. */
 int  dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* order, double* best_us);
 
+/* Contraction kinds of dl_tune_tsk. */
+#define DL_TSK_DOTS64   0  /* C = V^H W, FP64 basis and columns (nv <= 64, nw <= 16)            */
+#define DL_TSK_DOTS32   1  /* C = V^H W on the matrix cores, FP32 storage (nv <= 128, nw <= 16)  */
+#define DL_TSK_DOTS16   2  /* the same with BF16 storage                                         */
+#define DL_TSK_UPD64    3  /* X += V D, FP64 basis (nv <= 512, nw <= 16)                         */
+#define DL_TSK_UPD32    4  /* X += V D, FP32 basis, FP64 products                                */
+#define DL_TSK_COMBINE  5  /* Y = V G, G real nv x nw (the basis rebuild; nv, nw <= 512)         */
+
+/* Autotuner of the tall-skinny contractions (the Galerkin projection c = V^H r and x += V d over
+ * the eigenvectors, the re-orthogonalisation, and the basis rebuild Y = V G at a thick restart,
+ * section 2): time every launch shape of contraction `kind` for fields of n complex numbers, nv
+ * basis vectors and nw columns (outputs) -- grid size; for the matrix-core dots also 2, 4 or 8
+ * tiles of 16 basis vectors per launch; for the rebuild 8 or 16 outputs per block and blocks
+ * grouped per XCD -- with reps event-timed launches each on zero-filled device buffers the call
+ * allocates, keep the fastest for the process and append it to the tuning cache file.  Without
+ * an explicit call each shape is tuned on first use of its key (never inside graph capture;
+ * DEFLAN_AUTOTUNE=0: the default shape).  The update and the rebuild give the same bits in every
+ * shape; the dots' FP64 partial sums follow the grid, so their last bits do.  grid / tile /
+ * best_us (may be NULL) receive the choice and its time in microseconds. */
+int  dl_tune_tsk(dl_ctx* ctx, int kind, long n, int nv, int nw, int reps, int* grid, int* tile, double* best_us);
+
 /* One operator's share of a multi-lattice batch. */
 typedef struct {
   dl_op*        op;         /* operator (all items: the same context and the same kind) */

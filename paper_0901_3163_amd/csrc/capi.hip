@@ -700,6 +700,21 @@ int dl_tune_wilson(dl_op* op, int prec, int nrhs, int reps, int* variant, int* o
   });
 }
 
+int dl_tune_tsk(dl_ctx* ctx, int kind, long n, int nv, int nw, int reps, int* grid, int* tile, double* best_us) {
+  return guard([&] {
+    need(ctx != nullptr, "ctx is NULL");
+    need(kind >= 0 && kind < TK_COUNT, "unknown contraction kind");
+    need(n >= 1 && nv >= 1 && nw >= 1 && reps >= 1, "need n, nv, nw, reps >= 1");
+    use_device(ctx);
+    double us = 0.0;
+    const TskCfg c = tsk_tune(ctx->stream, kind, n, nv, nw, reps, &us);
+    if (grid) *grid = c.grid;
+    if (tile) *tile = c.tile;
+    if (best_us) *best_us = us;
+    return DL_OK;
+  });
+}
+
 int dl_net_num_weights(void) { return net_num_weights(); }
 
 int dl_net_create(dl_ctx* ctx, const double* weights, dl_net** out) {

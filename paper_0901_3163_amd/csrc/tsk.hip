@@ -12,6 +12,10 @@
 #include "cplx.hpp"
 #include "tsk.hpp"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 namespace dl {
 
 constexpr int kEPT = 8;        // elements of w cached per thread in the dots kernel
@@ -88,32 +92,45 @@ k_tsk_update(long n, int nv, const double2* __restrict__ base, long ld, const in
   }
 }
 
-// Y_l (+)= sum_j G[j * ldg + l] V_j for l in [l0, l0 + kNY) ; G real.
-constexpr int kNY = 8;
+// Y_l (+)= sum_j G[j * ldg + l] V_j for l in [l0, l0 + NY) ; G real.  Block (bx, by) covers
+// rows bx, bx + nbx, ... of outputs [by * NY, by * NY + NY).  xcd = 0: a 2-D grid (bx, by);
+// xcd = 1: a 1-D grid of nbx * nby blocks (nbx a multiple of 8) numbered so that the nby blocks
+// of one row range are consecutive on one XCD (hardware places block L on XCD L % 8), where they
+// read the same rows of V through that XCD's L2 instead of each from HBM.
+template <int NY>
 __global__ void __launch_bounds__(kBlock)
 k_tsk_combine(long n, int nv, const double2* __restrict__ base, long ld, const int* __restrict__ slot,
               const double* __restrict__ G, int ldg, int ny, double2* __restrict__ obase, long old,
-              const int* __restrict__ oslot, int accumulate) {
-  const int l0 = blockIdx.y * kNY;
-  const int nl = min(kNY, ny - l0);
-  __shared__ double gs[kMaxNV][kNY];
-  for (int t = threadIdx.x; t < nv * kNY; t += kBlock) {
-    const int j = t / kNY, l = t % kNY;
+              const int* __restrict__ oslot, int accumulate, int nbx, int nby, int xcd) {
+  int bx, by;
+  if (xcd) {
+    const int q = blockIdx.x >> 3;
+    by = q % nby;
+    bx = (q / nby) * 8 + (blockIdx.x & 7);
+  } else {
+    bx = blockIdx.x;
+    by = blockIdx.y;
+  }
+  const int l0 = by * NY;
+  const int nl = min(NY, ny - l0);
+  __shared__ double gs[NY == 8 ? kMaxNV : kMaxNV / 2][NY];
+  for (int t = threadIdx.x; t < nv * NY; t += kBlock) {
+    const int j = t / NY, l = t % NY;
     gs[j][l] = l < nl ? G[(long)j * ldg + l0 + l] : 0.0;
   }
   __syncthreads();
-  const long stride = (long)gridDim.x * kBlock;
-  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    double2 acc[kNY];
+  const long stride = (long)nbx * kBlock;
+  for (long i = (long)bx * kBlock + threadIdx.x; i < n; i += stride) {
+    double2 acc[NY];
 #pragma unroll
-    for (int l = 0; l < kNY; ++l) acc[l] = make_double2(0.0, 0.0);
+    for (int l = 0; l < NY; ++l) acc[l] = make_double2(0.0, 0.0);
     for (int j = 0; j < nv; ++j) {
       const double2 x = vec_at(base, ld, slot, j)[i];
 #pragma unroll
-      for (int l = 0; l < kNY; ++l) acc[l] = c_axpy(gs[j][l], x, acc[l]);
+      for (int l = 0; l < NY; ++l) acc[l] = c_axpy(gs[j][l], x, acc[l]);
     }
 #pragma unroll
-    for (int l = 0; l < kNY; ++l) {
+    for (int l = 0; l < NY; ++l) {
       if (l < nl) {
         double2* y = obase + (long)(oslot ? oslot[l0 + l] : l0 + l) * old;
         y[i] = accumulate ? c_add(y[i], acc[l]) : acc[l];
@@ -246,6 +263,31 @@ k_tsk_update_multi(long n, int nv, const VB* __restrict__ base, long ld, const d
   }
 }
 
+// One thread per element up to 8192 blocks: the largest grid the grid-stride kernels are tuned over.
+static int max_stream_blocks(long n) {
+  long nb = (n + kBlock - 1) / kBlock;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+// tsk_tune's request to re-time the next key, and what the launcher chose.
+namespace {
+struct TuneReq {
+  int reps = 0;
+  double us = 0.0;
+  TskCfg cfg;
+};
+thread_local TuneReq t_tune;
+}  // namespace
+
+static TskCfg choose(hipStream_t s, int kind, long n, int nv, int nw, const std::vector<TskCfg>& cands,
+                     const std::function<void(const TskCfg&)>& launch) {
+  const TskCfg c = tsk_choose(s, kind, n, nv, nw, cands, launch, t_tune.reps, &t_tune.us);
+  t_tune.cfg = c;
+  return c;
+}
+
 static int stream_blocks(long n) {
   long nb = (n + kBlock - 1) / kBlock;
   if (nb > 2048) nb = 2048;
@@ -272,15 +314,85 @@ void tsk_update(hipStream_t s, long n, int nv, const double2* base, long ld, con
   DL_HIP(hipGetLastError());
 }
 
+// Zero-filled device doubles (at least ndouble) for timing read-modify-write launches with no
+// effect (x + 0 = x): one buffer per device that only grows, kept until the process ends (filled
+// and synchronised before first use; timing happens outside graph capture).
+static const double2* zeros(hipStream_t s, size_t ndouble) {
+  static std::mutex mu;
+  static std::map<int, std::pair<double2*, size_t>> bufs;
+  int dev = 0;
+  DL_HIP(hipGetDevice(&dev));
+  const size_t n2 = (ndouble + 1) / 2;
+  std::lock_guard<std::mutex> g(mu);
+  auto& b = bufs[dev];
+  if (b.second < n2) {
+    if (b.first) {
+      DL_HIP(hipStreamSynchronize(s));
+      DL_HIP(hipFree(b.first));
+      b.first = nullptr;
+      b.second = 0;
+    }
+    void* p = nullptr;
+    DL_HIP(hipMalloc(&p, n2 * sizeof(double2)));
+    b.first = static_cast<double2*>(p);
+    b.second = n2;
+    zero(s, (long)n2, b.first);
+    DL_HIP(hipStreamSynchronize(s));
+  }
+  return b.first;
+}
+
+static void combine_launch(hipStream_t s, long n, int nv, const double2* base, long ld, const int* slot,
+                           const double* G, int ldg, int ny, double2* obase, long old, const int* oslot,
+                           int accumulate, const TskCfg& c) {
+  const int ny_per = (c.tile & 2) ? 16 : 8;
+  const int xcd = c.tile & 1;
+  const int nby = (ny + ny_per - 1) / ny_per;
+  int nbx = c.grid;
+  if (xcd) nbx = (nbx + 7) / 8 * 8;
+  const dim3 grid = xcd ? dim3((unsigned)nbx * nby) : dim3(nbx, nby);
+  if (ny_per == 16)
+    hipLaunchKernelGGL(k_tsk_combine<16>, grid, dim3(kBlock), 0, s, n, nv, base, ld, slot, G, ldg, ny, obase, old,
+                       oslot, accumulate, nbx, nby, xcd);
+  else
+    hipLaunchKernelGGL(k_tsk_combine<8>, grid, dim3(kBlock), 0, s, n, nv, base, ld, slot, G, ldg, ny, obase, old,
+                       oslot, accumulate, nbx, nby, xcd);
+  DL_HIP(hipGetLastError());
+}
+
+static TskCfg combine_shape(TskCfg c, long n, int nv) {
+  const int full = max_stream_blocks(n);
+  if (c.grid < 1) c.grid = stream_blocks(n);
+  if (c.grid > full) c.grid = full;
+  if (c.tile < 0 || c.tile > 3 || ((c.tile & 2) && nv > kMaxNV / 2)) c.tile = 0;
+  return c;
+}
+
 void tsk_combine(hipStream_t s, long n, int nv, const double2* base, long ld, const int* slot,
                  const double* G, int ldg, int ny, double2* obase, long old, const int* oslot,
                  int accumulate) {
   if (nv > kMaxNV) fail(DL_E_INVALID, "too many basis vectors (max 512)");
   if (nv <= 0 || ny <= 0) return;
-  const dim3 grid(stream_blocks(n), (ny + kNY - 1) / kNY);
-  hipLaunchKernelGGL(k_tsk_combine, grid, dim3(kBlock), 0, s, n, nv, base, ld, slot, G, ldg, ny, obase, old,
-                     oslot, accumulate);
-  DL_HIP(hipGetLastError());
+  std::vector<TskCfg> cands;
+  for (int t = 0; t < 4; ++t) {
+    if ((t & 2) && nv > kMaxNV / 2) continue;
+    for (int g : {2048, 1024, 4096}) {
+      const TskCfg c = combine_shape(TskCfg{g, t}, n, nv);
+      bool dup = false;
+      for (const auto& o : cands) dup |= o.grid == c.grid && o.tile == c.tile;
+      if (!dup) cands.push_back(c);
+    }
+  }
+  cands.insert(cands.begin(), combine_shape(TskCfg{}, n, nv));  // the default first
+  // timed with zero coefficients: outputs get zeros (or + 0) until the real launch below
+  const TskCfg c = combine_shape(
+      choose(s, TK_COMBINE, n, nv, ny, cands,
+                 [&](const TskCfg& t) {
+                   const double* gz = reinterpret_cast<const double*>(zeros(s, (size_t)nv * ldg));
+                   combine_launch(s, n, nv, base, ld, slot, gz, ldg, ny, obase, old, oslot, accumulate, t);
+                 }),
+      n, nv);
+  combine_launch(s, n, nv, base, ld, slot, G, ldg, ny, obase, old, oslot, accumulate, c);
 }
 
 int tsk_multi_nblocks(long n) {
@@ -290,25 +402,43 @@ int tsk_multi_nblocks(long n) {
   return (int)nb;
 }
 
+// Grid candidates of a partial-writing kernel: the default d, d/2, d/4 (at least 1).
+static std::vector<TskCfg> grid_cands(int d, const std::vector<int>& tiles) {
+  std::vector<TskCfg> c;
+  for (int t : tiles)
+    for (int g : {d, d / 2, d / 4})
+      if (g >= 1) {
+        bool dup = false;
+        for (const auto& o : c) dup |= o.grid == g && o.tile == t;
+        if (!dup) c.push_back(TskCfg{g, t});
+      }
+  return c;
+}
+
 int tsk_dots_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* W, long ldw, int nw,
                    const int* active, double* part) {
   if (nv > kMultiNV) fail(DL_E_INVALID, "too many basis vectors for one multi-column contraction (max 64)");
   if (nw < 1 || nw > kTW) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
-  const int nb = tsk_multi_nblocks(n);
-  for (int j0 = 0; j0 < nv; j0 += kTJ) {
-    const int nj = nv - j0 < kTJ ? nv - j0 : kTJ;
-    hipLaunchKernelGGL(k_tsk_dots_multi, dim3(nb), dim3(kBlock), 0, s, n, nv, j0, nj, base, ld, W, ldw, nw, active,
-                       part);
-    DL_HIP(hipGetLastError());
-  }
-  return nb;
+  const int d = tsk_multi_nblocks(n);
+  auto launch = [&](const TskCfg& c) {
+    for (int j0 = 0; j0 < nv; j0 += kTJ) {
+      const int nj = nv - j0 < kTJ ? nv - j0 : kTJ;
+      hipLaunchKernelGGL(k_tsk_dots_multi, dim3(c.grid), dim3(kBlock), 0, s, n, nv, j0, nj, base, ld, W, ldw, nw,
+                         active, part);
+      DL_HIP(hipGetLastError());
+    }
+  };
+  // timed into the caller's partials, which the launch below overwrites
+  TskCfg c = choose(s, TK_DOTS64, n, nv, nw, grid_cands(d, {0}), launch);
+  c.grid = std::max(1, std::min(c.grid, d));
+  c.tile = 0;
+  launch(c);
+  return c.grid;
 }
 
 template <class VB>
-static void update_multi(hipStream_t s, long n, int nv, const VB* base, long ld, const double2* D, int nw,
-                         const int* active, double2* X, long ldx) {
-  if (nw < 1 || nw > 16) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
-  const int nb = stream_blocks(n);
+static void update_launch(hipStream_t s, long n, int nv, const VB* base, long ld, const double2* D, int nw,
+                          const int* active, double2* X, long ldx, int nb) {
   constexpr int kChunk = kMaxNV / 4;  // basis vectors per launch (LDS holds kChunk x NW coefficients)
   for (int j0 = 0; j0 < nv; j0 += kChunk) {
     const int nc = nv - j0 < kChunk ? nv - j0 : kChunk;
@@ -328,6 +458,23 @@ static void update_multi(hipStream_t s, long n, int nv, const VB* base, long ld,
                          X, ldx);
     DL_HIP(hipGetLastError());
   }
+}
+
+template <class VB>
+static void update_multi(hipStream_t s, long n, int nv, const VB* base, long ld, const double2* D, int nw,
+                         const int* active, double2* X, long ldx) {
+  if (nw < 1 || nw > 16) fail(DL_E_INVALID, "multi-column contraction takes 1..16 columns");
+  if (nv <= 0) return;
+  const int full = max_stream_blocks(n);
+  std::vector<TskCfg> cands{TskCfg{stream_blocks(n), 0}};
+  for (int g : {512, 1024, 4096})
+    if (g <= full && g != cands[0].grid) cands.push_back(TskCfg{g, 0});
+  // timed with zero coefficients (X + 0 = X)
+  TskCfg c = choose(s, sizeof(VB) == 16 ? TK_UPD64 : TK_UPD32, n, nv, nw, cands, [&](const TskCfg& t) {
+    update_launch(s, n, nv, base, ld, zeros(s, (size_t)2 * nv * nw), nw, active, X, ldx, t.grid);
+  });
+  c.grid = std::max(1, std::min(c.grid, full));
+  update_launch(s, n, nv, base, ld, D, nw, active, X, ldx, c.grid);
 }
 
 void tsk_update_multi(hipStream_t s, long n, int nv, const double2* base, long ld, const double2* D, int nw,
@@ -358,7 +505,6 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kLpRows = 64;    // basis vectors per launch: four 16-row tiles
 constexpr int kLpBlocks = 512; // upper bound of partials per column
 
 template <class SV>
@@ -416,14 +562,14 @@ __device__ __forceinline__ void lp_mfma(f32x4_t& acc, u32x4_t a, u32x4_t b, floa
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[q]), __uint_as_float(b[q]), acc, 0, 0, 0);
 }
 
-// part[(2*(r*nv + j0 + j) + reim) * gridDim.x + blockIdx.x] for j < nj (<= 64), r < nw (<= 16).
-template <class SV>
+// part[(2*(r*nv + j0 + j) + reim) * gridDim.x + blockIdx.x] for j < nj (<= 16 * kNT), r < nw (<= 16).
+// kNT row tiles of 16 basis vectors per launch (2, 4 or 8; the autotuner picks it).
+template <class SV, int kNT>
 __global__ void __launch_bounds__(kBlock)
 k_tsk_dots_mfma(long n, int nv, int j0, int nj, const SV* __restrict__ base, long ld, const SV* __restrict__ W,
                 long ldw, int nw, const int* __restrict__ active, double* __restrict__ part) {
   constexpr int C = LpTraits<SV>::kCpl;
   constexpr int kStep = 4 * C;  // complex elements of each vector per step (4 lane groups)
-  constexpr int kNT = kLpRows / 16;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, grp = lane >> 4;
   const bool col_on = li < nw && (!active || active[li]);
@@ -463,25 +609,42 @@ k_tsk_dots_mfma(long n, int nv, int j0, int nj, const SV* __restrict__ base, lon
       }
     }
   }
-  // add the four waves' tiles in a fixed order; acc[t][c][q] of lane l is row 16t + 4*(l/16) + q,
-  // column l % 16 of the real (c = 0) or imaginary (c = 1) part
-  __shared__ float red[kBlock / 64][kNT * 2 * 4][64];
+  // add the four waves' tiles in a fixed order, four row tiles at a time; acc[t][c][q] of lane l
+  // is row 16t + 4*(l/16) + q, column l % 16 of the real (c = 0) or imaginary (c = 1) part
+  constexpr int kTG = kNT < 4 ? kNT : 4;
+  __shared__ float red[kBlock / 64][kTG * 2 * 4][64];
 #pragma unroll
-  for (int t = 0; t < kNT; ++t)
+  for (int t0 = 0; t0 < kNT; t0 += kTG) {
+    if (t0) __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int t = 0; t < kTG; ++t)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) red[wid][(t * 2 + c) * 4 + q][lane] = acc[t][c][q];
-  __syncthreads();
-  for (int e = threadIdx.x; e < kNT * 2 * 4 * 64; e += kBlock) {
-    const int slot = e / 64, l = e % 64;
-    const int t = slot / 8, c = (slot / 4) % 2, q = slot % 4;
-    const int j = 16 * t + 4 * (l / 16) + q, r = l % 16;
-    if (j >= nj || r >= nw) continue;
-    double v = 0.0;
+      for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) v += (double)red[w][slot][l];
-    part[(2L * ((long)r * nv + j0 + j) + c) * gridDim.x + blockIdx.x] = v;
+        for (int q = 0; q < 4; ++q) red[wid][(t * 2 + c) * 4 + q][lane] = acc[t0 + t][c][q];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTG * 2 * 4 * 64; e += kBlock) {
+      const int slot = e / 64, l = e % 64;
+      const int t = t0 + slot / 8, c = (slot / 4) % 2, q = slot % 4;
+      const int j = 16 * t + 4 * (l / 16) + q, r = l % 16;
+      if (j >= nj || r >= nw) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) v += (double)red[w][slot][l];
+      part[(2L * ((long)r * nv + j0 + j) + c) * gridDim.x + blockIdx.x] = v;
+    }
+  }
+}
+
+template <class SV, int kNT>
+static void mfma_launch(hipStream_t s, long n, int nv, const SV* base, long ld, const SV* W, long ldw, int nw,
+                        const int* active, double* part, int nb) {
+  constexpr int kRowsPer = 16 * kNT;
+  for (int j0 = 0; j0 < nv; j0 += kRowsPer) {
+    const int nj = nv - j0 < kRowsPer ? nv - j0 : kRowsPer;
+    hipLaunchKernelGGL((k_tsk_dots_mfma<SV, kNT>), dim3(nb), dim3(kBlock), 0, s, n, nv, j0, nj, base, ld, W, ldw, nw,
+                       active, part);
+    DL_HIP(hipGetLastError());
   }
 }
 
@@ -494,14 +657,18 @@ static int dots_mfma(hipStream_t s, long n, int nv, const SV* base, long ld, con
   constexpr int C = LpTraits<SV>::kCpl;
   if ((reinterpret_cast<uintptr_t>(base) | reinterpret_cast<uintptr_t>(W)) % 16 != 0 || ld % C != 0 || ldw % C != 0)
     fail(DL_E_INVALID, "low-precision contraction needs 16-byte aligned fields");
-  const int nb = tsk_lowp_nblocks(n, sizeof(SV) == 4 ? DL_BF16 : DL_FP32);
-  for (int j0 = 0; j0 < nv; j0 += kLpRows) {
-    const int nj = nv - j0 < kLpRows ? nv - j0 : kLpRows;
-    hipLaunchKernelGGL(k_tsk_dots_mfma<SV>, dim3(nb), dim3(kBlock), 0, s, n, nv, j0, nj, base, ld, W, ldw, nw, active,
-                       part);
-    DL_HIP(hipGetLastError());
-  }
-  return nb;
+  const int d = tsk_lowp_nblocks(n, sizeof(SV) == 4 ? DL_BF16 : DL_FP32);
+  auto launch = [&](const TskCfg& c) {
+    if (c.tile == 2) mfma_launch<SV, 2>(s, n, nv, base, ld, W, ldw, nw, active, part, c.grid);
+    else if (c.tile == 8) mfma_launch<SV, 8>(s, n, nv, base, ld, W, ldw, nw, active, part, c.grid);
+    else mfma_launch<SV, 4>(s, n, nv, base, ld, W, ldw, nw, active, part, c.grid);
+  };
+  // the default (4 row tiles, d blocks) first; timed into the caller's partials
+  TskCfg c = choose(s, sizeof(SV) == 4 ? TK_DOTS16 : TK_DOTS32, n, nv, nw, grid_cands(d, {4, 2, 8}), launch);
+  c.grid = std::max(1, std::min(c.grid, d));
+  if (c.tile != 2 && c.tile != 8) c.tile = 4;
+  launch(c);
+  return c.grid;
 }
 
 int tsk_lowp_nblocks(long n, int prec) {
@@ -520,6 +687,80 @@ int tsk_dots_lowp(hipStream_t s, long n, int nv, const float2* base, long ld, co
 int tsk_dots_lowp(hipStream_t s, long n, int nv, const bf2* base, long ld, const bf2* W, long ldw, int nw,
                   const int* active, double* part) {
   return dots_mfma(s, n, nv, base, ld, W, ldw, nw, active, part);
+}
+
+TskCfg tsk_tune(hipStream_t s, int kind, long n, int nv, int nw, int reps, double* best_us) {
+  if (reps < 1) fail(DL_E_INVALID, "reps must be >= 1");
+  if (n < 1) fail(DL_E_INVALID, "n must be >= 1");
+  const int nvmax = kind == TK_DOTS64 ? kMultiNV : (kind == TK_DOTS32 || kind == TK_DOTS16) ? kLpMaxNV : kMaxNV;
+  if (nv < 1 || nv > nvmax) fail(DL_E_INVALID, "nv out of range for this contraction");
+  if (nw < 1 || nw > (kind == TK_COMBINE ? kMaxNV : 16)) fail(DL_E_INVALID, "nw out of range for this contraction");
+  // fields of zeros (the kernels' time does not depend on the values)
+  const long ld = (n + 3) / 4 * 4;
+  DBuf<double2> V, W;
+  DBuf<double> part;
+  struct Reset {
+    ~Reset() { t_tune = TuneReq(); }
+  } reset;
+  t_tune.reps = reps;
+  switch (kind) {
+    case TK_DOTS64:
+      V.alloc((size_t)nv * n);
+      W.alloc((size_t)nw * n);
+      part.alloc((size_t)2 * nv * nw * tsk_multi_nblocks(n));
+      zero(s, (long)V.n, V.get());
+      zero(s, (long)W.n, W.get());
+      tsk_dots_multi(s, n, nv, V.get(), n, W.get(), n, nw, nullptr, part.get());
+      break;
+    case TK_DOTS32:
+    case TK_DOTS16: {
+      const bool b16 = kind == TK_DOTS16;
+      V.alloc(((size_t)nv * ld + 1) / 2);
+      W.alloc(((size_t)nw * ld + 1) / 2);
+      part.alloc((size_t)2 * nv * nw * tsk_lowp_nblocks(n, b16 ? DL_BF16 : DL_FP32));
+      zero(s, (long)V.n, V.get());
+      zero(s, (long)W.n, W.get());
+      if (b16)
+        tsk_dots_lowp(s, n, nv, reinterpret_cast<const bf2*>(V.get()), ld, reinterpret_cast<const bf2*>(W.get()), ld,
+                      nw, nullptr, part.get());
+      else
+        tsk_dots_lowp(s, n, nv, reinterpret_cast<const float2*>(V.get()), ld, reinterpret_cast<const float2*>(W.get()),
+                      ld, nw, nullptr, part.get());
+      break;
+    }
+    case TK_UPD64:
+    case TK_UPD32: {
+      const bool f32 = kind == TK_UPD32;
+      V.alloc(f32 ? ((size_t)nv * n + 1) / 2 : (size_t)nv * n);
+      W.alloc((size_t)nw * n);
+      DBuf<double2> D((size_t)nw * nv);
+      zero(s, (long)V.n, V.get());
+      zero(s, (long)W.n, W.get());
+      zero(s, (long)D.n, D.get());
+      if (f32)
+        tsk_update_multi32(s, n, nv, reinterpret_cast<const float2*>(V.get()), n, D.get(), nw, nullptr, W.get(), n);
+      else
+        tsk_update_multi(s, n, nv, V.get(), n, D.get(), nw, nullptr, W.get(), n);
+      DL_HIP(hipStreamSynchronize(s));
+      break;
+    }
+    case TK_COMBINE: {
+      V.alloc((size_t)nv * n);
+      W.alloc((size_t)nw * n);
+      DBuf<double2> G(((size_t)nv * nw + 1) / 2);
+      zero(s, (long)V.n, V.get());
+      zero(s, (long)G.n, G.get());
+      tsk_combine(s, n, nv, V.get(), n, nullptr, reinterpret_cast<const double*>(G.get()), nw, nw, W.get(), n,
+                  nullptr, 0);
+      DL_HIP(hipStreamSynchronize(s));
+      break;
+    }
+    default:
+      fail(DL_E_INVALID, "unknown contraction kind");
+  }
+  DL_HIP(hipStreamSynchronize(s));
+  if (best_us) *best_us = t_tune.us;
+  return t_tune.cfg;
 }
 
 }  // namespace dl

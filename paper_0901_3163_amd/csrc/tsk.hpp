@@ -1,8 +1,31 @@
 // Launchers of the tall-skinny basis contractions (tsk.hip).
 #pragma once
+#include <functional>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace dl {
+
+// Launch shapes of the contractions, chosen by the autotuner per (architecture, kind, n, nv,
+// nw).  grid: blocks (dots: at most the default count, so partial buffers sized by the
+// *_nblocks functions hold them); tile: kind-specific (matrix-core dots: row tiles of 16 basis
+// vectors per launch, 2, 4 or 8; rebuild: outputs per block 8 or 16 (bit 1) and blocks grouped
+// per XCD (bit 0); others 0).  Every shape of the update and the rebuild gives the same bits;
+// the dots' partial sums follow the grid, so their rounding does.
+enum TskKind { TK_DOTS64 = 0, TK_DOTS32, TK_DOTS16, TK_UPD64, TK_UPD32, TK_COMBINE, TK_COUNT };
+struct TskCfg {
+  int grid = 0;
+  int tile = 0;
+};
+// The shape for a key: DEFLAN_TSK_SHAPE (grid,tile or grid,tile,kind) when set, else the remembered choice, else (outside
+// graph capture, unless DEFLAN_AUTOTUNE=0) the fastest of cands timed through launch (reps
+// event-timed launches each after a warm-up; cands[0] is the default).  reps > 0 forces the
+// timing and replaces a remembered choice.  launch must leave the caller's results unchanged.
+TskCfg tsk_choose(hipStream_t s, int kind, long n, int nv, int nw, const std::vector<TskCfg>& cands,
+                  const std::function<void(const TskCfg&)>& launch, int reps = 0, double* best_us = nullptr);
+// Tune one key on buffers of its own (dl_tune_tsk).
+TskCfg tsk_tune(hipStream_t s, int kind, long n, int nv, int nw, int reps, double* best_us);
 
 // Partial count tsk_dots uses for length n (partials are [2*nv][nblocks]).
 int tsk_nblocks(long n);

@@ -1,21 +1,28 @@
-// Autotuner for the Wilson stencil's launch shape.
+// Autotuner for the launch shapes of the Wilson stencil and of the tall-skinny contractions.
 //
 // For one (device architecture, lattice extents, precision, batch size) the
-// tuner times every (variant, block order) candidate with HIP events on the
-// context's stream -- a warm-up launch, then `reps` back-to-back launches on
-// device fields -- and keeps the fastest.  Choices live in a process-wide
-// table (so every operator of a process makes the same choice and results are
+// tuner times every (variant, block order) candidate of the stencil with HIP
+// events on the context's stream -- a warm-up launch, then `reps` back-to-back
+// launches on device fields -- and keeps the fastest.  The contractions
+// (V^H W and X += V D over FP64, FP32 or BF16 bases, and the basis rebuild
+// Y = V G) are tuned the same way per (architecture, kind, field length,
+// vectors, columns): grid size, row tiles per matrix-core launch, outputs per
+// block and block-to-XCD mapping.  Choices live in process-wide tables (so
+// every operator of a process makes the same choice and results are
 // reproducible within a run) and in a text cache file, one line per key:
 //
-//     <arch> <Lx>x<Ly>x<Lz>x<Lt> <prec> <nrhs> <variant> <order> <us>
+//     <arch> <Lx>x<Ly>x<Lz>x<Lt> <prec> <nrhs> <variant> <order> <us>      (stencil)
+//     K <arch> <kind> <n> <nv> <nw> <grid> <tile> <us>                     (contraction)
 //
 // The file is $DEFLAN_TUNE_CACHE, else $HOME/.cache/deflan/tune.txt.
-// DEFLAN_AUTOTUNE=0 disables tuning (the default shape is used).
+// DEFLAN_AUTOTUNE=0 disables tuning (the default shapes are used).
 #include "engine.hpp"
+#include "tsk.hpp"
 
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -28,6 +35,7 @@ namespace {
 
 std::mutex g_mu;
 std::map<std::string, std::pair<WilsonCfg, double>> g_table;
+std::map<std::string, std::pair<TskCfg, double>> g_tsk;
 bool g_loaded = false;
 
 std::string cache_path() {
@@ -71,6 +79,18 @@ void load_cache() {
   while (std::getline(in, line)) {
     std::istringstream is(line);
     std::string arch, dims;
+    if (line.compare(0, 2, "K ") == 0) {  // contraction line
+      std::string tag;
+      int kind, nv, nw, grid, tile;
+      long n;
+      double us;
+      if (!(is >> tag >> arch >> kind >> n >> nv >> nw >> grid >> tile >> us)) continue;
+      if (kind < 0 || kind >= TK_COUNT || grid < 1 || tile < 0) continue;
+      std::ostringstream k;
+      k << arch << ' ' << kind << ' ' << n << ' ' << nv << ' ' << nw;
+      g_tsk[k.str()] = {TskCfg{grid, tile}, us};
+      continue;
+    }
     int prec, nrhs, v, o;
     double us;
     if (!(is >> arch >> dims >> prec >> nrhs >> v >> o >> us)) continue;
@@ -81,7 +101,7 @@ void load_cache() {
   }
 }
 
-void append_cache(const std::string& key, const WilsonCfg& c, double us) {
+void append_line(const std::string& text) {
   const std::string path = cache_path();
   const size_t slash = path.rfind('/');
   if (slash != std::string::npos) {
@@ -91,7 +111,13 @@ void append_cache(const std::string& key, const WilsonCfg& c, double us) {
       if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
   }
   std::ofstream out(path, std::ios::app);
-  if (out) out << key << ' ' << c.variant << ' ' << c.order << ' ' << us << '\n';
+  if (out) out << text << '\n';
+}
+
+void append_cache(const std::string& key, const WilsonCfg& c, double us) {
+  std::ostringstream os;
+  os << key << ' ' << c.variant << ' ' << c.order << ' ' << us;
+  append_line(os.str());
 }
 
 template <class R, class SV>
@@ -194,6 +220,81 @@ WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs) {
   if (!found && autotune_enabled()) c = tune_wilson(op, prec, nrhs, 10, nullptr);
   op->wcfg[okey] = c;
   return c;
+}
+
+// ---- contraction launch shapes ---------------------------------------------------------
+TskCfg tsk_choose(hipStream_t s, int kind, long n, int nv, int nw, const std::vector<TskCfg>& cands,
+                  const std::function<void(const TskCfg&)>& launch, int reps, double* best_us) {
+  // DEFLAN_TSK_SHAPE=grid,tile forces a shape for every contraction, grid,tile,kind for one kind
+  // (checked on every call; the launcher clamps it to what the kernel and the caller's partial
+  // buffers allow)
+  if (reps <= 0)
+    if (const char* e = std::getenv("DEFLAN_TSK_SHAPE")) {
+      int g = 0, t = 0, k = -1;
+      const int got = std::sscanf(e, "%d,%d,%d", &g, &t, &k);
+      if (got == 2 || (got == 3 && k == kind)) return TskCfg{g, t};
+    }
+  int dev = 0;
+  DL_HIP(hipGetDevice(&dev));
+  std::string key;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    std::ostringstream k;
+    k << arch_name(dev) << ' ' << kind << ' ' << n << ' ' << nv << ' ' << nw;
+    key = k.str();
+    if (reps <= 0) {
+      load_cache();
+      auto it = g_tsk.find(key);
+      if (it != g_tsk.end()) return it->second.first;
+    }
+  }
+  if (reps <= 0) {
+    // first use: tune unless disabled or inside a graph capture (timing events cannot be
+    // recorded there); the untuned default is then used and not remembered
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DL_HIP(hipStreamIsCapturing(s, &cs));
+    if (!autotune_enabled() || cs != hipStreamCaptureStatusNone) return cands.front();
+    reps = 5;
+  }
+  hipEvent_t a, b;
+  DL_HIP(hipEventCreate(&a));
+  DL_HIP(hipEventCreate(&b));
+  TskCfg best = cands.front();
+  double best_t = 1e300;
+  try {
+    for (const TskCfg& c : cands) {
+      launch(c);  // warm-up
+      DL_HIP(hipEventRecord(a, s));
+      for (int i = 0; i < reps; ++i) launch(c);
+      DL_HIP(hipEventRecord(b, s));
+      DL_HIP(hipEventSynchronize(b));
+      float ms = 0.f;
+      DL_HIP(hipEventElapsedTime(&ms, a, b));
+      const double t = 1e3 * ms / reps;
+      if (verbose()) {
+        std::fprintf(stderr, "[deflan] tune contraction %d n %ld nv %d nw %d grid %d tile %d: %.1f us\n", kind, n, nv,
+                     nw, c.grid, c.tile, t);
+        std::fflush(stderr);
+      }
+      if (t < best_t) {
+        best_t = t;
+        best = c;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (best_us) *best_us = best_t;
+  std::lock_guard<std::mutex> g(g_mu);
+  g_tsk[key] = {best, best_t};
+  std::ostringstream os;
+  os << "K " << key << ' ' << best.grid << ' ' << best.tile << ' ' << best_t;
+  append_line(os.str());
+  return best;
 }
 
 }  // namespace dl

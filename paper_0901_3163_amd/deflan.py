@@ -27,6 +27,7 @@ DL_HOST, DL_DEVICE = 0, 1
 DL_METHOD_DEFAULT, DL_METHOD_CG = 0, 1
 DL_APPLY_M, DL_APPLY_MDAG, DL_APPLY_G5M, DL_APPLY_MDAGM = 0, 1, 2, 3
 DL_REORTH_FULL, DL_REORTH_KEPT = 0, 1
+DL_TSK_DOTS64, DL_TSK_DOTS32, DL_TSK_DOTS16, DL_TSK_UPD64, DL_TSK_UPD32, DL_TSK_COMBINE = range(6)
 STOP_RULES = {0: "linear", 1: "eigen", 2: "mvp_factor", 3: "max_mvp", 4: "breakdown", -1: "none"}
 
 
@@ -119,6 +120,7 @@ def _load():
         "dl_solve_next_multi": (I, [P, I, C.POINTER(dl_batch_item), I, C.POINTER(dl_next_opts),
                                     C.POINTER(dl_stats)]),
         "dl_tune_wilson": (I, [P, I, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
+        "dl_tune_tsk": (I, [P, I, L, I, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
         "dl_eig_info": (I, [P, C.POINTER(I), P, P]),
         "dl_eig_vectors": (I, [P, P, I]),
         "dl_eig_destroy": (None, [P]),
@@ -151,7 +153,7 @@ lib = _load()
 EXPORTED = ("dl_last_error", "dl_version", "dl_ctx_create", "dl_ctx_destroy", "dl_ctx_sync", "dl_timing",
             "dl_kernel_time", "dl_op_create", "dl_op_destroy", "dl_op_size", "dl_apply", "dl_solve_first",
             "dl_solve_next", "dl_eig_create", "dl_eig_info", "dl_eig_vectors", "dl_eig_destroy",
-            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson",
+            "dl_tsk_project", "dl_tsk_combine", "dl_small_eigh", "dl_bench_wilson", "dl_tune_wilson", "dl_tune_tsk",
             "dl_net_num_weights", "dl_net_create", "dl_net_get_weights", "dl_net_set_weights", "dl_net_destroy",
             "dl_net_apply", "dl_net_loss_grad", "dl_net_train", "dl_apply_batched",
             "dl_solve_next_multi", "dl_tsk_project_multi", "dl_tsk_project_lowp", "dl_eig_lower",
@@ -227,6 +229,13 @@ class Context:
         ms = C.c_double()
         _check(lib.dl_bench_copy(self.h, int(nbytes), int(reps), C.byref(ms)))
         return ms.value
+
+    def tune_tsk(self, kind: int, n: int, nv: int, nw: int, reps: int = 5):
+        """(grid, tile, microseconds) of the fastest launch shape of a contraction kind."""
+        g, t, us = C.c_int(), C.c_int(), C.c_double()
+        _check(lib.dl_tune_tsk(self.h, int(kind), int(n), int(nv), int(nw), int(reps), C.byref(g), C.byref(t),
+                               C.byref(us)))
+        return g.value, t.value, us.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -45,6 +45,7 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert deflan.lib.dl_eig_save(None, b"/nonexistent/x") == deflan.DL_E_INVALID
     assert deflan.lib.dl_eig_load(None, b"/nonexistent/x", None) == deflan.DL_E_INVALID
     assert deflan.lib.dl_op_fingerprint(None, None) == deflan.DL_E_INVALID
+    assert deflan.lib.dl_tune_tsk(None, deflan.DL_TSK_DOTS16, 1024, 8, 4, 3, None, None, None) == deflan.DL_E_INVALID
 
 
 def test_binding_structs_match_the_header(tmp_path):
