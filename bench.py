@@ -586,6 +586,40 @@ def kernel_only(args):
     ctx.close()
 
 
+def tune_report(args):
+    """The autotuner's choices at the sizes the paths use: the stencil on the 16^3x32 learned-guess
+    field (BF16, FP32 and FP64 spinors with 64 rhs, FP64 with one) and the tall-skinny contractions
+    (projection dots and update over k = 60 eigenvectors for 16 rhs, the basis rebuild of
+    Lan-DR(120,60) and MinRes-DR(120,60); at 24^3x48 the FP32 projection over k = 100 for 12 rhs
+    and the Lan-DR(200,100) rebuild), every key re-timed (run with DEFLAN_VERBOSE=1 for every
+    candidate's time).  One JSON line."""
+    import torch
+    from lattice_inputs import su3_links
+    from paper_0901_3163_amd import deflan
+    e = kappa_for("16x16x16x32/seed10")
+    dims = tuple(e["dims"])
+    ctx = deflan.Context(0)
+    out = {"stencil": [], "contraction": []}
+    op = deflan.Operator(ctx, dims, torch.from_numpy(su3_links(dims, 10, e["eps"])).cuda(), e["kappa"],
+                         deflan.DL_MDAGM)
+    for prec, nrhs in [(deflan.DL_BF16, 64), (deflan.DL_FP32, 64), (deflan.DL_FP64, 64), (deflan.DL_FP64, 1)]:
+        v, o, us = op.tune_wilson(prec, nrhs, reps=10)
+        out["stencil"].append(dict(dims=list(dims), prec=prec, nrhs=nrhs, variant=v, order=o, us=round(us, 1)))
+        log(f"tune stencil prec {prec} nrhs {nrhs}: variant {v} order {o}, {us:.1f} us")
+    op.close()
+    n16, n24 = int(np.prod(dims)) * 12, 24 * 24 * 24 * 48 * 12
+    for kind, n, nv, nw in [(deflan.DL_TSK_DOTS16, n16, 60, 16), (deflan.DL_TSK_DOTS32, n16, 60, 16),
+                            (deflan.DL_TSK_UPD32, n16, 60, 16), (deflan.DL_TSK_DOTS64, n16, 60, 16),
+                            (deflan.DL_TSK_UPD64, n16, 60, 16), (deflan.DL_TSK_COMBINE, n16, 120, 60),
+                            (deflan.DL_TSK_COMBINE, n16, 121, 61), (deflan.DL_TSK_DOTS32, n24, 100, 12),
+                            (deflan.DL_TSK_UPD32, n24, 100, 12), (deflan.DL_TSK_COMBINE, n24, 200, 100)]:
+        g, t, us = ctx.tune_tsk(kind, n, nv, nw, reps=5)
+        out["contraction"].append(dict(kind=kind, n=n, nv=nv, nw=nw, grid=g, tile=t, us=round(us, 1)))
+        log(f"tune contraction {kind} n {n} nv {nv} nw {nw}: grid {g} tile {t}, {us:.1f} us")
+    ctx.close()
+    print(json.dumps(out))
+
+
 def projection_only(args):
     """The deflation contraction alone, for rocprofv3 counter runs: C = V^H W for k = 60
     eigenvectors and 12 columns of the 16^3x32 field length, reps calls each in FP64, FP32 and
@@ -775,7 +809,7 @@ def main():
     ap.add_argument("--test-rhs", type=int, default=64, help="right-hand sides per held-out field")
     ap.add_argument("--plain-rhs", type=int, default=8, help="rhs per held-out field of the plain FP64 baseline")
     ap.add_argument("--epochs", type=int, default=2, help="passes of the network training over the fields")
-    ap.add_argument("--reorth", choices=("full", "kept"), default="full",
+    ap.add_argument("--reorth", choices=("full", "kept"), default="kept",
                     help="re-orthogonalisation of the first-rhs Lan-DR runs")
     ap.add_argument("--no-c2", action="store_true", help="skip the plain-method (C2) extra keys")
     ap.add_argument("--c2-steps", type=int, default=3, help="timed steps of the C2 extra keys")
@@ -815,6 +849,8 @@ def main():
                     help="the learned-guess study across training and held-out fields instead (own JSON line)")
     ap.add_argument("--window-sweep", action="store_true",
                     help="the D-MinRes window sweep on the benchmark workload instead (own JSON line)")
+    ap.add_argument("--tune-report", action="store_true",
+                    help="the autotuner's choices at the paths' sizes (own JSON line)")
     ap.add_argument("--evenodd", action="store_true",
                     help="the even-odd (Schur) form against the whole lattice on a held-out field instead")
     ap.add_argument("--learned-pairs", type=int, default=256)
@@ -845,6 +881,8 @@ def main():
         return window_sweep(args)
     if args.evenodd:
         return evenodd_study(args)
+    if args.tune_report:
+        return tune_report(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
     return c5_headline(args)
 

@@ -505,7 +505,8 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kLpBlocks = 512; // upper bound of partials per column
+constexpr int kLpBlocks = 2048; // upper bound of partials per column
+constexpr int kLpDefault = 512; // the untuned grid (at most)
 
 template <class SV>
 struct LpTraits;
@@ -657,15 +658,24 @@ static int dots_mfma(hipStream_t s, long n, int nv, const SV* base, long ld, con
   constexpr int C = LpTraits<SV>::kCpl;
   if ((reinterpret_cast<uintptr_t>(base) | reinterpret_cast<uintptr_t>(W)) % 16 != 0 || ld % C != 0 || ldw % C != 0)
     fail(DL_E_INVALID, "low-precision contraction needs 16-byte aligned fields");
-  const int d = tsk_lowp_nblocks(n, sizeof(SV) == 4 ? DL_BF16 : DL_FP32);
+  const int dmax = tsk_lowp_nblocks(n, sizeof(SV) == 4 ? DL_BF16 : DL_FP32);  // what part holds
+  const int d = std::min(dmax, kLpDefault);
   auto launch = [&](const TskCfg& c) {
     if (c.tile == 2) mfma_launch<SV, 2>(s, n, nv, base, ld, W, ldw, nw, active, part, c.grid);
     else if (c.tile == 8) mfma_launch<SV, 8>(s, n, nv, base, ld, W, ldw, nw, active, part, c.grid);
     else mfma_launch<SV, 4>(s, n, nv, base, ld, W, ldw, nw, active, part, c.grid);
   };
   // the default (4 row tiles, d blocks) first; timed into the caller's partials
-  TskCfg c = choose(s, sizeof(SV) == 4 ? TK_DOTS16 : TK_DOTS32, n, nv, nw, grid_cands(d, {4, 2, 8}), launch);
-  c.grid = std::max(1, std::min(c.grid, d));
+  std::vector<TskCfg> cands;
+  for (int t : {4, 2, 8})
+    for (int g : {d, 2 * d, 4 * d, d / 2, d / 4})
+      if (g >= 1 && g <= dmax) {
+        bool dup = false;
+        for (const auto& o : cands) dup |= o.grid == g && o.tile == t;
+        if (!dup) cands.push_back(TskCfg{g, t});
+      }
+  TskCfg c = choose(s, sizeof(SV) == 4 ? TK_DOTS16 : TK_DOTS32, n, nv, nw, cands, launch);
+  c.grid = std::max(1, std::min(c.grid, dmax));
   if (c.tile != 2 && c.tile != 8) c.tile = 4;
   launch(c);
   return c.grid;

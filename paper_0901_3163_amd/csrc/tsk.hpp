@@ -56,8 +56,8 @@ void tsk_update_multi32(hipStream_t s, long n, int nv, const float2* base, long 
 
 // Matrix-core form of the multi-column dots over FP32- or BF16-stored fields (FP32
 // accumulation, FP64 partials): part <- partials of c[r*nv + j] = <V_j, W_r> for nv <= 128,
-// nw <= 16 (sum with sum_partials(part, np, 2*nv*nw, c)); returns np = tsk_lowp_nblocks(n, prec)
-// (<= 512, so part needs 2*nv*nw*512 doubles).  Fields must be 16-byte aligned, with ld and
+// nw <= 16 (sum with sum_partials(part, np, 2*nv*nw, c)); returns np <= tsk_lowp_nblocks(n, prec)
+// (<= 2048, so part needs 2*nv*nw*2048 doubles; the tuned grid picks np).  Fields must be 16-byte aligned, with ld and
 // ldw multiples of the elements per 16 bytes (2 for FP32, 4 for BF16).
 int tsk_dots_lowp(hipStream_t s, long n, int nv, const float2* base, long ld, const float2* W, long ldw, int nw,
                   const int* active, double* part);
