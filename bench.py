@@ -255,7 +255,8 @@ def precision_study(args):
     del U
     log(f"precision study 24^3x48 kappa {kappa:.7f}: Lan-DR({args.prec_m},{args.prec_k})")
     t0 = time.time()
-    _, eig, st1 = op.solve_first(torch.from_numpy(gaussian_spinor(dims, 299)).cuda(), args.prec_m, args.prec_k, tol)
+    _, eig, st1 = op.solve_first(torch.from_numpy(gaussian_spinor(dims, 299)).cuda(), args.prec_m, args.prec_k, tol,
+                                 reorth=deflan.DL_REORTH_KEPT if args.reorth == "kept" else deflan.DL_REORTH_FULL)
     torch.cuda.synchronize()
     t_first = time.time() - t0
     log(f"first rhs: {st1['mvp']} MVPs, {t_first:.1f}s, relres {st1['relres']:.2e}")
@@ -500,19 +501,26 @@ def multi_lattice(args):
     storage = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.multi_storage]
     kappa, tol = 0.145, args.tol
     lats = [((8, 8, 8, 8), 40), ((12, 12, 12, 12), 60), ((16, 16, 16, 32), 80), ((20, 20, 20, 40), 100)]
+    # --multi-critical: links seed 0 of each lattice at its own kappa for min|lambda(gamma5 M)| = 1e-3
+    crit = {"x".join(map(str, d)): kappa_for("x".join(map(str, d)) + "/batching") for d, _ in lats} \
+        if args.multi_critical else None
     ctx = deflan.Context(0)
     items, setup = [], {}
     seed = 400
     for j, (dims, k) in enumerate(lats):
-        U = torch.from_numpy(su3_links(dims, 10 + j)).cuda()
-        op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_MDAGM)
+        name = "x".join(map(str, dims))
+        kap = crit[name]["kappa"] if crit else kappa
+        U = torch.from_numpy(su3_links(dims, 0 if crit else 10 + j)).cuda()
+        op = deflan.Operator(ctx, dims, U, kap, deflan.DL_MDAGM)
         del U
         t0 = time.time()
         b1 = torch.from_numpy(gaussian_spinor(dims, 300 + j)).cuda()
-        _, eig, st1 = op.solve_first(b1, k + 40, k, tol)
+        _, eig, st1 = op.solve_first(b1, k + 40, k, tol,
+                                     reorth=deflan.DL_REORTH_KEPT if args.reorth == "kept" else deflan.DL_REORTH_FULL)
         torch.cuda.synchronize()
-        name = "x".join(map(str, dims))
-        setup[name] = dict(k=k, first_rhs_mvp=st1["mvp"], first_rhs_seconds=round(time.time() - t0, 2))
+        setup[name] = dict(k=k, kappa=kap, first_rhs_mvp=st1["mvp"], first_rhs_seconds=round(time.time() - t0, 2))
+        if crit:
+            setup[name]["min_abs_eig"] = crit[name]["min_abs_eig"]
         log(f"multi: {name} Lan-DR({k + 40},{k}) done, {st1['mvp']} MVPs")
         B = torch.from_numpy(np.stack([gaussian_spinor(dims, seed + i) for i in range(16)])).cuda()
         seed += 16
@@ -549,8 +557,10 @@ def multi_lattice(args):
         t_plain += (time.time() - t0) * 8  # 2 of 16 rhs
     out["plain_fp64_per_rhs"] = dict(value=round(nrhs / t_plain, 3), unit="RHS/s",
                                      sample="2 rhs per lattice, time scaled to 16")
+    kdesc = ("links seed 0, each lattice at its kappa for min|lambda(gamma5 M)| = 1e-3" if crit
+             else f"kappa {kappa}")
     res = dict(workload="uneven lattices 8^4, 12^4, 16^3x32, 20^3x40, 16 Gaussian rhs each, D-CG on M^dag M, "
-                        f"kappa {kappa}, tol {tol:g}, {args.multi_storage} storage", setup=setup, **out)
+                        f"{kdesc}, tol {tol:g}, {args.multi_storage} storage", setup=setup, **out)
     for op, eig, B, _ in items:
         eig.close()
         op.close()
@@ -836,6 +846,8 @@ def main():
                     help="inference precision of the learned guess on the timed fast path")
     ap.add_argument("--multi", action="store_true", help="the uneven multi-lattice batch instead (own JSON line)")
     ap.add_argument("--multi-storage", choices=("fp32", "bf16"), default="bf16")
+    ap.add_argument("--multi-critical", action="store_true",
+                    help="--multi at near-critical kappa per lattice (links seed 0)")
     ap.add_argument("--precision", action="store_true",
                     help="the 24^3x48 precision study instead (own JSON line)")
     ap.add_argument("--prec-m", type=int, default=200)
@@ -1168,9 +1180,10 @@ def c2_workload(args, ctx, deflan):
     U = torch.from_numpy(su3_links(dims, e["seed"], e["eps"])).cuda()
     op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_G5M)
     b1 = torch.from_numpy(gaussian_spinor(dims, 200)).cuda()
-    log(f"first rhs: MinRes-DR({args.m},{args.k})")
+    log(f"first rhs: MinRes-DR({args.m},{args.k}), re-orthogonalisation {args.reorth}")
     t0 = time.time()
-    x1, eig, st1 = op.solve_first(b1, args.m, args.k, args.tol)
+    x1, eig, st1 = op.solve_first(b1, args.m, args.k, args.tol,
+                                  reorth=deflan.DL_REORTH_KEPT if args.reorth == "kept" else deflan.DL_REORTH_FULL)
     torch.cuda.synchronize()
     t_first = time.time() - t0
     log(f"first rhs done: {st1['mvp']} MVPs ({st1['mvp_lin']} at linear convergence), {t_first:.1f}s, "
@@ -1299,7 +1312,7 @@ def c2_workload(args, ctx, deflan):
                   speedup_vs_plain_fp64=round(value / plain_value, 3),
                   eigenvector_lowering=lowering,
                   first_rhs=dict(mvp=st1["mvp"], mvp_lin=st1["mvp_lin"], seconds=round(t_first, 2),
-                                 relres=st1["relres"], stop_rule=st1["stop_rule"],
+                                 relres=st1["relres"], stop_rule=st1["stop_rule"], reorth=args.reorth,
                                  mvp_overhead=round(st1["mvp"] / max(st1["mvp_lin"], 1), 3)),
                   roofline=roofline)
     if net is not None:

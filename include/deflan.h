@@ -91,13 +91,17 @@ extern "C" {
 #define DL_APPLY_MDAGM 3
 
 /* Re-orthogonalisation of the Lanczos vectors of the first right-hand side (dl_first_opts.reorth) */
-#define DL_REORTH_FULL 0   /* every step: classical Gram-Schmidt twice against the whole basis (default) */
+#define DL_REORTH_FULL 0   /* every step: classical Gram-Schmidt against the whole basis (default) */
 #define DL_REORTH_KEPT 1   /* the paper's policy (Section 2, last paragraph): each step orthogonalises
-                              against the two previous Lanczos vectors (twice), the first step after
+                              against the two previous Lanczos vectors, the first step after
                               a restart against the whole basis, and every reorth_period steps the
-                              new vector is also orthogonalised (twice) against the vectors kept at
+                              new vector is also orthogonalised against the vectors kept at
                               the last restart.  Reads 2k instead of 2j fields per step (k kept, j the
-                              basis size), so it is cheaper for k well below m. */
+                              basis size), so it is cheaper for k well below m.
+                              In both policies a Gram-Schmidt pass is repeated only when the first
+                              removed more than half of the vector's squared norm (the test of
+                              Daniel, Gragg, Kaufman and Stewart with eta = 1/sqrt(2), decided on the
+                              device): against the kept vectors, nearly never. */
 
 /* stop rules reported in dl_stats.stop_rule for dl_solve_first */
 #define DL_STOP_LINEAR     0  /* k = 0: stopped at linear convergence */

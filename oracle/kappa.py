@@ -178,6 +178,13 @@ def main(argv=None):
         # the learned-guess workload: one kappa for every field, tuned on the first training field
         res["16x16x16x32/seed10"] = search_large((16, 16, 16, 32), 1e-3, seed=10, k0=0.145, k1=0.1474,
                                                  log=lambda m: print(m, flush=True))
+    if "batching" in argv:
+        # the four lattices of the multi-lattice work list, links seed 0, each at min|lambda| = 1e-3
+        for dims in ((8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (20, 20, 20, 40)):
+            name = "x".join(map(str, dims)) + "/batching"
+            res[name] = search_large(dims, 1e-3, k0=0.145, k1=0.1474, log=lambda m: print(m, flush=True))
+            with open(out, "w") as fh:
+                json.dump(res, fh, indent=1, sort_keys=True)
     if "ksweep" in argv:
         res["20x20x20x32"] = search_large((20, 20, 20, 32), 1e-3, k0=0.145, k1=0.1474,
                                           log=lambda m: print(m, flush=True))

@@ -799,6 +799,7 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
   // factors either way
   DBuf<double2> xbest(n);
   double best = HUGE_VAL;
+  DBuf<double> dgks(2);  // [0]: second Gram-Schmidt pass needed (1) or not (0); [1]: ||w||^2
   const bool kept_reorth = o.reorth == DL_REORTH_KEPT;
   const int period = std::max(1, o.reorth_period);
   DBuf<double> work(std::max(landr_work(m), minresdr_work(m)));
@@ -839,19 +840,25 @@ int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double to
     int mm = m;
     for (int j = j0; j < m; ++j) {
       mvp += apply_A(op, V(j), w.get(), tmp.get());
-      // Classical Gram-Schmidt twice against logical vectors [v0, v0 + nv); the coefficients land
-      // at cb[v0..] (k_fin_lanczos takes alpha_j from entry j of c1 + c2).
+      // Classical Gram-Schmidt against logical vectors [v0, v0 + nv), the second pass only when the
+      // first removed more than half of ||w||^2 (the DGKS criterion, eta = 1/sqrt(2); decided on
+      // the device, a skipped pass leaves zero coefficients); the coefficients land at cb[v0..]
+      // (k_fin_lanczos takes alpha_j from entry j of c1 + c2).
       auto cgs2 = [&](int v0, int nv, double* ca, double* cb2) {
         for (int pass = 0; pass < 2; ++pass) {
           double* cb = (pass == 0 ? ca : cb2) + 2 * v0;
+          const double* gate = pass == 0 ? nullptr : dgks.get();
           int nb;
           {
             TimeScope ts(ctx, T_TSK_DOTS);
-            nb = tsk_dots(s, n, nv, Vb.get(), n, slot_d.get() + v0, w.get(), S.part.get());
+            nb = tsk_dots(s, n, nv, Vb.get(), n, slot_d.get() + v0, w.get(), S.part.get(), gate, pass == 0);
           }
           sum_partials(s, S.part.get(), nb, 2 * nv, cb);
+          if (pass == 0) sum_partials(s, S.part.get() + (size_t)2 * nv * nb, nb, 1, dgks.get() + 1);
           TimeScope ts(ctx, T_TSK_UPDATE);
-          tsk_update(s, n, nv, Vb.get(), n, slot_d.get() + v0, reinterpret_cast<const double2*>(cb), -1.0, w.get());
+          tsk_update(s, n, nv, Vb.get(), n, slot_d.get() + v0, reinterpret_cast<const double2*>(cb), -1.0, w.get(),
+                     gate);
+          if (pass == 0) tsk_dgks_gate(s, cb, nv, dgks.get() + 1, 0.5, dgks.get());
         }
       };
       if (!kept_reorth || j == j0 || j == 0) {

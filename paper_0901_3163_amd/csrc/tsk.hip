@@ -32,12 +32,20 @@ __device__ __forceinline__ const double2* vec_at(const double2* base, long ld, c
   return base + (long)(slot ? slot[j] : j) * ld;
 }
 
-// part is column-major [2*nv][gridDim.x]: Re/Im of <V_j, w> partial of this block.
+// part is column-major [2*nv][gridDim.x]: Re/Im of <V_j, w> partial of this block; with_norm
+// adds column 2*nv, the block's partial of ||w||^2 (w is in registers already).  gate: when
+// non-null and *gate == 0, the pass is skipped and the block writes zero partials.
 __global__ void __launch_bounds__(kBlock)
 k_tsk_dots(long n, int nv, const double2* __restrict__ base, long ld, const int* __restrict__ slot,
-           const double2* __restrict__ w, double* __restrict__ part) {
-  __shared__ double2 lds[kBlock / 64][kMaxNV];
+           const double2* __restrict__ w, double* __restrict__ part, const double* __restrict__ gate,
+           int with_norm) {
+  __shared__ double2 lds[kBlock / 64][kMaxNV + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int ncol = nv + (with_norm ? 1 : 0);
+  if (gate && *gate == 0.0) {
+    for (int j = threadIdx.x; j < 2 * ncol; j += kBlock) part[(long)j * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   const long stride = (long)gridDim.x * kBlock;
   const long i0 = (long)blockIdx.x * kBlock + threadIdx.x;
   double2 wr[kEPT];
@@ -64,8 +72,15 @@ k_tsk_dots(long n, int nv, const double2* __restrict__ base, long ld, const int*
     im = wave_sum(im);
     if (lane == 0) lds[wid][j] = make_double2(re, im);
   }
+  if (with_norm) {
+    double nn = 0.0;
+#pragma unroll
+    for (int r = 0; r < kEPT; ++r) nn = fma(wr[r].x, wr[r].x, fma(wr[r].y, wr[r].y, nn));
+    nn = wave_sum(nn);
+    if (lane == 0) lds[wid][nv] = make_double2(nn, 0.0);
+  }
   __syncthreads();
-  for (int j = threadIdx.x; j < nv; j += kBlock) {
+  for (int j = threadIdx.x; j < ncol; j += kBlock) {
     double re = 0.0, im = 0.0;
 #pragma unroll
     for (int q = 0; q < kBlock / 64; ++q) {
@@ -80,7 +95,8 @@ k_tsk_dots(long n, int nv, const double2* __restrict__ base, long ld, const int*
 // w += sgn * sum_j c_j V_j ; c complex (interleaved) in device memory.
 __global__ void __launch_bounds__(kBlock)
 k_tsk_update(long n, int nv, const double2* __restrict__ base, long ld, const int* __restrict__ slot,
-             const double2* __restrict__ c, double sgn, double2* __restrict__ w) {
+             const double2* __restrict__ c, double sgn, double2* __restrict__ w, const double* __restrict__ gate) {
+  if (gate && *gate == 0.0) return;
   __shared__ double2 cs[kMaxNV];
   for (int j = threadIdx.x; j < nv; j += kBlock) cs[j] = make_double2(sgn * c[j].x, sgn * c[j].y);
   __syncthreads();
@@ -296,21 +312,37 @@ static int stream_blocks(long n) {
 }
 
 int tsk_dots(hipStream_t s, long n, int nv, const double2* base, long ld, const int* slot,
-             const double2* w, double* part) {
+             const double2* w, double* part, const double* gate, int with_norm) {
   if (nv > kMaxNV) fail(DL_E_INVALID, "too many basis vectors (max 512)");
   const int nb = tsk_nblocks(n);
-  if (nv > 0) {
-    hipLaunchKernelGGL(k_tsk_dots, dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, slot, w, part);
+  if (nv > 0 || with_norm) {
+    hipLaunchKernelGGL(k_tsk_dots, dim3(nb), dim3(kBlock), 0, s, n, nv, base, ld, slot, w, part, gate, with_norm);
     DL_HIP(hipGetLastError());
   }
   return nb;
 }
 
 void tsk_update(hipStream_t s, long n, int nv, const double2* base, long ld, const int* slot,
-                const double2* c, double sgn, double2* w) {
+                const double2* c, double sgn, double2* w, const double* gate) {
   if (nv > kMaxNV) fail(DL_E_INVALID, "too many basis vectors (max 512)");
   if (nv <= 0) return;
-  hipLaunchKernelGGL(k_tsk_update, dim3(stream_blocks(n)), dim3(kBlock), 0, s, n, nv, base, ld, slot, c, sgn, w);
+  hipLaunchKernelGGL(k_tsk_update, dim3(stream_blocks(n)), dim3(kBlock), 0, s, n, nv, base, ld, slot, c, sgn, w,
+                     gate);
+  DL_HIP(hipGetLastError());
+}
+
+// gate = 1 if the first Gram-Schmidt pass removed more than the DGKS share of w, that is
+// ||c||^2 > (1 - eta^2) ||w||^2 with ||w - V c||^2 = ||w||^2 - ||c||^2 for orthonormal V, else 0.
+__global__ void k_dgks_gate(const double* __restrict__ c, int nv, const double* __restrict__ wn2, double eta2,
+                            double* __restrict__ gate) {
+  double cc = 0.0;
+  for (int j = threadIdx.x; j < 2 * nv; j += blockDim.x) cc = fma(c[j], c[j], cc);
+  cc = wave_sum(cc);  // one wave
+  if (threadIdx.x == 0) *gate = cc > (1.0 - eta2) * *wn2 ? 1.0 : 0.0;
+}
+
+void tsk_dgks_gate(hipStream_t s, const double* c, int nv, const double* wn2, double eta2, double* gate) {
+  hipLaunchKernelGGL(k_dgks_gate, dim3(1), dim3(64), 0, s, c, nv, wn2, eta2, gate);
   DL_HIP(hipGetLastError());
 }
 

@@ -30,11 +30,16 @@ TskCfg tsk_tune(hipStream_t s, int kind, long n, int nv, int nw, int reps, doubl
 // Partial count tsk_dots uses for length n (partials are [2*nv][nblocks]).
 int tsk_nblocks(long n);
 // part <- partials of c = V^H w (sum with sum_partials(part, nb, 2*nv, c)). Returns nb.
+// with_norm: partial column 2*nv holds ||w||^2 (part needs 2*(nv+1)*nb doubles).  gate (device,
+// may be NULL): *gate == 0 skips the pass, leaving zero partials.
 int tsk_dots(hipStream_t s, long n, int nv, const double2* base, long ld, const int* slot,
-             const double2* w, double* part);
-// w <- w + sgn * V c, c: nv complex in device memory.
+             const double2* w, double* part, const double* gate = nullptr, int with_norm = 0);
+// w <- w + sgn * V c, c: nv complex in device memory; *gate == 0 (gate non-null) skips it.
 void tsk_update(hipStream_t s, long n, int nv, const double2* base, long ld, const int* slot,
-                const double2* c, double sgn, double2* w);
+                const double2* c, double sgn, double2* w, const double* gate = nullptr);
+// The DGKS test after a first Gram-Schmidt pass with coefficients c (nv complex) of a vector w
+// of squared norm *wn2: *gate = 1 (a second pass is needed) when ||c||^2 > (1 - eta2) *wn2.
+void tsk_dgks_gate(hipStream_t s, const double* c, int nv, const double* wn2, double eta2, double* gate);
 // Y_l (+)= sum_j G[j*ldg + l] V_j for l < ny; output l at obase + (oslot ? oslot[l] : l) * old.
 void tsk_combine(hipStream_t s, long n, int nv, const double2* base, long ld, const int* slot,
                  const double* G, int ldg, int ny, double2* obase, long old, const int* oslot,
