@@ -474,8 +474,10 @@ __global__ void __launch_bounds__(kBlock) k_b_cg_alpha(const double* part, int n
   }
 }
 
-// e += alpha p ; r -= alpha q ; partial ||r||^2
-template <class SV>
+// (E: e += alpha p ;) r -= alpha q ; partial ||r||^2.  Without E the e update waits for
+// k_b_cg_xpay of the same iteration, which reads p anyway (one field pass fewer per iteration,
+// the same bits: p does not change in between).
+template <class SV, bool E>
 __global__ void __launch_bounds__(kBlock)
 k_b_cg_xr(Seg g, const double* st, const SV* p, const SV* q, SV* e, SV* r, const int* __restrict__ active,
           double* __restrict__ part) {
@@ -485,7 +487,7 @@ k_b_cg_xr(Seg g, const double* st, const SV* p, const SV* q, SV* e, SV* r, const
     const float a = (float)st[rhs * NS + B_CGA];
     const long off = seg_off(g, rhs), n = seg_len(g, rhs);
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-      sst(e + off + i, c_axpy(a, sld(p + off + i), sld(e + off + i)));
+      if (E) sst(e + off + i, c_axpy(a, sld(p + off + i), sld(e + off + i)));
       const float2 v = c_axpy(-a, sld(q + off + i), sld(r + off + i));
       sst(r + off + i, v);
       acc = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, acc));
@@ -514,16 +516,20 @@ k_b_cg_beta(const double* ps, int nps, const double* pr, int npr, double* st, co
   }
 }
 
-// p = s + beta p
-template <class SV>
+// (E: e += alpha p, the update k_b_cg_xr<SV, false> left ;) p = s + beta p
+template <class SV, bool E>
 __global__ void __launch_bounds__(kBlock)
-k_b_cg_xpay(Seg g, const double* st, const SV* s, SV* p, const int* __restrict__ active) {
+k_b_cg_xpay(Seg g, const double* st, const SV* s, SV* p, SV* e, const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const float b = (float)st[rhs * NS + B_CGB];
+  const float a = E ? (float)st[rhs * NS + B_CGA] : 0.f;
   const long off = seg_off(g, rhs), n = seg_len(g, rhs);
-  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
-    sst(p + off + i, c_axpy(b, sld(p + off + i), sld(s + off + i)));
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    const float2 pv = sld(p + off + i);
+    if (E) sst(e + off + i, c_axpy(a, pv, sld(e + off + i)));
+    sst(p + off + i, c_axpy(b, pv, sld(s + off + i)));
+  }
 }
 
 // partial ||a||^2 of low-precision fields, column-major [rhs][G]
@@ -1241,8 +1247,14 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
         bwilson_lo(bt, 0, p, q, 1, bt.part.get());
         hipLaunchKernelGGL(k_b_cg_alpha, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.st.get(),
                            bt.active.get());
-        hipLaunchKernelGGL((k_b_cg_xr<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), p, q, e, r32,
-                           bt.active.get(), bt.part2.get());
+        // e += alpha p goes with r -= alpha q before a reliable update (which reads e), else
+        // with p = s + beta p below
+        if (update)
+          hipLaunchKernelGGL((k_b_cg_xr<SV, true>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), p, q, e, r32,
+                             bt.active.get(), bt.part2.get());
+        else
+          hipLaunchKernelGGL((k_b_cg_xr<SV, false>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), p, q, e, r32,
+                             bt.active.get(), bt.part2.get());
         if (update) {
           // reliable update: x64 += e, r = b - M x64 in FP64, the FP32 residual restarts from it
           // and the search direction p is kept
@@ -1256,7 +1268,12 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
         bwilson_lo(bt, 1, r32, sv, 1, bt.part.get());
         hipLaunchKernelGGL(k_b_cg_beta, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.part2.get(), G,
                            bt.st.get(), bt.active.get());
-        hipLaunchKernelGGL((k_b_cg_xpay<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, bt.active.get());
+        if (update)
+          hipLaunchKernelGGL((k_b_cg_xpay<SV, false>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, e,
+                             bt.active.get());
+        else
+          hipLaunchKernelGGL((k_b_cg_xpay<SV, true>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, e,
+                             bt.active.get());
         DL_HIP(hipGetLastError());
       };
       constexpr long kStall = 25L * check;
