@@ -752,6 +752,20 @@ static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
 // st[B_RR], st[B_NRM], st[B_INV].
 static void true_residual(Batch& bt, const double2* B, const double2* X, double2* R, double2* T,
                           bool x_zero = false) {
+  dl_op* op0 = bt.items[0].op;
+  if (!x_zero && bt.single() && !op0->lat.eo) {
+    // one whole-lattice operator: the FP64 stencil forms r = b - M x and ||r||^2 itself
+    int nbs;
+    {
+      TimeScope ts(bt.ctx, T_WILSON64, bt.wilson_bytes(576.0, 576.0));  // reads x and b, writes r
+      nbs = wilson_residual_f64(bt.s, op0->lat, op0->U.get(), op0->kappa, X, B, R, op0->lat.nc, bt.nr,
+                                bt.active.get(), bt.part.get());
+    }
+    hipLaunchKernelGGL(k_b_fin_store, dim3(bt.nr), dim3(kBlock), 0, bt.s, bt.part.get(), nbs, bt.st.get(),
+                       (int)B_RR);
+    DL_HIP(hipGetLastError());
+    return;
+  }
   if (!x_zero) bwilson64(bt, 0, X, T);
   hipLaunchKernelGGL(k_b_resid, dim3(bt.G, bt.nr), dim3(kBlock), 0, bt.s, bt.seg, B, x_zero ? nullptr : T, R,
                      bt.active.get(), bt.part.get());

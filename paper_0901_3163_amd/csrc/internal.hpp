@@ -188,6 +188,12 @@ int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double
                    const SV* in, SV* out, long fstride, int nrhs, int red, const double* scale,
                    const int* active, double* part, WilsonCfg cfg = WilsonCfg());
 
+// r = b - M x in FP64 for nrhs whole-lattice fields at stride fstride, with ||r||^2 partials
+// column-major [nrhs][nbs] (an inactive rhs: r untouched, partials 0); returns nbs.  The time-marching stencil
+// computes it in its epilogue, so M x is never stored.
+int wilson_residual_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, const double2* x,
+                        const double2* b, double2* r, long fstride, int nrhs, const int* active, double* part);
+
 // Several lattices in one stencil launch (the multi-lattice batched solver): one item per
 // operator, right-hand sides [rhs0, rhs0 + nrhs) of the batch, nbs = ceil(V / 256) site blocks,
 // blocks [block0, block0 + nbs * nrhs) of the launch.  Field j of the batch starts at offs[j].

@@ -297,20 +297,25 @@ template void wilson_multi<float, bf2>(hipStream_t, const WilsonItem*, int, int,
 // read once along t; the x, y, z neighbours lie in the same time slice, which the
 // blocks of one XCD walk together, so they come from L2.  A block is NT consecutive
 // (x, y, z) sites of one time chunk of one right-hand side; logical block = (site block,
-// rhs) with the same order options as k_wilson.
-template <class R, class SV, int WHICH, int RED, int NT>
+// rhs) with the same order options as k_wilson.  RES: out = add - op(in) (the residual
+// b - M x, with its ||.||^2 under RED = 1), so M x is never written out.
+template <class R, class SV, int WHICH, int RED, int NT, bool RES = false>
 __global__ void __launch_bounds__(NT)
 k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
             SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
             int Lt, long V, long Vpad, int T, int nb3, int nbs, int order, const double* __restrict__ scale,
-            const int* __restrict__ active, double* __restrict__ part) {
+            const int* __restrict__ active, double* __restrict__ part, const SV* __restrict__ add) {
   using C = typename CT<R>::type;
   const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
   const int rhs = order == 1 ? lb / nbs : lb % nrhs;
   const int sb = order == 1 ? lb % nbs : lb / nrhs;
-  if (active && !active[rhs]) return;
+  if (active && !active[rhs]) {
+    if (RES && RED != 0 && threadIdx.x == 0) part[(long)rhs * nbs + sb] = 0.0;  // an inactive rhs sums to 0
+    return;
+  }
   in += rhs * fstride;
   out += rhs * fstride;
+  if (RES) add += rhs * fstride;
   const int b3 = sb % nb3, tc = sb / nb3;
   const int V3 = Lx * Ly * Lz;
   const int s3 = b3 * NT + (int)threadIdx.x;
@@ -395,6 +400,10 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
         const C p = cen[c];
         C r = CT<R>::make(fma(mk, acc[c].x, p.x) * sc, fma(mk, acc[c].y, p.y) * sc);
         if (WHICH == 2 && c >= 6) r = CT<R>::make(-r.x, -r.y);
+        if (RES) {
+          const C bv = sld(add + sp_base(site) + c * kTile);
+          r = CT<R>::make(bv.x - r.x, bv.y - r.y);
+        }
         sst(op + c * kTile, r);
         if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
         if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
@@ -936,7 +945,7 @@ static void launch_tm(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, dou
   const int* L = lat.L;
   hipLaunchKernelGGL((k_wilson_tm<R, SV, WHICH, RED, NT>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
-                     order, scale, active, part);
+                     order, scale, active, part, static_cast<const SV*>(nullptr));
 }
 
 template <class R, class SV, int WHICH, int RED, int NT, int OCC>
@@ -1260,6 +1269,21 @@ void eo_hop_f64(hipStream_t s, const Lattice& lat, const double2* U, double fac,
   hipLaunchKernelGGL(k_eo_hop_f64, dim3((unsigned)((lat.V + 255) / 256)), dim3(256), 0, s, U, in, add, out, fac, L[0],
                      L[1], L[2], L[3], lat.V, lat.ntiles * kTile, par);
   DL_HIP(hipGetLastError());
+}
+
+int wilson_residual_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, const double2* x,
+                        const double2* b, double2* r, long fstride, int nrhs, const int* active, double* part) {
+  if (lat.eo) fail(DL_E_INVALID, "the fused residual serves whole-lattice operators");
+  constexpr int v = 6;  // time-marching, 256 threads, chunks of 16 slices
+  const int nbs = tm_nb3(lat, v) * tm_chunks(lat, v);
+  if (nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
+  if ((long)nbs * nrhs > 2147483647L) fail(DL_E_INVALID, "grid too large");
+  const int* L = lat.L;
+  hipLaunchKernelGGL((k_wilson_tm<double, double2, 0, 1, 256, true>), dim3(nbs * nrhs), dim3(256), 0, s, U, x, r,
+                     fstride, nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v],
+                     tm_nb3(lat, v), nbs, 2, static_cast<const double*>(nullptr), active, part, b);
+  DL_HIP(hipGetLastError());
+  return nbs;
 }
 
 int wilson_nbs(const Lattice& lat, const WilsonCfg& cfg) {

@@ -207,7 +207,8 @@ def test_kept_reorthogonalisation_converges_to_the_same_results(gpu_ctx, c1_conf
 
 def test_stencil_timer_families_match_mvp_counts(gpu_ctx, c1_config, g5_first):
     """One rhs: every FP64 stencil launch is one MVP of the FP64 path ("wilson64"), and on the
-    batched path the low-precision launches ("wilson") plus the FP64 ones equal its MVPs."""
+    batched path the low-precision launches ("wilson") plus the FP64 ones equal its MVPs; there
+    (gamma5 M) every FP64 launch forms a true residual r = b - M x, which reads b as well."""
     from paper_0901_3163_amd import deflan
     op, eig = g5_first["op"], g5_first["eig"]
     b = gaussian_spinor(c1_config["dims"], 130)[None]
@@ -225,7 +226,7 @@ def test_stencil_timer_families_match_mvp_counts(gpu_ctx, c1_config, g5_first):
     nlo, _, bylo = gpu_ctx.kernel_time("wilson")
     gpu_ctx.timing(False)
     assert nlo > 0 and n64 > 0 and nlo + n64 == sb[0]["mvp"]
-    assert by64 == pytest.approx(n64 * 960.0 * op.V)
+    assert by64 == pytest.approx(n64 * (576.0 + 576.0) * op.V)
     assert bylo == pytest.approx(nlo * (288.0 + 96.0) * op.V)
 
 
