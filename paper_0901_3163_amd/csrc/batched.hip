@@ -433,6 +433,22 @@ k_b_accum(Seg g, double2* x, const SV* e, const int* __restrict__ active) {
   }
 }
 
+// x64 += e, then e = 0 and the rhs's state flag cleared: the CGLS reliable update whose
+// residual the FP64 stencil stores straight into the low-precision r (k_b_cg_start's other work)
+template <class SV>
+__global__ void __launch_bounds__(kBlock)
+k_b_accum_clear(Seg g, double2* x, SV* e, double* st, const int* __restrict__ active) {
+  const int rhs = blockIdx.y;
+  if (active && !active[rhs]) return;
+  const long off = seg_off(g, rhs), n = seg_len(g, rhs);
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    const float2 d = sld(e + off + i);
+    x[off + i] = make_double2(x[off + i].x + (double)d.x, x[off + i].y + (double)d.y);
+    sst(e + off + i, make_float2(0.f, 0.f));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[rhs * NS + B_FLAG] = 0.0;
+}
+
 // gamma5 on FP64 fields (batched)
 __global__ void __launch_bounds__(kBlock) k_b_gamma5(Seg g, const double2* in, double2* out, const int* active) {
   const int rhs = blockIdx.y;
@@ -1269,18 +1285,29 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
         else
           hipLaunchKernelGGL((k_b_cg_xr<SV, false>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), p, q, e, r32,
                              bt.active.get(), bt.part2.get());
+        int npr = G;  // partials per rhs of ||r||^2 in part2
         if (update) {
-          // reliable update: x64 += e, r = b - M x64 in FP64, the FP32 residual restarts from it
-          // and the search direction p is kept
-          hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
-          true_residual(bt, B, X, R64.get(), T64.get());
-          hipLaunchKernelGGL((k_b_cg_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e, bt.st.get(),
-                             bt.active.get());
-          hipLaunchKernelGGL((k_b_norm2_f32<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, r32, bt.active.get(),
-                             bt.part2.get());
+          // reliable update: x64 += e, r = b - M x64 in FP64, the low-precision residual restarts
+          // from it and the search direction p is kept
+          dl_op* op0 = bt.items[0].op;
+          if (bt.single() && !op0->lat.eo) {
+            // the FP64 stencil stores b - M x64 straight into r32 (rounded) with its ||.||^2
+            hipLaunchKernelGGL((k_b_accum_clear<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.st.get(),
+                               bt.active.get());
+            TimeScope ts(bt.ctx, T_WILSON64, bt.wilson_bytes(576.0, 384.0 + kSpin * sizeof(SV)));
+            npr = wilson_residual_f64(s, op0->lat, op0->U.get(), op0->kappa, X, B, nullptr, op0->lat.nc, nr,
+                                      bt.active.get(), bt.part2.get(), r32, sizeof(SV) == 4 ? DL_BF16 : DL_FP32);
+          } else {
+            hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
+            true_residual(bt, B, X, R64.get(), T64.get());
+            hipLaunchKernelGGL((k_b_cg_start<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, R64.get(), r32, e,
+                               bt.st.get(), bt.active.get());
+            hipLaunchKernelGGL((k_b_norm2_f32<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, r32, bt.active.get(),
+                               bt.part2.get());
+          }
         }
         bwilson_lo(bt, 1, r32, sv, 1, bt.part.get());
-        hipLaunchKernelGGL(k_b_cg_beta, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.part2.get(), G,
+        hipLaunchKernelGGL(k_b_cg_beta, dim3(nr), dim3(kBlock), 0, s, bt.part.get(), nbs, bt.part2.get(), npr,
                            bt.st.get(), bt.active.get());
         if (update)
           hipLaunchKernelGGL((k_b_cg_xpay<SV, false>), dim3(G, nr), dim3(kBlock), 0, s, g, bt.st.get(), sv, p, e,

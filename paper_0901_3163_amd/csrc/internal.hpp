@@ -189,10 +189,13 @@ int wilson_batched(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double
                    const int* active, double* part, WilsonCfg cfg = WilsonCfg());
 
 // r = b - M x in FP64 for nrhs whole-lattice fields at stride fstride, with ||r||^2 partials
-// column-major [nrhs][nbs] (an inactive rhs: r untouched, partials 0); returns nbs.  The time-marching stencil
-// computes it in its epilogue, so M x is never stored.
+// column-major [nrhs][nbs] (an inactive rhs: r untouched, partials 0); returns nbs.  The
+// time-marching stencil computes it in its epilogue, so M x is never stored.  With lo (and
+// r == nullptr) the residual is stored only rounded to lo_prec (DL_FP32: float2, DL_BF16: bf2,
+// through FP32) at the same offsets, and the partials sum the squares of the stored values.
 int wilson_residual_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, const double2* x,
-                        const double2* b, double2* r, long fstride, int nrhs, const int* active, double* part);
+                        const double2* b, double2* r, long fstride, int nrhs, const int* active, double* part,
+                        void* lo = nullptr, int lo_prec = 0);
 
 // Several lattices in one stencil launch (the multi-lattice batched solver): one item per
 // operator, right-hand sides [rhs0, rhs0 + nrhs) of the batch, nbs = ceil(V / 256) site blocks,

@@ -298,13 +298,16 @@ template void wilson_multi<float, bf2>(hipStream_t, const WilsonItem*, int, int,
 // blocks of one XCD walk together, so they come from L2.  A block is NT consecutive
 // (x, y, z) sites of one time chunk of one right-hand side; logical block = (site block,
 // rhs) with the same order options as k_wilson.  RES: out = add - op(in) (the residual
-// b - M x, with its ||.||^2 under RED = 1), so M x is never written out.
-template <class R, class SV, int WHICH, int RED, int NT, bool RES = false>
+// b - M x, with its ||.||^2 under RED = 1), so M x is never written out.  LO = 1 / 2 (with RES):
+// the residual is stored only rounded to FP32 / BF16 (through FP32) in lo, at the same element
+// offsets, and RED = 1 sums the squares of the stored values.
+template <class R, class SV, int WHICH, int RED, int NT, bool RES = false, int LO = 0>
 __global__ void __launch_bounds__(NT)
 k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
             SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
             int Lt, long V, long Vpad, int T, int nb3, int nbs, int order, const double* __restrict__ scale,
-            const int* __restrict__ active, double* __restrict__ part, const SV* __restrict__ add) {
+            const int* __restrict__ active, double* __restrict__ part, const SV* __restrict__ add,
+            void* __restrict__ lo = nullptr) {
   using C = typename CT<R>::type;
   const int lb = order == 2 ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
   const int rhs = order == 1 ? lb / nbs : lb % nrhs;
@@ -314,13 +317,16 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
     return;
   }
   in += rhs * fstride;
-  out += rhs * fstride;
+  if (LO == 0) out += rhs * fstride;
   if (RES) add += rhs * fstride;
+  float2* lo32 = LO == 1 ? static_cast<float2*>(lo) + rhs * fstride : nullptr;
+  bf2* lo16 = LO == 2 ? static_cast<bf2*>(lo) + rhs * fstride : nullptr;
   const int b3 = sb % nb3, tc = sb / nb3;
   const int V3 = Lx * Ly * Lz;
   const int s3 = b3 * NT + (int)threadIdx.x;
   double red = 0.0;
-  if (b3 == 0 && (tc + 1) * T >= Lt) {
+  // (the low-precision residual's padding sites are zero already and stay so)
+  if (LO == 0 && b3 == 0 && (tc + 1) * T >= Lt) {
     // padding sites of the last tile are kept at zero (written by the last chunk's first block)
     for (long sp = V + threadIdx.x; sp < Vpad; sp += NT) {
       SV* op = out + sp_base((int)sp);
@@ -404,7 +410,19 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
           const C bv = sld(add + sp_base(site) + c * kTile);
           r = CT<R>::make(bv.x - r.x, bv.y - r.y);
         }
-        sst(op + c * kTile, r);
+        if (LO != 0) {
+          const float2 vf = make_float2((float)r.x, (float)r.y);
+          float2 vs = vf;  // the stored value, as read back
+          if (LO == 1) {
+            lo32[sp_base(site) + c * kTile] = vf;
+          } else {
+            sst(lo16 + sp_base(site) + c * kTile, vf);
+            vs = make_float2(__uint_as_float((unsigned)f2bf(vf.x) << 16), __uint_as_float((unsigned)f2bf(vf.y) << 16));
+          }
+          r = CT<R>::make((R)vs.x, (R)vs.y);
+        } else {
+          sst(op + c * kTile, r);
+        }
         if (RED == 1) sred = fma(r.x, r.x, fma(r.y, r.y, sred));
         if (RED == 2) sred = fma(p.x, r.x, fma(p.y, r.y, sred));
       }
@@ -945,7 +963,7 @@ static void launch_tm(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, dou
   const int* L = lat.L;
   hipLaunchKernelGGL((k_wilson_tm<R, SV, WHICH, RED, NT>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out, fstride, nrhs,
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
-                     order, scale, active, part, static_cast<const SV*>(nullptr));
+                     order, scale, active, part, static_cast<const SV*>(nullptr), static_cast<void*>(nullptr));
 }
 
 template <class R, class SV, int WHICH, int RED, int NT, int OCC>
@@ -1272,16 +1290,24 @@ void eo_hop_f64(hipStream_t s, const Lattice& lat, const double2* U, double fac,
 }
 
 int wilson_residual_f64(hipStream_t s, const Lattice& lat, const double2* U, double kappa, const double2* x,
-                        const double2* b, double2* r, long fstride, int nrhs, const int* active, double* part) {
+                        const double2* b, double2* r, long fstride, int nrhs, const int* active, double* part,
+                        void* lo, int lo_prec) {
   if (lat.eo) fail(DL_E_INVALID, "the fused residual serves whole-lattice operators");
+  if ((lo == nullptr) == (r == nullptr)) fail(DL_E_INVALID, "the fused residual goes to r or to lo");
   constexpr int v = 6;  // time-marching, 256 threads, chunks of 16 slices
   const int nbs = tm_nb3(lat, v) * tm_chunks(lat, v);
   if (nbs > kMaxPartials) fail(DL_E_INVALID, "lattice too large for fused reduction");
   if ((long)nbs * nrhs > 2147483647L) fail(DL_E_INVALID, "grid too large");
   const int* L = lat.L;
-  hipLaunchKernelGGL((k_wilson_tm<double, double2, 0, 1, 256, true>), dim3(nbs * nrhs), dim3(256), 0, s, U, x, r,
-                     fstride, nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v],
-                     tm_nb3(lat, v), nbs, 2, static_cast<const double*>(nullptr), active, part, b);
+#define DL_RES(LOP)                                                                                                 \
+  hipLaunchKernelGGL((k_wilson_tm<double, double2, 0, 1, 256, true, LOP>), dim3(nbs * nrhs), dim3(256), 0, s, U, x,  \
+                     r, fstride, nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v],       \
+                     tm_nb3(lat, v), nbs, 2, static_cast<const double*>(nullptr), active, part, b, lo)
+  if (!lo) DL_RES(0);
+  else if (lo_prec == DL_FP32) DL_RES(1);
+  else if (lo_prec == DL_BF16) DL_RES(2);
+  else fail(DL_E_INVALID, "lo_prec must be DL_FP32 or DL_BF16");
+#undef DL_RES
   DL_HIP(hipGetLastError());
   return nbs;
 }
