@@ -399,7 +399,7 @@ k_wilson_tm(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
         project<3, -SF>(cen, h);
         mul_half<true>(u, h, gb);
       }
-      SV* op = out + sp_base(site);
+      SV* op = LO == 0 ? out + sp_base(site) : nullptr;  // (LO: out is not used)
       R sred = 0;  // this site's share of the reduction, summed in R
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
