@@ -716,6 +716,7 @@ def evenodd_study(args):
     import torch
     from lattice_inputs import gaussian_spinor, gaussian_spinors_device, su3_links
     from paper_0901_3163_amd import deflan
+    reorth = deflan.DL_REORTH_KEPT if args.reorth == "kept" else deflan.DL_REORTH_FULL
     os.environ.setdefault("DEFLAN_VERBOSE", "1")
     e = kappa_for("16x16x16x32/seed10")
     dims, kappa, tol = tuple(e["dims"]), e["kappa"], args.tol
@@ -740,9 +741,9 @@ def evenodd_study(args):
         if op is half:
             bh = op.eo_prepare(b1)
             tol1 = tol * float(torch.linalg.vector_norm(b1)) / float(torch.linalg.vector_norm(bh))
-            _, eig, st1 = op.solve_first(bh, args.m, args.k, tol1)
+            _, eig, st1 = op.solve_first(bh, args.m, args.k, tol1, reorth=reorth)
         else:
-            _, eig, st1 = op.solve_first(b1, args.m, args.k, tol)
+            _, eig, st1 = op.solve_first(b1, args.m, args.k, tol, reorth=reorth)
         eig.lower(deflan.DL_FP32)
         torch.cuda.synchronize()
         t_first = time.time() - t0
