@@ -597,8 +597,14 @@ def kernel_only(args):
     dims = tuple(e["dims"])
     nrhs = args.test_rhs
     ctx = deflan.Context(0)
-    op = deflan.Operator(ctx, dims, torch.from_numpy(su3_links(dims, 20, e["eps"])).cuda(), e["kappa"],
-                         deflan.DL_MDAGM)
+    if args.ko_lattice:
+        # an HBM-resident lattice of the sweep instead (links: a seeded 8^4 field tiled)
+        dims = tuple(int(v) for v in args.ko_lattice.split("x"))
+        links = tiled_links(dims)
+    else:
+        links = su3_links(dims, 20, e["eps"])
+    op = deflan.Operator(ctx, dims, torch.from_numpy(links).cuda(), e["kappa"], deflan.DL_MDAGM)
+    del links
     prec = {"fp32": deflan.DL_FP32, "bf16": deflan.DL_BF16}[args.storage]
     op.tune_wilson(prec, nrhs, reps=3)
     ms, by = op.bench_wilson(deflan.DL_APPLY_M, prec, nrhs, args.reps)
@@ -848,6 +854,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the Dslash bandwidth sweep")
     ap.add_argument("--kappa", type=float, default=None, help="override the stored kappa (exploration only)")
     ap.add_argument("--kernel-only", action="store_true", help="run only the dominant kernel + a copy (profiling)")
+    ap.add_argument("--ko-lattice", default=None, help="--kernel-only on this lattice (e.g. 32x32x32x64) instead")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--train-rhs", type=int, default=24, help="training pairs of the learned guess (0: no net)")
     ap.add_argument("--train-steps", type=int, default=100, help="Adam steps per field and pass")
