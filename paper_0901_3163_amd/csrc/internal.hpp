@@ -155,8 +155,10 @@ void pack_links(hipStream_t s, const Lattice& lat, const double2* host_layout, d
 // the x, y links too, FP32 only; T = 8, 8, 16, 8; 14 issues each hop's loads one hop ahead); order = block order (0: rhs fastest, XCD-contiguous; 1: sites
 // fastest, XCD-contiguous; 2: rhs fastest, hardware order).  Chosen by the autotuner.
 // 15-17 = one thread per site for 2 or 4 rhs of a group (256 threads; 2 rhs with 128 threads), each
-// hop's link loaded once for the group.
-constexpr int kWilsonVariants = 18;
+// hop's link loaded once for the group.  18-19 = the slice-staged form with each block a box of
+// whole x rows spanning y and z (T = 8, 16), so z neighbours inside the box come from LDS too
+// (variants 12 and 13 where no box tiles the slice).
+constexpr int kWilsonVariants = 20;
 constexpr int kWilsonOrders = 3;
 struct WilsonCfg {
   int variant = 0;

@@ -464,6 +464,33 @@ __device__ __forceinline__ HopSrc hop_src(int hh, int d, int s3, int base3, int 
   r.near = mu < 2 && r.li < (unsigned)NT && nb3 < V3;
   return r;
 }
+// Neighbour source for a block that is a box of whole x rows: Lx x by x bz sites of the
+// slice, thread tid = lx + Lx (ly + by lz).  The x neighbour is always in the box (the box
+// holds the whole periodic row); the y (z) neighbour is in it unless the site sits on the
+// box's y (z) face, or the box spans the lattice in y (z), where the periodic neighbour is
+// in the box again.  d is the neighbour's site offset, as for hop_src.
+__device__ __forceinline__ HopSrc hop_src_box(int hh, int d, int tid, int Lx, int ly, int lz, int by, int bz,
+                                              int Ly, int Lz) {
+  const int mu = hh >> 1;
+  const bool fwd = (hh & 1) == 0;
+  HopSrc r;
+  r.d = d;
+  int dl;
+  if (mu == 0) {
+    r.near = true;
+    dl = d;  // the row's own sites: lx + 1 or the periodic wrap, as in site numbering
+  } else if (mu == 1) {
+    const bool face = fwd ? ly == by - 1 : ly == 0;
+    r.near = !face || by == Ly;
+    dl = (face ? (fwd ? 1 - by : by - 1) : (fwd ? 1 : -1)) * Lx;
+  } else {
+    const bool face = fwd ? lz == bz - 1 : lz == 0;
+    r.near = !face || bz == Lz;
+    dl = (face ? (fwd ? 1 - bz : bz - 1) : (fwd ? 1 : -1)) * (Lx * by);
+  }
+  r.li = (unsigned)(tid + dl);
+  return r;
+}
 template <class SV>
 __device__ __forceinline__ SpRaw<SV> fetch_sp(const SV* __restrict__ in, int site) {
   SpRaw<SV> r;
@@ -501,12 +528,16 @@ __device__ __forceinline__ Lk<C> fetch_link(const C* __restrict__ U, const C* pu
 // 16 x 16 plane per block that is all of them), the z neighbours and the z, t links come
 // from memory, and the t hops are carried along t as in k_wilson_tm.  Same arithmetic and
 // order as k_wilson.
-template <class R, class SV, int WHICH, int RED, int NT, bool LK, bool PF>
+// BOX: the block is instead a box of by x bz whole x rows (Lx by bz = NT, by | Ly, bz | Lz),
+// so the z neighbours inside the box come from LDS as well; for a 16^3 or 32^3 slice a box
+// of 4 x 4 or 4 x 2 rows leaves 1-1.5 neighbour spinors per site to memory instead of 2-2.25.
+template <class R, class SV, int WHICH, int RED, int NT, bool LK, bool PF, bool BOX = false>
 __global__ void __launch_bounds__(NT)
 k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ in,
              SV* __restrict__ out, long fstride, int nrhs, double kappa, int Lx, int Ly, int Lz,
              int Lt, long V, long Vpad, int T, int nb3, int nbs, int order, const double* __restrict__ scale,
-             const int* __restrict__ active, double* __restrict__ part) {
+             const int* __restrict__ active, double* __restrict__ part, int boy, int boz) {
+  static_assert(!(LK && BOX), "the staged links cover the x and y hops only");
   using C = typename CT<R>::type;
   __shared__ C ps[12 * NT];               // centre spinors of the block's sites, component-major
   __shared__ C pu[LK ? 2 * 9 * NT : 1];   // forward x and y links of the block's sites (LK)
@@ -520,8 +551,14 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
   const int V3 = Lx * Ly * Lz;
   const int base3 = b3 * NT;
   const int tid = (int)threadIdx.x;
-  const int s3 = base3 + tid;
-  const bool valid = s3 < V3;
+  int s3 = base3 + tid, ly = 0, lz = 0;
+  if (BOX) {
+    const int nby = Ly / boy;
+    ly = (tid / Lx) % boy;
+    lz = tid / (Lx * boy);
+    s3 = tid % Lx + Lx * ((b3 % nby) * boy + ly + Ly * ((b3 / nby) * boz + lz));
+  }
+  const bool valid = BOX || s3 < V3;
   double red = 0.0;
   if (b3 == 0 && (tc + 1) * T >= Lt) {
     for (long sp = V + tid; sp < Vpad; sp += NT) {
@@ -590,11 +627,15 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
       auto hop_d = [=](int hh) {
         return hh == 0 ? fx : hh == 1 ? bx : hh == 2 ? fy : hh == 3 ? by : hh == 4 ? fz : bz;
       };
+      auto src_of = [=](int hh) {
+        return BOX ? hop_src_box(hh, hop_d(hh), tid, Lx, ly, lz, boy, boz, Ly, Lz)
+                   : hop_src<NT>(hh, hop_d(hh), s3, base3, V3);
+      };
       HopSrc nsrc{};
       SpRaw<SV> nraw{};
       Lk<C> nu{};
       if (PF) {
-        nsrc = hop_src<NT>(0, hop_d(0), s3, base3, V3);
+        nsrc = src_of(0);
         if (!nsrc.near) nraw = fetch_sp(in, site + nsrc.d);
         nu = fetch_link<LK, NT>(U, pu, 0, nsrc, site, tid);
       }
@@ -611,12 +652,12 @@ k_wilson_tmp(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ 
           raw = nraw;
           lk = nu;
           if (hop2 < 5) {
-            nsrc = hop_src<NT>(hop2 + 1, hop_d(hop2 + 1), s3, base3, V3);
+            nsrc = src_of(hop2 + 1);
             if (!nsrc.near) nraw = fetch_sp(in, site + nsrc.d);
             nu = fetch_link<LK, NT>(U, pu, hop2 + 1, nsrc, site, tid);
           }
         } else {
-          src = hop_src<NT>(hop2, hop_d(hop2), s3, base3, V3);
+          src = src_of(hop2);
           if (!src.near) raw = fetch_sp(in, site + src.d);
           lk = fetch_link<LK, NT>(U, pu, hop2, src, site, tid);
         }
@@ -946,10 +987,12 @@ k_wilson_mr(const typename CT<R>::type* __restrict__ U, const SV* __restrict__ i
 // chunks of T = 4, 8, 16 slices; 7-10: k_wilson_tml with 64 sites per block and
 // (rhs per block, T) = (4, 8), (4, 16), (8, 8), (2, 8).
 // 15-17: k_wilson_mr with (threads per block, rhs per thread) = (256, 2), (256, 4), (128, 2).
+// 18-19: k_wilson_tmp with box blocks of whole x rows (T = 8, 16); where no box tiles the
+// slice they launch variants 12 and 13.
 static constexpr int kVariantNT[kWilsonVariants] = {256, 128, 512, 256, 256, 256, 256, 64, 64, 64, 64, 256, 256, 256, 256,
-                                                    256, 256, 128};
-static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8, 8, 8, 16, 8, 0, 0, 0};
-static constexpr int kVariantRT[kWilsonVariants] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 2};
+                                                    256, 256, 128, 256, 256};
+static constexpr int kVariantT[kWilsonVariants] = {0, 0, 0, 0, 4, 8, 16, 8, 16, 8, 8, 8, 8, 16, 8, 0, 0, 0, 8, 16};
+static constexpr int kVariantRT[kWilsonVariants] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 2, 1, 1};
 
 static int tm_nb3(const Lattice& lat, int v) {
   return (lat.L[0] * lat.L[1] * lat.L[2] + kVariantNT[v] - 1) / kVariantNT[v];
@@ -975,15 +1018,46 @@ static void launch_one(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, do
                      kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, nbs, order, scale, active, part);
 }
 
-template <class R, class SV, int WHICH, int RED, int NT, bool LK, bool PF>
+// Box of whole x rows for k_wilson_tmp<..., BOX>: y and z extents (by, bz) with
+// Lx by bz = nt, by | Ly and bz | Lz, chosen for the fewest neighbour spinors outside the box
+// per site (2 / by for the y faces unless by = Ly, 2 / bz for the z faces unless bz = Lz; a
+// tie goes to the larger by, the longer contiguous run of sites).  False if no box fits.
+static bool tmp_box(const Lattice& lat, int nt, int* by, int* bz) {
+  const int* L = lat.L;
+  if (L[0] > nt || nt % L[0] != 0) return false;
+  const int rows = nt / L[0];
+  double best = 1e300;
+  bool found = false;
+  for (int y = 1; y <= rows; ++y) {
+    if (rows % y != 0 || L[1] % y != 0) continue;
+    const int z = rows / y;
+    if (L[2] % z != 0) continue;
+    const double cost = (y < L[1] ? 2.0 / y : 0.0) + (z < L[2] ? 2.0 / z : 0.0);
+    if (cost <= best) {
+      best = cost;
+      *by = y;
+      *bz = z;
+      found = true;
+    }
+  }
+  return found;
+}
+
+template <class R, class SV, int WHICH, int RED, int NT, bool LK, bool PF, bool BOX = false>
 static void launch_tmp(hipStream_t s, const Lattice& lat, const cplx_t<R>* U, double kappa, const SV* in,
                        SV* out, long fstride, int nrhs, int order, const double* scale, const int* active,
                        double* part, int nbs, int v) {
   const int* L = lat.L;
-  hipLaunchKernelGGL((k_wilson_tmp<R, SV, WHICH, RED, NT, LK, PF>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in, out,
-                     fstride,
-                     nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v], tm_nb3(lat, v), nbs,
-                     order, scale, active, part);
+  int by = 0, bz = 0;
+  if (BOX && !tmp_box(lat, NT, &by, &bz)) {
+    // no box tiles this slice: the same chunks with blocks of consecutive sites
+    launch_tmp<R, SV, WHICH, RED, NT, LK, PF, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active,
+                                                     part, nbs, v);
+    return;
+  }
+  hipLaunchKernelGGL((k_wilson_tmp<R, SV, WHICH, RED, NT, LK, PF, BOX>), dim3(nbs * nrhs), dim3(NT), 0, s, U, in,
+                     out, fstride, nrhs, kappa, L[0], L[1], L[2], L[3], lat.V, lat.ntiles * kTile, kVariantT[v],
+                     tm_nb3(lat, v), nbs, order, scale, active, part, by, bz);
 }
 
 template <class R, class SV, int WHICH, int RED, int RB>
@@ -1040,6 +1114,10 @@ static void launch_variant(int variant, hipStream_t s, const Lattice& lat, const
     case 12: case 13:
       launch_tmp<R, SV, WHICH, RED, 256, false, false>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active,
                                                        part, nbs, variant);
+      break;
+    case 18: case 19:
+      launch_tmp<R, SV, WHICH, RED, 256, false, false, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale,
+                                                             active, part, nbs, variant);
       break;
     case 14:
       launch_tmp<R, SV, WHICH, RED, 256, false, true>(s, lat, U, kappa, in, out, fstride, nrhs, order, scale, active,

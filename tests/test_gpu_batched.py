@@ -139,6 +139,30 @@ def test_batched_solver_in_each_stencil_family(gpu_ctx, c1_config, variant, monk
     op.close()
 
 
+@pytest.mark.parametrize("variant", [18, 19])
+def test_batched_cg_with_box_blocks(gpu_ctx, variant, monkeypatch):
+    """Batched D-CG on M^dag M (FP32 and BF16 storage) with the stencil forced to the box
+    shapes on an 8^4 lattice (boxes of 8 x 4 rows: y periodic inside the box, z faces between
+    boxes), so the fused ||Mp||^2 and residual reductions sum over box-shaped blocks: every
+    rhs reaches tol by the oracle's own M."""
+    from paper_0901_3163_amd import deflan
+    dims, kappa = (8, 8, 8, 8), 0.13
+    U = su3_links(dims, 5, 0.5)
+    monkeypatch.setenv("DEFLAN_WILSON_VARIANT", f"{variant},0")
+    op = deflan.Operator(gpu_ctx, dims, U, kappa, deflan.DL_MDAGM)
+    _, eig, _ = op.solve_first(gaussian_spinor(dims, 300), 40, 16, 1e-10)
+    B = np.stack([gaussian_spinor(dims, 310 + i) for i in range(4)] + [point_source(dims, 7, 2, 1)])
+    ora = dirac.WilsonOperator(U, dims, kappa)
+    for storage in (deflan.DL_FP32, deflan.DL_BF16):
+        X, sts, rc = op.solve_next(B, eig, 1e-10, storage=storage, batched=1)
+        assert rc == deflan.DL_OK, storage
+        for i in range(len(B)):
+            r = np.linalg.norm(B[i].ravel() - ora.M(X[i].ravel())) / np.linalg.norm(B[i])
+            assert sts[i]["relres"] <= 1e-10 and r <= 1.0001e-10, (storage, i, r)
+    eig.close()
+    op.close()
+
+
 def test_batched_cg_reliable_updates(gpu_ctx, c1_config):
     """Batched D-CG with FP64 reliable updates every 10 or 50 iterations inside each restart
     cycle (search direction kept) and without them: all reach tol and the same solution, at

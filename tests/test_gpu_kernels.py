@@ -129,10 +129,12 @@ def test_tsk_project_and_combine(gpu_ctx, n, nv):
     assert _rel(Y, G.T @ V) < 1e-13
 
 
-N_VARIANTS = 18  # launch shapes: 0-3 per site, 4-6 time-marching, 7-10 LDS links, 11-14 LDS slice, 15-17 rhs per thread
+N_VARIANTS = 20  # launch shapes: 0-3 per site, 4-6 time-marching, 7-10 LDS links, 11-14 LDS slice,
+# 15-17 rhs per thread, 18-19 LDS slice in boxes of whole x rows
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 16), (16, 16, 16, 32)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 16), (16, 16, 16, 32), (16, 4, 4, 8),
+                                  (8, 16, 4, 4)])
 def test_multi_rhs_apply_every_variant(gpu_ctx, dims, monkeypatch):
     """The multi-rhs stencil in every launch shape and block order, FP64 and FP32, on 3 fields.
 
@@ -145,7 +147,11 @@ def test_multi_rhs_apply_every_variant(gpu_ctx, dims, monkeypatch):
     launch shapes of one precision give bitwise the same numbers (the same operations in
     the same order), so time-marching and per-site forms are interchangeable for the tuner.
     The (3, 5, 7, 6) lattice has 105 sites per time slice (not a multiple of the block) and 6
-    slices (not a multiple of the time chunk); (16, 16, 16, 32) is the benchmark lattice.
+    slices (not a multiple of the time chunk); (16, 16, 16, 32) is the benchmark lattice.  The
+    box shapes (18, 19) run as boxes of 8 x 4 rows of 8 on (8, 8, 8, 16), 4 x 4 rows of 16 on
+    the benchmark lattice, the whole 16 x 4 x 4 slice on (16, 4, 4, 8) (periodic y and z
+    neighbours inside the box) and 8 x 4 rows of 8 on (8, 16, 4, 4) (y faces inside the
+    lattice, z periodic inside the box); on the other lattices they fall back to 12 and 13.
     """
     from paper_0901_3163_amd import deflan
     U = su3_links(dims, seed=21)
