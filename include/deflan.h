@@ -161,7 +161,10 @@ typedef struct {
   double inner_drop;        /* batched path: residual reduction that ends an inner cycle (then
                                FP64 residual, projection, restart); 0 = default: 1e-4 with DL_FP32
                                storage; with DL_BF16 (whose rounding limits one cycle) 1e-2 for
-                               D-MinRes and 1e-3 for D-CG */
+                               D-MinRes, and for D-CG (whose reliable updates carry it further;
+                               much longer cycles let the deflated modes back) 1e-5 from the
+                               projection-only start and 1e-3 with a net (the drops measured
+                               fastest for each start on near-critical fields) */
   int    eig_storage;       /* batched path: eigenvectors the Galerkin projection reads.  DL_FP64
                                (0, default): the handle's FP64 basis.  DL_FP32 / DL_BF16: the
                                lowered copies made by dl_eig_lower (DL_E_INVALID if missing):

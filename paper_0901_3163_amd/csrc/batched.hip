@@ -1081,14 +1081,21 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   // Per-cycle residual drop and D-CG reliable-update interval; 0 in the options = the default
   // for the storage and solver.  BF16 rounding limits what a MinRes cycle can reach, so BF16
   // D-MinRes cycles end at 1e-2.  BF16 D-CG keeps its search direction through FP64 residual
-  // replacements every 8 iterations and runs 1e-3 cycles: on a near-critical 24^3x48 field that
-  // took 410 iterations per rhs (FP32: 392), against 1662 with 1e-2 cycles and updates every 50,
-  // while 1e-4 cycles stalled above their target (BF16 rounding) before the stagnation rule
-  // existed.  A batch that falls back from BF16 to FP32 takes the FP32 defaults for the values
-  // the caller left at 0 and keeps the ones it set.
+  // replacements every 8 iterations and runs 1e-5 cycles from the projection-only start, 1e-3
+  // cycles from a learned start.  On near-critical Wilson fields (min|lambda(gamma5 M)| = 1e-3,
+  // M^dag M, tol 1e-10) 1e-5 cycles took 272 iterations per rhs on 16^3x32 (1e-3: 288), 400 on
+  // 24^3x48 (1e-3: 408) and 8% less time on a batch of four lattices from 8^4 to 20^3x40; each
+  // cycle start costs an FP64 residual and a projection and discards the Krylov space.  Longer
+  // cycles lose: at 1e-6, or with no restarts, the 16^3x32 field needed 464-479 iterations, as
+  // BF16 rounding brings the deflated low modes back and only the projection removes them
+  // cheaply.  From the learned start on the same fields 1e-3 cycles took 264.6 iterations, 1e-4
+  // 275, 3e-5 272 and 1e-5 280.  With 1e-2 cycles and updates every 50 the 24^3x48 field took
+  // 1662.  A batch that falls back from BF16 to FP32 takes the FP32 defaults for the values the
+  // caller left at 0 and keeps the ones it set.
   const bool drop_default = o.inner_drop == 0.0, rel_default = o.reliable_every == 0;
   const bool bf16_cg = o.storage == DL_BF16 && !mr;
-  double inner_drop = drop_default ? (o.storage == DL_BF16 ? (bf16_cg ? 1e-3 : 1e-2) : 1e-4) : o.inner_drop;
+  double inner_drop =
+      drop_default ? (o.storage == DL_BF16 ? (bf16_cg ? (o.net ? 1e-3 : 1e-5) : 1e-2) : 1e-4) : o.inner_drop;
   int rel_opt = rel_default ? (bf16_cg ? 8 : 50) : o.reliable_every;
   bool stalled_any = false;
   const int check = 8;                 // iterations between host checks (even)
