@@ -507,9 +507,10 @@ def ksweep_study(args):
 def multi_lattice(args):
     """Uneven lattices in one batched solve: 16 Gaussian rhs on each of 8^4, 12^4, 16^3x32 and
     20^3x40 (64 in all), D-CG on M^dag M with k = 40, 60, 80, 100 eigenvectors from Lan-DR(k + 40, k)
-    (setup, untimed).  Timed: one dl_solve_next_multi over all 64 rhs (with and without graph
-    replay), the same rhs as four per-lattice batched calls, and plain FP64 D-CG on 2 rhs per
-    lattice (per-rhs time, scaled to 16 rhs).  Prints one JSON line."""
+    (setup, untimed).  Timed, each after a warm-up: one dl_solve_next_multi over all 64 rhs with
+    either stencil form (one work-list launch, or one tuned launch per lattice), with and
+    without graph replay; the same rhs as four per-lattice batched calls; plain FP64 D-CG on 2
+    rhs per lattice (per-rhs time, scaled to 16 rhs).  Prints one JSON line."""
     import torch
     from lattice_inputs import gaussian_spinor, su3_links
     from paper_0901_3163_amd import deflan
@@ -543,18 +544,32 @@ def multi_lattice(args):
         items.append((op, eig, B, tol))
     nrhs = 16 * len(lats)
     out = {}
-    for graph in (False, True):
-        deflan.solve_next_multi(ctx, items, storage=storage, graph=graph)  # warm-up (tuning, graphs)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        Xs, sts, rc = deflan.solve_next_multi(ctx, items, storage=storage, graph=graph)
-        torch.cuda.synchronize()
-        dt = time.time() - t0
-        ok = rc == 0 and all(s["relres"] <= tol for ss in sts for s in ss)
-        out["one_launch_per_stage" + ("_graph" if graph else "")] = dict(
-            value=round(nrhs / dt, 3), unit="RHS/s", seconds=round(dt, 3), all_rhs_converged=bool(ok),
-            iters_per_rhs=float(np.mean([s["iters"] for ss in sts for s in ss])))
-        log(f"multi: one batch over all lattices (graph {graph}): {nrhs / dt:.2f} RHS/s")
+    # one batched solve over all lattices; its stencil stage either one work-list launch over
+    # every lattice ("list") or one launch per lattice in that lattice's tuned shape ("lattice"),
+    # the library's choice by timing unless DEFLAN_MULTI_STENCIL forces one; every other stage
+    # is one launch over all 64 rhs
+    forced = os.environ.get("DEFLAN_MULTI_STENCIL")
+    for form, key in (("list", "one_launch_per_stage"), ("lattice", "per_lattice_stencil_in_one_batch")):
+        os.environ["DEFLAN_MULTI_STENCIL"] = form
+        for graph in (False, True):
+            deflan.solve_next_multi(ctx, items, storage=storage, graph=graph)  # warm-up (tuning, graphs)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            Xs, sts, rc = deflan.solve_next_multi(ctx, items, storage=storage, graph=graph)
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+            ok = rc == 0 and all(s["relres"] <= tol for ss in sts for s in ss)
+            out[key + ("_graph" if graph else "")] = dict(
+                value=round(nrhs / dt, 3), unit="RHS/s", seconds=round(dt, 3), all_rhs_converged=bool(ok),
+                iters_per_rhs=float(np.mean([s["iters"] for ss in sts for s in ss])))
+            log(f"multi: one batch over all lattices, stencil form {form} (graph {graph}): {nrhs / dt:.2f} RHS/s")
+    if forced is None:
+        del os.environ["DEFLAN_MULTI_STENCIL"]
+    else:
+        os.environ["DEFLAN_MULTI_STENCIL"] = forced
+    for op, eig, B, _ in items:  # warm-up of the per-lattice shapes (tuning) as for the work list
+        op.solve_next(B, eig, tol, storage=storage, batched=1)
+    torch.cuda.synchronize()
     t0 = time.time()
     ok = True
     for op, eig, B, _ in items:
@@ -567,6 +582,8 @@ def multi_lattice(args):
     log(f"multi: four per-lattice batches: {nrhs / dt:.2f} RHS/s")
     t_plain = 0.0
     for op, eig, B, _ in items:
+        op.solve_next(B[:1], eig, tol)  # warm-up (tuning of the one-rhs shapes)
+        torch.cuda.synchronize()
         t0 = time.time()
         X, st, rc = op.solve_next(B[:2], eig, tol)
         torch.cuda.synchronize()

@@ -608,6 +608,12 @@ struct Batch {
   // multi-lattice stencil work lists (FP32 and FP64 links)
   DBuf<WilsonItem> wl32, wl64;
   int ml_blocks = 0, ml_pstride = 0;
+  // multi-lattice stencil form, chosen by timing at the first low-precision apply: -1 undecided,
+  // 0 one work-list launch over all lattices, 1 one launch per lattice in its tuned shape (fused
+  // reductions re-strided from ml_part to pw partials per rhs)
+  int ml_mode = -1;
+  int pw = 0;
+  DBuf<double> ml_part;
   // projection over lowered eigenvectors (eig_prec DL_FP32 / DL_BF16): rA rounded for the
   // matrix-core contraction
   int eig_prec = DL_FP64;
@@ -644,8 +650,10 @@ struct Batch {
     for (const auto& it : items) pw = std::max(pw, wilson_max_nbs(it.op->lat));
     pw = std::max(pw, ml_pstride);
     const size_t np = (size_t)nr * pw;
+    this->pw = pw;
     part.alloc(np);
     part2.alloc(np);
+    if (!single()) ml_part.alloc(np);
     active.alloc(nr);
     invs.alloc(nr);
     h_active.assign(nr, 1);
@@ -732,13 +740,94 @@ void Batch::build_worklists() {
   DL_HIP(hipStreamSynchronize(s));
 }
 
-// FP32 stencil over the whole batch; returns the partial stride per rhs of the fused reduction.
+// One lattice's fused-reduction partials (nbs per rhs, column-major) into the batch layout of
+// pw partials per rhs, zero beyond nbs, so that one reduction serves every lattice.
+__global__ void k_restride_partials(const double* __restrict__ src, int nbs, int nr, double* __restrict__ dst,
+                                    int pw) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)nr * pw) return;
+  const int r = (int)(i / pw), sb = (int)(i % pw);
+  dst[i] = sb < nbs ? src[(long)r * nbs + sb] : 0.0;
+}
+
+// The multi-lattice stencil in form `mode` (0 work list, 1 per lattice in its tuned shape); the
+// lattices' fields are consecutive in the batch, lattice i's rhs at [r0, r0 + nr).  Returns the
+// partial stride per rhs of the fused reduction.
+template <class R, class SV>
+static int bwilson_multi(Batch& bt, int mode, int which, const SV* in, SV* out, int red, double* part,
+                         const double* scale) {
+  constexpr int prec = sizeof(R) == 8 ? DL_FP64 : sizeof(SV) == sizeof(float2) ? DL_FP32 : DL_BF16;
+  if (mode == 0) {
+    wilson_multi<R>(bt.s, sizeof(R) == 8 ? bt.wl64.get() : bt.wl32.get(), (int)bt.items.size(), bt.ml_blocks,
+                    bt.ml_pstride, which, in, out, bt.d_off.get(), red, scale, bt.active.get(), part);
+    return red ? bt.ml_pstride : 0;
+  }
+  for (const auto& it : bt.items) {
+    dl_op* op = it.op;
+    const long off = bt.h_off[it.r0];
+    double* ip = red ? bt.ml_part.get() + (size_t)it.r0 * bt.pw : nullptr;
+    const cplx_t<R>* U;
+    if constexpr (sizeof(R) == 8) U = op->U.get();
+    else U = op_links32_public(op);
+    const int nbs = wilson_batched<R>(bt.s, op->lat, U, op->kappa, which, in + off, out + off, op->lat.nc, it.nr, red,
+                                      scale ? scale + it.r0 : nullptr, bt.active.get() + it.r0, ip,
+                                      wilson_cfg(op, prec, it.nr));
+    if (red) {
+      if (nbs > bt.pw) fail(DL_E_INVALID, "stencil partials exceed the batch's partial stride");
+      const long n = (long)it.nr * bt.pw;
+      hipLaunchKernelGGL(k_restride_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, bt.s, ip, nbs, it.nr,
+                         part + (size_t)it.r0 * bt.pw, bt.pw);
+    }
+  }
+  return red ? bt.pw : 0;
+}
+
+// Chooses the multi-lattice stencil form by timing both on this batch (3 applies each after a
+// warm-up; the per-lattice shapes are tuned first).  Inside a graph capture, or with autotuning
+// off, the work list is taken; DEFLAN_MULTI_STENCIL=list or =lattice forces a form.  Kept for
+// the batch's lifetime, so that the partial stride a solve reads stays the same.
+template <class SV>
+static int ml_choose(Batch& bt, int which, const SV* in, SV* out) {
+  constexpr int prec = sizeof(SV) == sizeof(float2) ? DL_FP32 : DL_BF16;
+  if (const char* e = std::getenv("DEFLAN_MULTI_STENCIL")) {
+    if (std::strcmp(e, "list") == 0) return 0;
+    if (std::strcmp(e, "lattice") == 0) return 1;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  DL_HIP(hipStreamIsCapturing(bt.s, &cs));
+  if (cs != hipStreamCaptureStatusNone || !autotune_enabled()) return 0;
+  for (const auto& it : bt.items) (void)wilson_cfg(it.op, prec, it.nr);
+  hipEvent_t a, b;
+  DL_HIP(hipEventCreate(&a));
+  DL_HIP(hipEventCreate(&b));
+  float ms[2] = {0.f, 0.f};
+  for (int m = 0; m < 2; ++m) {
+    bwilson_multi<float, SV>(bt, m, which, in, out, 0, nullptr, nullptr);
+    DL_HIP(hipEventRecord(a, bt.s));
+    for (int rep = 0; rep < 3; ++rep) bwilson_multi<float, SV>(bt, m, which, in, out, 0, nullptr, nullptr);
+    DL_HIP(hipEventRecord(b, bt.s));
+    DL_HIP(hipEventSynchronize(b));
+    DL_HIP(hipEventElapsedTime(&ms[m], a, b));
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  const int mode = ms[1] < ms[0] ? 1 : 0;
+  if (verbose()) {
+    std::fprintf(stderr, "[deflan] multi-lattice stencil (%d lattices, %d rhs): work list %.1f us, per-lattice tuned "
+                 "launches %.1f us -> %s\n", (int)bt.items.size(), bt.nr, 1e3 * ms[0] / 3, 1e3 * ms[1] / 3,
+                 mode ? "per lattice" : "work list");
+    std::fflush(stderr);
+  }
+  return mode;
+}
+
 // Low-precision stencil over the whole batch (FP32 arithmetic and links; spinors stored as SV:
 // float2 or bf2); returns the partial stride per rhs of the fused reduction.
 template <class SV>
 static int bwilson_lo(Batch& bt, int which, const SV* in, SV* out, int red, double* part,
                       const double* scale = nullptr) {
   constexpr int prec = sizeof(SV) == sizeof(float2) ? DL_FP32 : DL_BF16;
+  if (!bt.single() && bt.ml_mode < 0) bt.ml_mode = ml_choose<SV>(bt, which, in, out);
   TimeScope ts(bt.ctx, T_WILSON, bt.wilson_bytes(288.0, 2.0 * kSpin * sizeof(SV)));
   if (bt.single()) {
     dl_op* op = bt.items[0].op;
@@ -746,9 +835,7 @@ static int bwilson_lo(Batch& bt, int which, const SV* in, SV* out, int red, doub
     return wilson_batched<float>(bt.s, op->lat, op_links32_public(op), op->kappa, which, in, out, op->lat.nc, bt.nr,
                                  red, scale, bt.active.get(), part, cfg);
   }
-  wilson_multi<float>(bt.s, bt.wl32.get(), (int)bt.items.size(), bt.ml_blocks, bt.ml_pstride, which, in, out,
-                      bt.d_off.get(), red, scale, bt.active.get(), part);
-  return red ? bt.ml_pstride : 0;
+  return bwilson_multi<float, SV>(bt, bt.ml_mode, which, in, out, red, part, scale);
 }
 
 static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
@@ -760,8 +847,8 @@ static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
                            bt.active.get(), nullptr, cfg);
     return;
   }
-  wilson_multi<double>(bt.s, bt.wl64.get(), (int)bt.items.size(), bt.ml_blocks, bt.ml_pstride, which, in, out,
-                       bt.d_off.get(), 0, nullptr, bt.active.get(), nullptr);
+  // the FP64 applies follow the form chosen for the low-precision ones (work list until then)
+  bwilson_multi<double, double2>(bt, bt.ml_mode == 1 ? 1 : 0, which, in, out, 0, nullptr, nullptr);
 }
 
 // r64 = b - M x64 for active rhs (x_zero: x64 = 0, r64 = b without the stencil); refreshes
@@ -1297,13 +1384,33 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
           // reliable update: x64 += e, r = b - M x64 in FP64, the low-precision residual restarts
           // from it and the search direction p is kept
           dl_op* op0 = bt.items[0].op;
-          if (bt.single() && !op0->lat.eo) {
+          bool whole = true;  // no even-odd operator in the batch
+          for (const auto& it : bt.items) whole = whole && !it.op->lat.eo;
+          if (bt.single() && whole) {
             // the FP64 stencil stores b - M x64 straight into r32 (rounded) with its ||.||^2
             hipLaunchKernelGGL((k_b_accum_clear<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.st.get(),
                                bt.active.get());
             TimeScope ts(bt.ctx, T_WILSON64, bt.wilson_bytes(576.0, 384.0 + kSpin * sizeof(SV)));
             npr = wilson_residual_f64(s, op0->lat, op0->U.get(), op0->kappa, X, B, nullptr, op0->lat.nc, nr,
                                       bt.active.get(), bt.part2.get(), r32, sizeof(SV) == 4 ? DL_BF16 : DL_FP32);
+          } else if (bt.ml_mode == 1 && whole) {
+            // the same per lattice of a multi-lattice batch, its partials re-strided to pw per rhs
+            hipLaunchKernelGGL((k_b_accum_clear<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.st.get(),
+                               bt.active.get());
+            TimeScope ts(bt.ctx, T_WILSON64, bt.wilson_bytes(576.0, 384.0 + kSpin * sizeof(SV)));
+            for (const auto& it : bt.items) {
+              dl_op* op = it.op;
+              const long off = bt.h_off[it.r0];
+              double* ip = bt.ml_part.get() + (size_t)it.r0 * bt.pw;
+              const int nb = wilson_residual_f64(s, op->lat, op->U.get(), op->kappa, X + off, B + off, nullptr,
+                                                 op->lat.nc, it.nr, bt.active.get() + it.r0, ip, r32 + off,
+                                                 sizeof(SV) == 4 ? DL_BF16 : DL_FP32);
+              if (nb > bt.pw) fail(DL_E_INVALID, "stencil partials exceed the batch's partial stride");
+              const long n = (long)it.nr * bt.pw;
+              hipLaunchKernelGGL(k_restride_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ip, nb,
+                                 it.nr, bt.part2.get() + (size_t)it.r0 * bt.pw, bt.pw);
+            }
+            npr = bt.pw;
           } else {
             hipLaunchKernelGGL((k_b_accum<SV>), dim3(G, nr), dim3(kBlock), 0, s, g, X, e, bt.active.get());
             true_residual(bt, B, X, R64.get(), T64.get());

@@ -80,6 +80,7 @@ int apply_wilson(dl_op* op, int which, const double2* in, double2* out, int red 
 // unless DEFLAN_AUTOTUNE=0), and the explicit tuner.
 WilsonCfg wilson_cfg(dl_op* op, int prec, int nrhs);
 WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us);
+bool autotune_enabled();  // false when DEFLAN_AUTOTUNE=0
 
 // hist (may be nullptr): residual history of the solve's right-hand sides.
 int solve_first(dl_op* op, const double2* b, double2* x, int m, int k, double tol, const dl_first_opts& o,

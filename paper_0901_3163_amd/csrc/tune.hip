@@ -45,11 +45,6 @@ std::string cache_path() {
   return std::string(h && *h ? h : "/tmp") + "/.cache/deflan/tune.txt";
 }
 
-bool autotune_enabled() {
-  const char* e = std::getenv("DEFLAN_AUTOTUNE");
-  return !(e && e[0] == '0');
-}
-
 std::string arch_name(int device) {
   static std::map<int, std::string> names;  // callers hold g_mu
   auto it = names.find(device);
@@ -136,6 +131,11 @@ double time_cfg(dl_op* op, const cplx_t<R>* U, const SV* in, SV* out, int nrhs, 
 }
 
 }  // namespace
+
+bool autotune_enabled() {
+  const char* e = std::getenv("DEFLAN_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
 
 WilsonCfg tune_wilson(dl_op* op, int prec, int nrhs, int reps, double* best_us) {
   op->wcfg.erase(prec * 100000 + nrhs);

@@ -1,4 +1,5 @@
-"""Several lattices in one batched solve (work-list stencil launch, per-rhs masks) on the GPU.
+"""Several lattices in one batched solve (per-rhs masks; the stencil as one work-list launch over
+all lattices or as one launch per lattice in its tuned shape) on the GPU.
 
 Each lattice's solutions are checked against the oracle: a dense solve where the
 lattice is small enough, the oracle's Wilson matrix for the true residual otherwise,
@@ -17,9 +18,14 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("kind", ["g5m", "mdagm"])
-def test_multi_lattice_batch(gpu_ctx, c1_config, kind):
+@pytest.mark.parametrize("kind,form,storage", [("g5m", "list", "fp32"), ("g5m", "lattice", "fp32"),
+                                               ("mdagm", "list", "fp32"), ("mdagm", "lattice", "fp32"),
+                                               ("mdagm", "lattice", "bf16")])
+def test_multi_lattice_batch(gpu_ctx, c1_config, kind, form, storage, monkeypatch):
+    """Both stencil forms carry the fused reductions of D-MinRes (Re<in, out> with the per-rhs
+    scale) and D-CG (||out||^2) through the batch's partial layout: every solution reaches tol."""
     from paper_0901_3163_amd import deflan
+    monkeypatch.setenv("DEFLAN_MULTI_STENCIL", form)
     k = deflan.DL_G5M if kind == "g5m" else deflan.DL_MDAGM
     c1 = c1_config
     lat = [
@@ -40,7 +46,8 @@ def test_multi_lattice_batch(gpu_ctx, c1_config, kind):
         eigs.append(eig)
         Bs.append(B)
         items.append((op, eig, B, L["tol"]))
-    Xs, sts, rc = deflan.solve_next_multi(gpu_ctx, items)
+    Xs, sts, rc = deflan.solve_next_multi(gpu_ctx, items,
+                                          storage=deflan.DL_BF16 if storage == "bf16" else deflan.DL_FP32)
     assert rc == deflan.DL_OK
     for j, L in enumerate(lat):
         ora = dirac.WilsonOperator(L["U"], L["dims"], L["kappa"])
