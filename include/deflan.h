@@ -357,11 +357,15 @@ typedef struct {
 
 /* Later right-hand sides of several operators (lattices of different sizes) solved
  * together by the batched mixed-precision path (D-CG or D-MinRes as in dl_solve_next,
- * Section 2): every stage is one launch over all lattices and rhs (a work list), with
- * per-rhs scalars and convergence masks.  opts NULL: DL_FP32 storage, batched; a non-NULL
- * opts must ask for DL_FP32 and batched = 1, and no network.  stats (may be NULL) gets
- * one entry per rhs in item order.  All pointers of all items are host (DL_HOST) or all
- * device (DL_DEVICE).  Returns DL_NOT_CONVERGED if any rhs missed its tol. */
+ * Section 2): every vector stage is one launch over all lattices and rhs, with per-rhs
+ * scalars and convergence masks.  The stencil stage is either one work-list launch over all
+ * lattices or one launch per lattice in its tuned shape; the library times both on the
+ * batch's first apply and keeps the faster (the environment variable DEFLAN_MULTI_STENCIL =
+ * "list" or "lattice" forces one).  opts NULL: DL_FP32 storage, batched; a non-NULL opts must
+ * ask for DL_FP32 or DL_BF16 storage and batched = 1, and no network; the operators are
+ * whole-lattice ones (no DL_EVEN_ODD).  stats (may be NULL) gets one entry per rhs in item
+ * order.  All pointers of all items are host (DL_HOST) or all device (DL_DEVICE).  Returns
+ * DL_NOT_CONVERGED if any rhs missed its tol. */
 int  dl_solve_next_multi(dl_ctx* ctx, int nitems, const dl_batch_item* items, int mem,
                          const dl_next_opts* opts, dl_stats* stats);
 
