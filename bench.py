@@ -729,6 +729,55 @@ def net_only(args):
     ctx.close()
 
 
+def drop_sweep(args):
+    """The residual drop that ends an inner cycle of batched BF16 D-CG, from the projection-only
+    start: the 4 held-out fields of the learned-guess workload (16^3x32, kappa tuned on field 10),
+    Lan-DR(m,k) on M^dag M for a Gaussian first rhs (kept-vector re-orthogonalisation,
+    eigenvectors lowered to FP32), then per field and drop one 64-rhs batched solve (BF16
+    storage, FP32-eigenvector projection, reliable updates every 8 iterations) after a warm-up,
+    the faster of two timed solves kept.  Prints one JSON line."""
+    import torch
+    from lattice_inputs import gaussian_spinor, gaussian_spinors_device, su3_links
+    from paper_0901_3163_amd import deflan
+    e = kappa_for("16x16x16x32/seed10")
+    dims, kappa, tol = tuple(e["dims"]), e["kappa"], args.tol
+    ctx = deflan.Context(0)
+    drops = (1e-3, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6)
+    res = {f"{d:g}": dict(ms_per_field=[], iters_per_rhs=[], all_rhs_converged=True) for d in drops}
+    for seed in (20, 21, 22, 23):
+        U = torch.from_numpy(su3_links(dims, seed, e["eps"])).cuda()
+        op = deflan.Operator(ctx, dims, U, kappa, deflan.DL_MDAGM)
+        del U
+        b1 = torch.from_numpy(gaussian_spinor(dims, 1000 + seed)).cuda()
+        _, eig, _ = op.solve_first(b1, args.m, args.k, tol, reorth=deflan.DL_REORTH_KEPT)
+        eig.lower(deflan.DL_FP32)
+        B = gaussian_spinors_device(dims, 60000 + seed, args.test_rhs)
+        kw = dict(storage=deflan.DL_BF16, batched=1, eig_storage=deflan.DL_FP32, reliable_every=8)
+        op.solve_next(B, eig, tol, **kw)  # warm-up (tuning)
+        for d in drops:
+            ts = []
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.time()
+                _, sts, rc = op.solve_next(B, eig, tol, inner_drop=d, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.time() - t0)
+            r = res[f"{d:g}"]
+            r["ms_per_field"].append(round(1e3 * min(ts), 1))
+            r["iters_per_rhs"].append(float(np.mean([s["iters"] for s in sts])))
+            r["all_rhs_converged"] &= bool(rc == deflan.DL_OK and all(s["relres"] <= tol for s in sts))
+            log(f"drop sweep: field {seed} drop {d:g}: {1e3 * min(ts):.1f} ms, "
+                f"{np.mean([s['iters'] for s in sts]):.1f} iterations per rhs")
+        eig.close()
+        op.close()
+    for r in res.values():
+        r["rhs_per_s"] = round(4 * args.test_rhs / (sum(r["ms_per_field"]) / 1e3), 2)
+    print(json.dumps(dict(workload=(f"16^3x32 Wilson (kappa {kappa:.6f}), held-out fields 20-23, Lan-DR({args.m},"
+                                    f"{args.k}) on M^dag M, batched BF16 D-CG from the projection-only start for "
+                                    f"{args.test_rhs} Gaussian rhs per field, tol {tol:g}"),
+                          drops=res)))
+
+
 def evenodd_study(args):
     """The even-odd (Schur complement) form against the whole-lattice system on held-out field 20
     of the learned-guess workload (16^3x32, kappa tuned on field 10): Lan-DR(m,k) for a Gaussian
@@ -908,6 +957,8 @@ def main():
                     help="the autotuner's choices at the paths' sizes (own JSON line)")
     ap.add_argument("--evenodd", action="store_true",
                     help="the even-odd (Schur) form against the whole lattice on a held-out field instead")
+    ap.add_argument("--drop-sweep", action="store_true",
+                    help="the inner-cycle residual drop of batched BF16 D-CG on the held-out fields (own JSON line)")
     ap.add_argument("--learned-pairs", type=int, default=256)
     ap.add_argument("--learned-test", type=int, default=64)
     ap.add_argument("--learned-epochs", type=int, default=2)
@@ -936,6 +987,8 @@ def main():
         return window_sweep(args)
     if args.evenodd:
         return evenodd_study(args)
+    if args.drop_sweep:
+        return drop_sweep(args)
     if args.tune_report:
         return tune_report(args)
     os.environ.setdefault("DEFLAN_VERBOSE", "1")  # per-cycle progress lines from the library
