@@ -608,7 +608,7 @@ struct Batch {
   // multi-lattice stencil work lists (FP32 and FP64 links)
   DBuf<WilsonItem> wl32, wl64;
   int ml_blocks = 0, ml_pstride = 0;
-  // multi-lattice stencil form, chosen by timing at the first low-precision apply: -1 undecided,
+  // multi-lattice stencil form, chosen by timing at the batch's setup (ml_choose): -1 not yet,
   // 0 one work-list launch over all lattices, 1 one launch per lattice in its tuned shape (fused
   // reductions re-strided from ml_part to pw partials per rhs)
   int ml_mode = -1;
@@ -782,29 +782,40 @@ static int bwilson_multi(Batch& bt, int mode, int which, const SV* in, SV* out, 
   return red ? bt.pw : 0;
 }
 
-// Chooses the multi-lattice stencil form by timing both on this batch (3 applies each after a
-// warm-up; the per-lattice shapes are tuned first).  Inside a graph capture, or with autotuning
-// off, the work list is taken; DEFLAN_MULTI_STENCIL=list or =lattice forces a form.  Kept for
-// the batch's lifetime, so that the partial stride a solve reads stays the same.
+// Chooses the multi-lattice stencil form at the batch's setup, outside any graph capture: the
+// per-lattice shapes (storage precision and FP64) are settled first, so that no captured
+// block tunes, then both forms of the M apply are timed on zeroed temporary fields (3 applies
+// each after a warm-up) and the faster is kept for the batch's lifetime (so the partial
+// stride a solve reads stays the same).  DEFLAN_MULTI_STENCIL=list or =lattice forces a form;
+// with autotuning off the work list is taken.
 template <class SV>
-static int ml_choose(Batch& bt, int which, const SV* in, SV* out) {
+static int ml_choose(Batch& bt) {
   constexpr int prec = sizeof(SV) == sizeof(float2) ? DL_FP32 : DL_BF16;
-  if (const char* e = std::getenv("DEFLAN_MULTI_STENCIL")) {
-    if (std::strcmp(e, "list") == 0) return 0;
-    if (std::strcmp(e, "lattice") == 0) return 1;
+  const char* e = std::getenv("DEFLAN_MULTI_STENCIL");
+  if (e && std::strcmp(e, "list") == 0) return 0;
+  for (const auto& it : bt.items) {
+    (void)wilson_cfg(it.op, prec, it.nr);
+    (void)wilson_cfg(it.op, DL_FP64, it.nr);
   }
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  DL_HIP(hipStreamIsCapturing(bt.s, &cs));
-  if (cs != hipStreamCaptureStatusNone || !autotune_enabled()) return 0;
-  for (const auto& it : bt.items) (void)wilson_cfg(it.op, prec, it.nr);
+  if (e && std::strcmp(e, "lattice") == 0) return 1;
+  if (!autotune_enabled()) return 0;
+  // two fields of bt.total SV elements, allocated as double2 (16 B) and zeroed
+  const long nd = (long)((bt.total * (long)sizeof(SV) + 15) / 16);
+  DBuf<double2> tin, tout;
+  tin.alloc((size_t)nd);
+  tout.alloc((size_t)nd);
+  zero(bt.s, nd, tin.get());
+  const SV* in = reinterpret_cast<const SV*>(tin.get());
+  SV* out = reinterpret_cast<SV*>(tout.get());
+  bt.push_active();
   hipEvent_t a, b;
   DL_HIP(hipEventCreate(&a));
   DL_HIP(hipEventCreate(&b));
   float ms[2] = {0.f, 0.f};
   for (int m = 0; m < 2; ++m) {
-    bwilson_multi<float, SV>(bt, m, which, in, out, 0, nullptr, nullptr);
+    bwilson_multi<float, SV>(bt, m, 0, in, out, 0, nullptr, nullptr);
     DL_HIP(hipEventRecord(a, bt.s));
-    for (int rep = 0; rep < 3; ++rep) bwilson_multi<float, SV>(bt, m, which, in, out, 0, nullptr, nullptr);
+    for (int rep = 0; rep < 3; ++rep) bwilson_multi<float, SV>(bt, m, 0, in, out, 0, nullptr, nullptr);
     DL_HIP(hipEventRecord(b, bt.s));
     DL_HIP(hipEventSynchronize(b));
     DL_HIP(hipEventElapsedTime(&ms[m], a, b));
@@ -827,7 +838,6 @@ template <class SV>
 static int bwilson_lo(Batch& bt, int which, const SV* in, SV* out, int red, double* part,
                       const double* scale = nullptr) {
   constexpr int prec = sizeof(SV) == sizeof(float2) ? DL_FP32 : DL_BF16;
-  if (!bt.single() && bt.ml_mode < 0) bt.ml_mode = ml_choose<SV>(bt, which, in, out);
   TimeScope ts(bt.ctx, T_WILSON, bt.wilson_bytes(288.0, 2.0 * kSpin * sizeof(SV)));
   if (bt.single()) {
     dl_op* op = bt.items[0].op;
@@ -835,7 +845,7 @@ static int bwilson_lo(Batch& bt, int which, const SV* in, SV* out, int red, doub
     return wilson_batched<float>(bt.s, op->lat, op_links32_public(op), op->kappa, which, in, out, op->lat.nc, bt.nr,
                                  red, scale, bt.active.get(), part, cfg);
   }
-  return bwilson_multi<float, SV>(bt, bt.ml_mode, which, in, out, red, part, scale);
+  return bwilson_multi<float, SV>(bt, bt.ml_mode == 1 ? 1 : 0, which, in, out, red, part, scale);
 }
 
 static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
@@ -847,7 +857,7 @@ static void bwilson64(Batch& bt, int which, const double2* in, double2* out) {
                            bt.active.get(), nullptr, cfg);
     return;
   }
-  // the FP64 applies follow the form chosen for the low-precision ones (work list until then)
+  // the FP64 applies follow the form chosen at the batch's setup
   bwilson_multi<double, double2>(bt, bt.ml_mode == 1 ? 1 : 0, which, in, out, 0, nullptr, nullptr);
 }
 
@@ -1058,6 +1068,8 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
   if (bt.single()) {
     (void)wilson_cfg(items[0].op, o.storage == DL_BF16 ? DL_BF16 : DL_FP32, nr);
     (void)wilson_cfg(items[0].op, DL_FP64, nr);
+  } else {
+    bt.ml_mode = o.storage == DL_BF16 ? ml_choose<bf2>(bt) : ml_choose<float2>(bt);
   }
   const bool mr = items[0].op->kind == DL_G5M;
   int kmax = 1;
@@ -1495,6 +1507,8 @@ static int solve_batch(const std::vector<BItem>& items, const double2* B, double
       }
       ring16.release();
       if (bt.single()) (void)wilson_cfg(items[0].op, DL_FP32, nr);
+      if (!bt.single() && bt.ml_mode == 1)
+        for (const auto& it : items) (void)wilson_cfg(it.op, DL_FP32, it.nr);
       graphs.clear();  // captured blocks name the BF16 buffers
       bf16 = false;
       // defaulted settings give way to the FP32 defaults; values the caller set are kept

@@ -18,14 +18,20 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("kind,form,storage", [("g5m", "list", "fp32"), ("g5m", "lattice", "fp32"),
-                                               ("mdagm", "list", "fp32"), ("mdagm", "lattice", "fp32"),
-                                               ("mdagm", "lattice", "bf16")])
-def test_multi_lattice_batch(gpu_ctx, c1_config, kind, form, storage, monkeypatch):
-    """Both stencil forms carry the fused reductions of D-MinRes (Re<in, out> with the per-rhs
-    scale) and D-CG (||out||^2) through the batch's partial layout: every solution reaches tol."""
+@pytest.mark.parametrize("kind,form,storage,graph", [
+    ("g5m", "list", "fp32", False), ("g5m", "lattice", "fp32", False), ("mdagm", "list", "fp32", False),
+    ("mdagm", "lattice", "fp32", False), ("mdagm", "lattice", "bf16", False),
+    ("g5m", "lattice", "fp32", True), ("g5m", "auto", "fp32", True), ("mdagm", "auto", "bf16", True)])
+def test_multi_lattice_batch(gpu_ctx, c1_config, kind, form, storage, graph, monkeypatch):
+    """Both stencil forms (forced, or the library's timed choice) carry the fused reductions of
+    D-MinRes (Re<in, out> with the per-rhs scale) and D-CG (||out||^2) through the batch's
+    partial layout, also when the inner blocks are replayed as graphs (the form and the
+    per-lattice shapes are settled before any capture): every solution reaches tol."""
     from paper_0901_3163_amd import deflan
-    monkeypatch.setenv("DEFLAN_MULTI_STENCIL", form)
+    if form == "auto":
+        monkeypatch.delenv("DEFLAN_MULTI_STENCIL", raising=False)
+    else:
+        monkeypatch.setenv("DEFLAN_MULTI_STENCIL", form)
     k = deflan.DL_G5M if kind == "g5m" else deflan.DL_MDAGM
     c1 = c1_config
     lat = [
@@ -46,7 +52,7 @@ def test_multi_lattice_batch(gpu_ctx, c1_config, kind, form, storage, monkeypatc
         eigs.append(eig)
         Bs.append(B)
         items.append((op, eig, B, L["tol"]))
-    Xs, sts, rc = deflan.solve_next_multi(gpu_ctx, items,
+    Xs, sts, rc = deflan.solve_next_multi(gpu_ctx, items, graph=graph,
                                           storage=deflan.DL_BF16 if storage == "bf16" else deflan.DL_FP32)
     assert rc == deflan.DL_OK
     for j, L in enumerate(lat):
