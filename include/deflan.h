@@ -359,8 +359,8 @@ typedef struct {
  * together by the batched mixed-precision path (D-CG or D-MinRes as in dl_solve_next,
  * Section 2): every vector stage is one launch over all lattices and rhs, with per-rhs
  * scalars and convergence masks.  The stencil stage is either one work-list launch over all
- * lattices or one launch per lattice in its tuned shape; the library times both on the
- * batch's first apply and keeps the faster (the environment variable DEFLAN_MULTI_STENCIL =
+ * lattices or one launch per lattice in its tuned shape; the library times both when it sets
+ * the batch up and keeps the faster (the environment variable DEFLAN_MULTI_STENCIL =
  * "list" or "lattice" forces one).  opts NULL: DL_FP32 storage, batched; a non-NULL opts must
  * ask for DL_FP32 or DL_BF16 storage and batched = 1, and no network; the operators are
  * whole-lattice ones (no DL_EVEN_ODD).  stats (may be NULL) gets one entry per rhs in item
